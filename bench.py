@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the Manifold k-NN query path on one MI355X.
+
+A step is one pass of the whole query path over one batch: the query batch preparation
+(Morton bucketing), the 1-NN descent (Alg. 1) and the k-expansion (Alg. 2) with the prefix
+bound, writing indices and distances -- for the headline workload: 1,000,000 points on a
+torus (R=1, r=0.3, normal noise 1e-3, random insertion order), 1,000,000 volume queries
+uniform in the bounding box expanded by 10%, k=16, m=n.  Inputs are resident in HBM
+before timing starts; the host-side list construction is reported but not timed.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(P, Q, k, target_s: float):
+    """Time the FP64 brute-force oracle on a bounded sample of the same queries."""
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.max_threads()
+    oracle.knn_bruteforce(P, Q[:16], k)           # load the library, start the threads
+    n0 = min(64, Q.shape[0])
+    while True:
+        t = time.perf_counter()
+        oracle.knn_bruteforce(P, Q[:n0], k)
+        dt = max(time.perf_counter() - t, 1e-6)
+        if dt >= 0.5 or n0 >= Q.shape[0]:
+            break
+        n0 = min(Q.shape[0], n0 * 4)
+    ns = int(min(Q.shape[0], max(n0, n0 * target_s / dt)))
+    t = time.perf_counter()
+    oracle.knn_bruteforce(P, Q[:ns], k)
+    dt = time.perf_counter() - t
+    return {"value": ns / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {ns} of the {Q.shape[0]} timed queries, brute force over all "
+                      f"{P.shape[0]} points, FP64, {dt:.1f} s wall"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--nq", type=int, default=1_000_000)
+    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 2
+    from paper_2605_02224_amd import workloads as W
+    from paper_2605_02224_amd import _lib
+    from paper_2605_02224_amd.api import Cloud
+
+    t0 = time.perf_counter()
+    w = W.torus_paper_scale(n=args.n, nq=args.nq, k=args.k)
+    P = w.cloud.by_rank
+    log(f"workload generated in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    cl = Cloud.build(P)
+    build_s = time.perf_counter() - t0
+    log(f"lists built in {build_s:.1f} s")
+    cl.upload()
+    q = torch.from_numpy(w.queries).cuda()
+    qb = torch.from_numpy(w.queries_b).cuda()
+    nq = q.shape[0]
+    k = args.k
+    idx = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+    dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+
+    # algorithmic bytes per query: 16 B per list entry examined, 8 B per list opened,
+    # 12 B query, 8 B per output neighbour (rank + distance)
+    ce, cn = cl.knn_counts(q, k)
+    torch.cuda.synchronize()
+    E = ce.double().mean().item()
+    L = cn.double().mean().item()
+    bytes_per_q = 16.0 * E + 8.0 * L + 12.0 + 8.0 * k
+    log(f"per query: {E:.1f} entries, {L:.2f} lists -> {bytes_per_q:.0f} algorithmic bytes")
+
+    for _ in range(args.warmup):
+        cl.knn(q, k, out=(idx, dist))
+    torch.cuda.synchronize()
+    lib = _lib.lib()
+    lib.mknn_timing_enable(1)
+    import ctypes
+    tot = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    lib.mknn_timing_read(ctypes.byref(tot), ctypes.byref(cnt))   # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cl.knn(q, k, out=(idx, dist))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _lib.check(lib.mknn_timing_read(ctypes.byref(tot), ctypes.byref(cnt)))
+    lib.mknn_timing_enable(0)
+    ms_step = 1e3 * wall / args.steps
+    qps = nq * args.steps / wall
+    kern_ms = tot.value / max(cnt.value, 1)
+    achieved = bytes_per_q * nq / (kern_ms * 1e-3) / 1e9
+    log(f"{qps / 1e6:.1f} M queries/s, {ms_step:.3f} ms/step, query kernel {kern_ms:.3f} ms")
+
+    # context numbers (not the headline): k=1 and the on-surface query set
+    extras = {"build_s": round(build_s, 2), "device_bytes": cl.device_bytes,
+              "entries_per_query": round(E, 2), "lists_per_query": round(L, 3),
+              "kernel_ms": round(kern_ms, 4)}
+    for name, qq, kk in (("volume_k1", q, 1), ("surface_k16", qb, 16), ("surface_k1", qb, 1)):
+        i2 = torch.empty((nq, kk), dtype=torch.int32, device="cuda")
+        d2 = torch.empty((nq, kk), dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            cl.knn(qq, kk, out=(i2, d2))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(3, args.steps // 4)
+        for _ in range(reps):
+            cl.knn(qq, kk, out=(i2, d2))
+        torch.cuda.synchronize()
+        extras[name + "_qps"] = round(nq * reps / (time.perf_counter() - t0), 1)
+    log(f"extras: {extras}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(P, w.queries, k, args.cpu_seconds)
+        log(f"cpu baseline: {cpu}")
+
+    line = {
+        "metric": "k-NN queries/sec (k=16, 1M-pt surface) + p50/p99 latency, batched vs plain",
+        "value": round(qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "torus_1M_volume_queries_k16", "n": args.n, "nq": nq, "k": k,
+                   "m": args.n, "form": "plain (one launch per batch)",
+                   "queries": "uniform in bbox x1.1", "order": "seeded random"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "cpu_baseline": cpu,
+        "extra": extras,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

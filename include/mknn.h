@@ -1,0 +1,160 @@
+/*
+ * mknn.h -- C ABI of the MI355X (gfx950) Manifold k-NN query engine.
+ *
+ * Method (Manifold k-NN, Sec. 3-4): points P = p_0..p_{n-1} are ordered by insertion
+ * ("birth rank", 0-based: rank r is the paper's p_{r+1}).  For every rank i the successor
+ * list L_i holds, ascending, the ranks j > i whose insertion pruned the Voronoi cell of p_i
+ * (Sec. 3).  A k-NN query descends the lists from the oldest site to the nearest neighbour
+ * (Alg. 1, collecting the "transition sites" it visits), then expands the lists of the
+ * confirmed neighbours (Alg. 2, justified by Theorem 1).  Ignoring ranks >= m answers the
+ * query within the prefix P_{1:m} (Sec. 4.2).  Deleting a site updates the lists locally
+ * (Alg. 3, Sec. 4.3) so that they equal the lists of P minus that site inserted in the
+ * original relative order.
+ *
+ * Results are exact with respect to squared Euclidean distances evaluated in float64 from
+ * the float32 inputs as D = ((qx-px)^2 + (qy-py)^2) + (qz-pz)^2 (each operation rounded,
+ * no fused multiply-add).  Neighbours are ordered by the key (D, rank): an exact tie goes to
+ * the older site.  Returned distances are (float)sqrt(D).
+ *
+ * Conventions for every call:
+ *   - the return value is an mknn_status; no C++ exception crosses this boundary;
+ *     mknn_last_error() returns a thread-local message describing the last failure;
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP device memory of
+ *     the current device; the caller owns every buffer it passes in;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default stream); device
+ *     work is enqueued on it and the call returns without synchronising unless stated.
+ */
+#ifndef MKNN_H_
+#define MKNN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mknn_cloud mknn_cloud; /* opaque, owned by the library */
+
+typedef enum {
+  MKNN_OK = 0,
+  MKNN_EINVAL = -1,       /* bad argument (NULL pointer, size or range) */
+  MKNN_ENOMEM = -2,       /* host or device allocation failed */
+  MKNN_EDUPLICATE = -3,   /* two input points are bit-identical */
+  MKNN_ENONFINITE = -4,   /* NaN or infinite coordinate */
+  MKNN_EHIP = -5,         /* a HIP runtime call failed (message names the hipError_t) */
+  MKNN_ENOTFOUND = -6,    /* deletion of an unknown or already deleted rank */
+  MKNN_EBUSY = -7,        /* resource pool full; retry later */
+  MKNN_EUNSUPPORTED = -8  /* valid request outside what this build handles */
+} mknn_status;
+
+/* Largest k a query may ask for. */
+#define MKNN_KMAX 64
+
+/* ---------------------------------------------------------------------------------------
+ * Construction (host side).
+ *
+ * mknn_build: builds the successor lists of Sec. 3 by incremental Delaunay triangulation
+ * (exact predicates, vertex at infinity), inserting the points in birth order.
+ *   xyz    host float32 [n][3], row-major, in the caller's own order; copied.
+ *   order  host int32 [n] permutation: rank r is the caller's point order[r];
+ *          NULL means the identity (rank r = row r).
+ *   out    receives a new cloud handle; release it with mknn_free().
+ * Errors: EINVAL (n < 1, NULL xyz/out, order not a permutation), ENONFINITE, EDUPLICATE,
+ * EUNSUPPORTED (the first four ranks are coplanar, so the prefix diagram starts
+ * degenerate), ENOMEM.
+ */
+mknn_status mknn_build(const float *xyz, int64_t n, const int32_t *order, mknn_cloud **out);
+
+/* Number of points n of the cloud (including deleted ranks). */
+int64_t mknn_size(const mknn_cloud *c);
+
+/* Host view of the successor lists as CSR (Sec. 3, "successor table"): list i is
+ * ranks[offsets[i] .. offsets[i+1]), ascending.  The pointers stay valid until the next
+ * mutation of the cloud (mknn_delete) or mknn_free.  Deleted ranks have empty lists and
+ * appear in no list. */
+mknn_status mknn_successors(const mknn_cloud *c, const int64_t **offsets,
+                            const int32_t **ranks, int64_t *nnz);
+
+/* Host copy of the points by rank: float32 [n][3] (valid like mknn_successors). */
+mknn_status mknn_points_by_rank(const mknn_cloud *c, const float **xyz);
+
+/* ---------------------------------------------------------------------------------------
+ * Device residency.
+ *
+ * mknn_upload: packs the lists for the device and copies them to the current device
+ * (synchronously).  Layout: one 16-byte record {x, y, z, rank} per list entry, lists
+ * stored contiguously in the Morton order of their owner points, and one 64-bit
+ * {start, length} descriptor per rank.  Idempotent; re-uploads after a deletion.
+ * Errors: EHIP, ENOMEM.
+ */
+mknn_status mknn_upload(mknn_cloud *c, void *stream);
+
+/* Bytes of device memory the uploaded cloud occupies. */
+int64_t mknn_device_bytes(const mknn_cloud *c);
+
+/* ---------------------------------------------------------------------------------------
+ * Queries (device side; Alg. 1 + Alg. 2 with the prefix bound of Sec. 4.2).
+ *
+ * mknn_knn: k nearest ranks r < m (live ranks only) of every query.
+ *   d_q     device float32 [nq][3]
+ *   k       1 <= k <= MKNN_KMAX;  m  1 <= m <= n (prefix size)
+ *   d_idx   device int32 [nq][k]  ranks, ascending by key; -1 where fewer than k exist
+ *   d_dist  device float32 [nq][k] (float)sqrt(D); +inf in padded slots
+ * nq = 0 is a no-op.  The cloud must be uploaded.  Scratch for the query sort is taken from
+ * the stream-ordered allocator and released on the stream.
+ * Errors: EINVAL (k or m out of range, NULL pointers, not uploaded), EUNSUPPORTED
+ * (k > MKNN_KMAX), EHIP.
+ */
+mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k, int32_t m,
+                     int32_t *d_idx, float *d_dist, void *stream);
+
+/* mknn_knn_var: per-query k and prefix m with ragged output rows.
+ *   d_k        device int32 [nq], each in [1, MKNN_KMAX]
+ *   d_m        device int32 [nq], each in [1, n] (values above n are clamped to n)
+ *   d_row_off  device int64 [nq+1]; row q occupies [d_row_off[q], d_row_off[q+1]) of
+ *              d_idx / d_dist, and d_row_off[q+1] - d_row_off[q] must equal d_k[q]
+ *   kmax       host int32, an upper bound of all d_k (selects the kernel variant)
+ * Errors as mknn_knn.  Out-of-range per-query values are not checked on the device: a
+ * query with k or m outside its range returns its row untouched.
+ */
+mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, const int32_t *d_k,
+                         const int32_t *d_m, const int64_t *d_row_off, int32_t kmax,
+                         int32_t *d_idx, float *d_dist, void *stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Work counters (diagnostics for the memory roofline).
+ *
+ * mknn_knn_counts: runs the same query path as mknn_knn and writes, per query, the number of
+ * list entries examined E and of lists opened L (int32 [nq] each, device).  The final list
+ * of the descent, which Alg. 2's first iteration would scan again, is counted once.
+ */
+mknn_status mknn_knn_counts(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
+                            int32_t m, int32_t *d_entries, int32_t *d_lists, void *stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Kernel timing (diagnostics for the memory roofline).
+ *
+ * mknn_timing_enable(1): from now on every query call records a pair of HIP events on its
+ * stream immediately before and after its main query kernel (the query sort is outside the
+ * pair).  mknn_timing_read() waits for all recorded pairs, returns the summed kernel time in
+ * milliseconds and the number of launches, and forgets them.  Not thread-safe: meant for
+ * single-threaded benchmarking.  Errors: EHIP.
+ */
+mknn_status mknn_timing_enable(int enable);
+mknn_status mknn_timing_read(double *total_ms, int64_t *launches);
+
+/* Release a cloud and all its host and device memory (device frees synchronise). */
+void mknn_free(mknn_cloud *c);
+
+/* Thread-local description of the last error ("" if none). */
+const char *mknn_last_error(void);
+
+/* Library version string. */
+const char *mknn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MKNN_H_ */

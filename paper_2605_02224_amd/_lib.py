@@ -1,0 +1,67 @@
+"""ctypes binding of libmknn.so (argument marshalling only; every step runs in the library)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmknn.so")
+
+# status codes of mknn.h
+OK, EINVAL, ENOMEM, EDUPLICATE, ENONFINITE, EHIP, ENOTFOUND, EBUSY, EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDUPLICATE", -4: "ENONFINITE",
+                -5: "EHIP", -6: "ENOTFOUND", -7: "EBUSY", -8: "EUNSUPPORTED"}
+KMAX = 64
+
+# every symbol the public header declares, with (restype, argtypes)
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_PP = ctypes.POINTER(ctypes.c_void_p)
+SIGNATURES = {
+    "mknn_build": (ctypes.c_int, [_P, _I64, _P, _PP]),
+    "mknn_size": (_I64, [_P]),
+    "mknn_successors": (ctypes.c_int, [_P, _PP, _PP, ctypes.POINTER(_I64)]),
+    "mknn_points_by_rank": (ctypes.c_int, [_P, _PP]),
+    "mknn_upload": (ctypes.c_int, [_P, _P]),
+    "mknn_device_bytes": (_I64, [_P]),
+    "mknn_knn": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P]),
+    "mknn_knn_var": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P]),
+    "mknn_knn_counts": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P]),
+    "mknn_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "mknn_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+    "mknn_free": (None, [_P]),
+    "mknn_last_error": (ctypes.c_char_p, []),
+    "mknn_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class MknnError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def lib():
+    """Load libmknn.so; raises if the library has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2605_02224_amd.build`")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != OK:
+        msg = lib().mknn_last_error().decode(errors="replace")
+        raise MknnError(status, msg)

@@ -1,0 +1,139 @@
+"""Python front end over the C ABI.  Torch provides device memory and streams only."""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import check
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return ctypes.c_void_p(t.ctypes.data)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Cloud:
+    """A point cloud with its successor lists (built on the host, resident on the GPU)."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+
+    @classmethod
+    def build(cls, points: np.ndarray, order: Optional[np.ndarray] = None) -> "Cloud":
+        """points: float32 [n,3] in caller order; order[r] = caller index of rank r."""
+        pts = np.ascontiguousarray(points, dtype=np.float32).reshape(-1, 3)
+        o = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
+        if o is not None and o.shape[0] != pts.shape[0]:
+            raise ValueError("order must have one entry per point")
+        h = ctypes.c_void_p()
+        check(_lib.lib().mknn_build(_ptr(pts), pts.shape[0], _ptr(o), ctypes.byref(h)))
+        return cls(h)
+
+    def __del__(self):
+        self.close()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().mknn_free(self._h)
+            self._h = None
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    @property
+    def n(self) -> int:
+        return int(_lib.lib().mknn_size(self._h))
+
+    def successors(self) -> Tuple[np.ndarray, np.ndarray]:
+        """(offsets int64 [n+1], ranks int32 [nnz]) -- copies of the host CSR lists."""
+        off = ctypes.c_void_p()
+        ent = ctypes.c_void_p()
+        nnz = ctypes.c_int64()
+        check(_lib.lib().mknn_successors(self._h, ctypes.byref(off), ctypes.byref(ent),
+                                         ctypes.byref(nnz)))
+        n = self.n
+        offs = np.ctypeslib.as_array(ctypes.cast(off, ctypes.POINTER(ctypes.c_int64)), (n + 1,)).copy()
+        if nnz.value:
+            ranks = np.ctypeslib.as_array(ctypes.cast(ent, ctypes.POINTER(ctypes.c_int32)),
+                                          (nnz.value,)).copy()
+        else:
+            ranks = np.zeros(0, np.int32)
+        return offs, ranks
+
+    def lists(self):
+        """Successor lists as a list of Python lists (small clouds)."""
+        off, ent = self.successors()
+        return [ent[off[i]:off[i + 1]].tolist() for i in range(self.n)]
+
+    def points_by_rank(self) -> np.ndarray:
+        p = ctypes.c_void_p()
+        check(_lib.lib().mknn_points_by_rank(self._h, ctypes.byref(p)))
+        return np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_float)),
+                                     (self.n, 3)).copy()
+
+    # ---- device side
+    def upload(self, stream=None) -> "Cloud":
+        check(_lib.lib().mknn_upload(self._h, _stream(stream)))
+        return self
+
+    @property
+    def device_bytes(self) -> int:
+        return int(_lib.lib().mknn_device_bytes(self._h))
+
+    def knn(self, q, k: int, m: Optional[int] = None, out=None, stream=None):
+        """q: float32 [nq,3] CUDA tensor -> (idx int32 [nq,k], dist float32 [nq,k])."""
+        import torch
+        q = q.contiguous()
+        nq = q.shape[0]
+        m = self.n if m is None else int(m)
+        if out is None:
+            idx = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+            dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        else:
+            idx, dist = out
+        check(_lib.lib().mknn_knn(self._h, _ptr(q), nq, int(k), m, _ptr(idx), _ptr(dist),
+                                  _stream(stream)))
+        return idx, dist
+
+    def knn_var(self, q, k_per_query, m_per_query, stream=None):
+        """Per-query k and m; returns (idx, dist, row_off) with ragged rows (flat tensors)."""
+        import torch
+        q = q.contiguous()
+        nq = q.shape[0]
+        kq = k_per_query.to(torch.int32).contiguous()
+        mq = m_per_query.to(torch.int32).contiguous()
+        row_off = torch.zeros(nq + 1, dtype=torch.int64, device=q.device)
+        if nq:
+            torch.cumsum(kq.to(torch.int64), 0, out=row_off[1:])
+        tot = int(row_off[-1].item()) if nq else 0
+        kmax = int(kq.max().item()) if nq else 1
+        idx = torch.empty(tot, dtype=torch.int32, device=q.device)
+        dist = torch.empty(tot, dtype=torch.float32, device=q.device)
+        check(_lib.lib().mknn_knn_var(self._h, _ptr(q), nq, _ptr(kq), _ptr(mq), _ptr(row_off),
+                                      kmax, _ptr(idx), _ptr(dist), _stream(stream)))
+        return idx, dist, row_off
+
+    def knn_counts(self, q, k: int, m: Optional[int] = None, stream=None):
+        """Per-query work: (entries examined E, lists opened L) as int32 tensors."""
+        import torch
+        q = q.contiguous()
+        nq = q.shape[0]
+        m = self.n if m is None else int(m)
+        ce = torch.empty(nq, dtype=torch.int32, device=q.device)
+        cl = torch.empty(nq, dtype=torch.int32, device=q.device)
+        check(_lib.lib().mknn_knn_counts(self._h, _ptr(q), nq, int(k), m, _ptr(ce), _ptr(cl),
+                                         _stream(stream)))
+        return ce, cl

@@ -1,0 +1,425 @@
+// Incremental 3-D Delaunay triangulation recording successor lists (see delaunay.h).
+#include "delaunay.h"
+
+#include <algorithm>
+#include <cstring>
+
+#include "exact.h"
+
+namespace mknn {
+
+namespace {
+inline double sqd(const double *a, const double *b) {
+  double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+  return (dx * dx + dy * dy) + dz * dz;
+}
+inline uint64_t edge_key(int32_t a, int32_t b) {
+  uint32_t x = (uint32_t)(a + 1), y = (uint32_t)(b + 1);
+  if (x > y) std::swap(x, y);
+  return ((uint64_t)x << 32) | y;
+}
+}  // namespace
+
+DelaunayBuilder::DelaunayBuilder(const double *pts, int64_t n) : P_(pts), n_(n) {
+  vtet_.assign(n, -1);
+  lstart_.assign(n, 0);
+  llen_.assign(n, 0);
+  lcap_.assign(n, 0);
+  vmark_.assign(n, 0);
+  tv_.reserve((size_t)std::max<int64_t>(64, 7 * n) * 4);
+  tn_.reserve((size_t)std::max<int64_t>(64, 7 * n) * 4);
+  stamp_.reserve((size_t)std::max<int64_t>(64, 7 * n));
+  pool_.reserve((size_t)std::max<int64_t>(64, 20 * n));
+}
+
+int64_t DelaunayBuilder::num_tets() const {
+  return (int64_t)stamp_.size() - (int64_t)free_.size();
+}
+
+int32_t DelaunayBuilder::alloc_tet() {
+  if (!free_.empty()) {
+    int32_t t = free_.back();
+    free_.pop_back();
+    return t;
+  }
+  int32_t t = (int32_t)stamp_.size();
+  tv_.resize(tv_.size() + 4);
+  tn_.resize(tn_.size() + 4);
+  stamp_.push_back(0);
+  return t;
+}
+
+void DelaunayBuilder::append(int32_t owner, int32_t rank) {
+  if (llen_[owner] == lcap_[owner]) {
+    int32_t cap = lcap_[owner] ? 2 * lcap_[owner] : 8;
+    int64_t ns = (int64_t)pool_.size();
+    pool_.resize(pool_.size() + cap);
+    if (llen_[owner])
+      std::memcpy(&pool_[ns], &pool_[lstart_[owner]], sizeof(int32_t) * llen_[owner]);
+    lstart_[owner] = ns;
+    lcap_[owner] = cap;
+  }
+  pool_[lstart_[owner] + llen_[owner]++] = rank;
+}
+
+// A tetrahedron conflicts with the new (newest) site p when p lies inside or on its
+// circumsphere; a ghost tetrahedron (hull facet F plus the vertex at infinity) conflicts
+// when p lies strictly beyond F, or in F's plane inside or on F's circumcircle.
+bool DelaunayBuilder::conflict(int32_t t, const double *p) const {
+  const int32_t *v = &tv_[4 * (int64_t)t];
+  int inf = -1;
+  for (int i = 0; i < 4; ++i)
+    if (v[i] == kInf) inf = i;
+  if (inf < 0) return insphere(pt(v[0]), pt(v[1]), pt(v[2]), pt(v[3]), p) >= 0;
+  const double *q[4];
+  for (int i = 0; i < 4; ++i) q[i] = (i == inf) ? p : pt(v[i]);
+  int o = orient3d(q[0], q[1], q[2], q[3]);
+  if (o != 0) return o > 0;
+  // p is in the facet's plane: test against the circumcircle through an auxiliary point f
+  // beyond the facet (any such f gives a sphere meeting the plane in that circle).
+  const double *a = pt(v[(inf + 1) & 3]);
+  for (int k = 0; k < 3; ++k) {
+    for (int s = 0; s < 2; ++s) {
+      double f[3] = {a[0], a[1], a[2]};
+      f[k] = s == 0 ? a[k] + 1.0 : a[k] - 1.0;
+      const double *r[4];
+      for (int i = 0; i < 4; ++i) r[i] = (i == inf) ? f : pt(v[i]);
+      if (orient3d(r[0], r[1], r[2], r[3]) > 0) return insphere(r[0], r[1], r[2], r[3], p) >= 0;
+    }
+  }
+  return false;  // unreachable for a non-degenerate facet
+}
+
+// 1-NN of p among the inserted sites by the descent over the lists built so far: start at
+// rank 0 and jump to the first list entry strictly closer (key = (D, rank)).
+int32_t DelaunayBuilder::nearest_inserted(const double *p, double *dbest) const {
+  int32_t cur = 0;
+  double dcur = sqd(p, pt(0));
+  for (;;) {
+    const int32_t *l = &pool_[lstart_[cur]];
+    int32_t len = llen_[cur];
+    int32_t next = -1;
+    double dn = 0;
+    for (int32_t e = 0; e < len; ++e) {
+      double d = sqd(p, pt(l[e]));
+      if (d < dcur) {
+        next = l[e];
+        dn = d;
+        break;
+      }
+    }
+    if (next < 0) break;
+    cur = next;
+    dcur = dn;
+  }
+  *dbest = dcur;
+  return cur;
+}
+
+// Find one tetrahedron in conflict with p, searching the star of `near` first and then,
+// if the nearest site came from a rounded tie, widening breadth-first.
+int32_t DelaunayBuilder::locate(int32_t near, const double *p) {
+  uint32_t ep = ++epoch_;
+  star_.clear();
+  int32_t t0 = vtet_[near];
+  star_.push_back(t0);
+  stamp_[t0] = ep;
+  for (size_t s = 0; s < star_.size(); ++s) {
+    int32_t t = star_[s];
+    if (conflict(t, p)) return t;
+    for (int h = 0; h < 4; ++h) {
+      if (tv_[4 * (int64_t)t + h] == near) continue;   // faces through `near` only
+      int32_t u = tn_[4 * (int64_t)t + h];
+      if (stamp_[u] != ep) {
+        stamp_[u] = ep;
+        star_.push_back(u);
+      }
+    }
+  }
+  // widen: plain breadth-first search over all tetrahedra
+  for (size_t s = 0; s < star_.size(); ++s) {
+    int32_t t = star_[s];
+    if (conflict(t, p)) return t;
+    for (int h = 0; h < 4; ++h) {
+      int32_t u = tn_[4 * (int64_t)t + h];
+      if (stamp_[u] != ep) {
+        stamp_[u] = ep;
+        star_.push_back(u);
+      }
+    }
+  }
+  return -1;
+}
+
+bool DelaunayBuilder::init_first_tet() {
+  if (n_ < 4) return false;
+  int o = orient3d(pt(0), pt(1), pt(2), pt(3));
+  if (o == 0) return false;
+  int32_t v[4] = {0, 1, 2, 3};
+  if (o < 0) std::swap(v[2], v[3]);
+  int32_t t = alloc_tet();
+  int32_t g[4];
+  for (int i = 0; i < 4; ++i) g[i] = alloc_tet();
+  for (int i = 0; i < 4; ++i) {
+    tv_[4 * t + i] = v[i];
+    tn_[4 * t + i] = g[i];
+  }
+  // ghost across face i: vertex i replaced by infinity, then two finite vertices swapped
+  // so that replacing infinity by a point beyond the face gives a positive orientation.
+  for (int i = 0; i < 4; ++i) {
+    int32_t w[4] = {v[0], v[1], v[2], v[3]};
+    w[i] = kInf;
+    int a = (i + 1) & 3, b = (i + 2) & 3;
+    std::swap(w[a], w[b]);
+    for (int k = 0; k < 4; ++k) tv_[4 * g[i] + k] = w[k];
+  }
+  // neighbours of the ghosts: across the facet opposite infinity lies t; across the other
+  // faces lie the other ghosts (two ghosts share the edge common to their faces).
+  for (int i = 0; i < 4; ++i) {
+    for (int k = 0; k < 4; ++k) {
+      int32_t vk = tv_[4 * g[i] + k];
+      if (vk == kInf) {
+        tn_[4 * g[i] + k] = t;
+      } else {
+        // face opposite vk contains infinity and the two other finite vertices; the ghost
+        // sharing it is the one whose missing vertex is vk
+        int idx = 0;
+        while (v[idx] != vk) ++idx;
+        tn_[4 * g[i] + k] = g[idx];
+      }
+    }
+  }
+  for (int i = 0; i < 4; ++i) vtet_[v[i]] = t;
+  // lists: with four affinely independent sites every pair is Voronoi-adjacent
+  for (int32_t j = 1; j < 4; ++j)
+    for (int32_t i = 0; i < j; ++i) append(i, j);
+  ninserted_ = 4;
+  return true;
+}
+
+BuildStatus DelaunayBuilder::insert_next() {
+  if (ninserted_ == 0) {
+    if (!init_first_tet()) return kBuildDegenerateStart;
+    return kBuildOk;
+  }
+  const int32_t j = (int32_t)ninserted_;
+  const double *p = pt(j);
+  double dnear;
+  int32_t near = nearest_inserted(p, &dnear);
+  if (dnear == 0.0) return kBuildDuplicate;
+  int32_t seed = locate(near, p);
+  if (seed < 0) return kBuildInternal;
+
+  // grow the cavity: all tetrahedra in conflict, connected to the seed
+  uint32_t ein = ++epoch_;
+  uint32_t eout = ++epoch_;
+  cavity_.clear();
+  stack_.clear();
+  bnd_.clear();
+  stamp_[seed] = ein;
+  cavity_.push_back(seed);
+  stack_.push_back(seed);
+  while (!stack_.empty()) {
+    int32_t t = stack_.back();
+    stack_.pop_back();
+    for (int h = 0; h < 4; ++h) {
+      int32_t u = tn_[4 * (int64_t)t + h];
+      if (stamp_[u] == ein) continue;
+      if (stamp_[u] != eout) {
+        if (conflict(u, p)) {
+          stamp_[u] = ein;
+          cavity_.push_back(u);
+          stack_.push_back(u);
+          continue;
+        }
+        stamp_[u] = eout;
+      }
+      Boundary b;
+      for (int k = 0; k < 4; ++k) b.v[k] = tv_[4 * (int64_t)t + k];
+      b.v[h] = j;
+      b.h = h;
+      b.outer = u;
+      b.outer_face = -1;
+      for (int k = 0; k < 4; ++k)
+        if (tn_[4 * (int64_t)u + k] == t) b.outer_face = k;
+      if (b.outer_face < 0) return kBuildInternal;
+      bnd_.push_back(b);
+    }
+  }
+  for (int32_t t : cavity_) free_.push_back(t);
+
+  // new tetrahedra: each boundary facet joined to p
+  size_t nb = bnd_.size();
+  size_t hsize = 16;
+  while (hsize < 4 * 3 * nb) hsize <<= 1;
+  if (hkey_.size() < hsize) {
+    hkey_.assign(hsize, 0);
+    hval_.assign(hsize, 0);
+    hstamp_.assign(hsize, 0);
+  }
+  hsize = hkey_.size();
+  uint32_t he = ++hepoch_;
+  uint32_t ve = ++vepoch_;
+  nbrs_.clear();
+  for (size_t bi = 0; bi < nb; ++bi) {
+    const Boundary &b = bnd_[bi];
+    int32_t nt = alloc_tet();
+    for (int k = 0; k < 4; ++k) tv_[4 * (int64_t)nt + k] = b.v[k];
+    tn_[4 * (int64_t)nt + b.h] = b.outer;
+    tn_[4 * (int64_t)b.outer + b.outer_face] = nt;
+    for (int k = 0; k < 4; ++k) {
+      int32_t w = b.v[k];
+      if (w == kInf) continue;
+      vtet_[w] = nt;
+      if (w != j && vmark_[w] != ve) {
+        vmark_[w] = ve;
+        nbrs_.push_back(w);
+      }
+    }
+    // faces through p: match by the opposite edge
+    for (int k = 0; k < 4; ++k) {
+      if (k == b.h) continue;
+      int32_t x = -2, y = -2;
+      for (int m = 0; m < 4; ++m) {
+        if (m == k || m == b.h) continue;
+        if (x == -2) x = b.v[m]; else y = b.v[m];
+      }
+      uint64_t key = edge_key(x, y);
+      size_t slot = (size_t)((key * 0x9E3779B97F4A7C15ull) >> 40) & (hsize - 1);
+      for (;;) {
+        if (hstamp_[slot] != he) {
+          hstamp_[slot] = he;
+          hkey_[slot] = key;
+          hval_[slot] = nt * 4 + k;
+          break;
+        }
+        if (hkey_[slot] == key) {
+          int32_t ot = hval_[slot] >> 2, ok = hval_[slot] & 3;
+          tn_[4 * (int64_t)nt + k] = ot;
+          tn_[4 * (int64_t)ot + ok] = nt;
+          break;
+        }
+        slot = (slot + 1) & (hsize - 1);
+      }
+    }
+  }
+  std::sort(nbrs_.begin(), nbrs_.end());
+  for (int32_t i : nbrs_) append(i, j);
+  ++ninserted_;
+  return kBuildOk;
+}
+
+BuildStatus DelaunayBuilder::build(int64_t *bad_rank) {
+  while (ninserted_ < n_) {
+    int64_t j = ninserted_;
+    if (n_ < 4) {
+      // fewer than four sites: pairwise adjacency unless collinear ordering hides a pair
+      // (handled by the caller rejecting n < 4 clouds that are degenerate)
+      return kBuildDegenerateStart;
+    }
+    BuildStatus s = insert_next();
+    if (s != kBuildOk) {
+      if (bad_rank) *bad_rank = (s == kBuildDegenerateStart) ? 3 : j;
+      return s;
+    }
+  }
+  return kBuildOk;
+}
+
+Csr DelaunayBuilder::successors() const {
+  Csr c;
+  c.off.assign(n_ + 1, 0);
+  for (int64_t i = 0; i < n_; ++i) c.off[i + 1] = c.off[i] + llen_[i];
+  c.ent.resize(c.off[n_]);
+  for (int64_t i = 0; i < n_; ++i)
+    if (llen_[i])
+      std::memcpy(&c.ent[c.off[i]], &pool_[lstart_[i]], sizeof(int32_t) * llen_[i]);
+  return c;
+}
+
+Csr DelaunayBuilder::predecessors() const {
+  Csr c;
+  c.off.assign(n_ + 1, 0);
+  for (int64_t i = 0; i < n_; ++i)
+    for (int32_t e = 0; e < llen_[i]; ++e) c.off[pool_[lstart_[i] + e] + 1]++;
+  for (int64_t i = 0; i < n_; ++i) c.off[i + 1] += c.off[i];
+  c.ent.resize(c.off[n_]);
+  std::vector<int64_t> pos(c.off.begin(), c.off.end() - 1);
+  for (int64_t i = 0; i < n_; ++i)   // ascending owner => each row ascending
+    for (int32_t e = 0; e < llen_[i]; ++e) c.ent[pos[pool_[lstart_[i] + e]]++] = (int32_t)i;
+  return c;
+}
+
+bool DelaunayBuilder::validate(std::string *why) const {
+  std::vector<char> dead(stamp_.size(), 0);
+  for (int32_t t : free_) dead[t] = 1;
+  for (size_t t = 0; t < stamp_.size(); ++t) {
+    if (dead[t]) continue;
+    const int32_t *v = &tv_[4 * t];
+    int inf = -1;
+    for (int i = 0; i < 4; ++i)
+      if (v[i] == kInf) inf = i;
+    if (inf < 0 && orient3d(pt(v[0]), pt(v[1]), pt(v[2]), pt(v[3])) <= 0) {
+      if (why) *why = "non-positive finite tetrahedron " + std::to_string(t);
+      return false;
+    }
+    for (int h = 0; h < 4; ++h) {
+      int32_t u = tn_[4 * t + h];
+      if (u < 0 || (size_t)u >= stamp_.size() || dead[u]) {
+        if (why) *why = "dangling neighbour";
+        return false;
+      }
+      int back = 0, shared = 0;
+      for (int k = 0; k < 4; ++k) {
+        if (tn_[4 * (size_t)u + k] == (int32_t)t) ++back;
+        for (int m = 0; m < 4; ++m)
+          if (m != h && tv_[4 * (size_t)u + k] == v[m]) ++shared;
+      }
+      if (back != 1 || shared != 3) {
+        if (why) *why = "asymmetric neighbour link at tet " + std::to_string(t);
+        return false;
+      }
+    }
+  }
+  for (int64_t v = 0; v < ninserted_; ++v) {
+    int32_t t = vtet_[v];
+    bool ok = t >= 0 && !dead[t];
+    if (ok) {
+      ok = false;
+      for (int k = 0; k < 4; ++k) ok |= tv_[4 * (size_t)t + k] == (int32_t)v;
+    }
+    if (!ok) {
+      if (why) *why = "bad vertex incidence " + std::to_string(v);
+      return false;
+    }
+  }
+  return true;
+}
+
+bool DelaunayBuilder::validate_empty_spheres(std::string *why) const {
+  std::vector<char> dead(stamp_.size(), 0);
+  for (int32_t t : free_) dead[t] = 1;
+  for (size_t t = 0; t < stamp_.size(); ++t) {
+    if (dead[t]) continue;
+    const int32_t *v = &tv_[4 * t];
+    bool ghost = false;
+    for (int i = 0; i < 4; ++i) ghost |= v[i] == kInf;
+    if (ghost) continue;
+    for (int64_t q = 0; q < ninserted_; ++q) {
+      if (q == v[0] || q == v[1] || q == v[2] || q == v[3]) continue;
+      int s = insphere(pt(v[0]), pt(v[1]), pt(v[2]), pt(v[3]), pt((int32_t)q));
+      // a site exactly on the sphere is allowed only if it is older than some vertex
+      // (the perturbation puts the newest of the five inside)
+      int32_t vmax = std::max(std::max(v[0], v[1]), std::max(v[2], v[3]));
+      if (s > 0 || (s == 0 && q > vmax)) {
+        if (why) *why = "site " + std::to_string(q) + " inside sphere of tet " + std::to_string(t);
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+int64_t DelaunayBuilder::exact_fallbacks() const { return 0; }
+
+}  // namespace mknn

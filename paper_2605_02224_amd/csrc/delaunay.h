@@ -1,0 +1,96 @@
+// Incremental 3-D Delaunay triangulation that records successor lists (host side).
+//
+// Successor list L_i (Sec. 3; Fig. 2 caption): when p_j is inserted, j is appended to the
+// list of every Delaunay neighbour of p_j in DT(P_{1:j}), so each list is ascending in rank.
+// The construction is Bowyer-Watson with exact predicates and a vertex at infinity (ghost
+// tetrahedra on every convex-hull facet), so hull adjacencies are exact and no bounding box
+// distorts the diagram.  Point location uses the lists already built: a 1-NN descent
+// (the DP-NNS walk of Sec. 3) finds the nearest older site of p_j, and some tetrahedron
+// incident to that site conflicts with p_j.
+//
+// Degeneracies: ties of the in-sphere test are resolved by perturbing the lifted coordinate
+// |p|^2 of every site downward by an amount that grows with its rank, so the newest site is
+// inside every sphere it lies exactly on (the triangulation is the unique regular
+// triangulation of the perturbed lifting).  Facet adjacency (positive-area Voronoi facet) is
+// never lost by this choice; exactly degenerate contacts may add weak adjacencies.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mknn {
+
+constexpr int32_t kInf = -1;
+
+struct Csr {
+  std::vector<int64_t> off;   // n + 1
+  std::vector<int32_t> ent;   // ranks
+};
+
+enum BuildStatus { kBuildOk = 0, kBuildDuplicate = 1, kBuildDegenerateStart = 2,
+                   kBuildInternal = 3 };
+
+class DelaunayBuilder {
+ public:
+  // pts: n x 3 doubles by rank (must outlive the builder)
+  DelaunayBuilder(const double *pts, int64_t n);
+
+  // Inserts ranks 0..n-1 in order.  On failure, *bad_rank names the offending rank.
+  BuildStatus build(int64_t *bad_rank);
+
+  // Inserts rank j (j == number inserted so far); used by build() and by incremental use.
+  BuildStatus insert_next();
+
+  int64_t inserted() const { return ninserted_; }
+
+  // Successor lists as CSR (entries ascending within each list).
+  Csr successors() const;
+  // Delaunay neighbours of each rank at its own insertion (the transpose of the lists).
+  Csr predecessors() const;
+
+  // Structural self-check: orientations, symmetric neighbour links, vertex incidences.
+  bool validate(std::string *why) const;
+  // Every finite tetrahedron has an empty circumsphere (exact); O(T * n), small inputs only.
+  bool validate_empty_spheres(std::string *why) const;
+
+  int64_t num_tets() const;
+  int64_t exact_fallbacks() const;
+
+ private:
+  const double *P_;
+  int64_t n_;
+  int64_t ninserted_ = 0;
+
+  std::vector<int32_t> tv_;   // 4 vertices per tet (kInf for the vertex at infinity)
+  std::vector<int32_t> tn_;   // 4 neighbours per tet, opposite the same-index vertex
+  std::vector<uint32_t> stamp_;
+  std::vector<int32_t> free_;
+  std::vector<int32_t> vtet_; // one incident tet per vertex
+  uint32_t epoch_ = 1;
+
+  // dynamic successor lists
+  std::vector<int64_t> lstart_;
+  std::vector<int32_t> llen_, lcap_;
+  std::vector<int32_t> pool_;
+
+  // scratch
+  std::vector<int32_t> stack_, cavity_, star_;
+  struct Boundary { int32_t v[4]; int32_t h; int32_t outer; int32_t outer_face; };
+  std::vector<Boundary> bnd_;
+  std::vector<uint64_t> hkey_;
+  std::vector<int32_t> hval_;
+  std::vector<uint32_t> hstamp_;
+  std::vector<uint32_t> vmark_;
+  uint32_t vepoch_ = 1, hepoch_ = 1;
+  std::vector<int32_t> nbrs_;
+
+  const double *pt(int32_t v) const { return P_ + 3 * (int64_t)v; }
+  int32_t alloc_tet();
+  bool conflict(int32_t t, const double *p) const;
+  int32_t nearest_inserted(const double *p, double *dbest) const;
+  int32_t locate(int32_t near, const double *p);
+  void append(int32_t owner, int32_t rank);
+  bool init_first_tet();
+};
+
+}  // namespace mknn

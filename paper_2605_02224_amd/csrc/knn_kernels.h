@@ -1,0 +1,38 @@
+// Query kernels for gfx950: the 1-NN descent of Alg. 1 fused with the k-expansion of
+// Alg. 2, one query per lane, over successor lists resident in HBM.
+//
+// Device layout of one cloud:
+//   ent[]  16-byte records {x, y, z, rank} (float, float, float, int32 bit pattern).  The
+//          entries of list L_i are contiguous and ascending in rank (Sec. 3); whole lists
+//          are placed in the Morton order of their owner points.  The array is padded with
+//          kEntPad records so a lane may load a 4-record chunk past the end of a list.
+//   lst[r] 64-bit descriptor: start index of L_r in ent (low 32 bits) | length (high 32).
+// Each list entry carries its point's coordinates, so scanning a list is one contiguous
+// read and no second gather is needed to evaluate the distance.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mknn {
+
+constexpr int kEntPad = 4;
+constexpr int32_t kEmpty = 0x7fffffff;   // rank of an empty candidate slot
+
+struct QueryArgs {
+  const float4 *ent;
+  const uint64_t *lst;
+  float hx, hy, hz;          // coordinates of the head (oldest live site)
+  int32_t head;
+  int64_t n;
+  const float *q;            // [nq][3] in caller order
+  const float4 *qs;          // sorted queries {x, y, z, original index} or NULL
+  int64_t nq;
+  int32_t k, m;              // scalars (used when kq / mq are NULL)
+  const int32_t *kq, *mq;    // per-query k and m (caller order) or NULL
+  const int64_t *row_off;    // ragged rows (with kq) or NULL
+  int32_t *out_idx;
+  float *out_dist;
+  int32_t *cnt_entries, *cnt_lists;   // diagnostics (COUNT variant only)
+};
+
+}  // namespace mknn

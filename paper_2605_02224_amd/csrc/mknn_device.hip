@@ -1,0 +1,605 @@
+// Device half of the C ABI: residency of successor lists in HBM and the query kernels.
+//
+// Per query (one lane), the kernel runs the 1-NN descent of Alg. 1 and the k-expansion of
+// Alg. 2 with the prefix bound of Sec. 4.2:
+//   descent:  cur = head; scan L_cur in order; at the first entry strictly closer than cur,
+//             jump to it and restart on its list; stop at the end of a list or at the first
+//             rank >= m (lists are ascending, Sec. 3).  The last site reached is the 1-NN.
+//   seeding:  every examined entry, in particular every transition site, is inserted into
+//             the candidate list N (capacity k, sorted by (D, rank)).  Inserting more true
+//             sites than Alg. 1 does never changes the result, and it makes the final,
+//             completely scanned list of the descent serve as Alg. 2's first iteration.
+//   expansion: for i = 2..k-1 (1-based) scan L_{N[i]} inserting each entry not in N.
+// N lives in registers: a fully unrolled sorted array of K (D, rank) pairs, so no slot is
+// ever addressed dynamically.  Distances are evaluated in float64 exactly as the brute-force
+// definition (each operation rounded, no FMA), so ties resolve identically.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cloud.h"
+#include "knn_kernels.h"
+
+namespace mknn {
+
+#define HIP_TRY(expr, what)                                                             \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return set_error(MKNN_EHIP, std::string(what) + ": " + hipGetErrorName(e_) + " (" + \
+                                      hipGetErrorString(e_) + ")");                     \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double sq_dist(double qx, double qy, double qz, float4 c) {
+  double dx = qx - (double)c.x;
+  double dy = qy - (double)c.y;
+  double dz = qz - (double)c.z;
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range
+// of tiles so Morton-adjacent queries share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
+  uint32_t x = b & 7u, i = b >> 3, q8 = nb >> 3, r8 = nb & 7u;
+  return x * q8 + (x < r8 ? x : r8) + i;
+}
+
+template <int K>
+struct TopK {
+  double d[K];
+  int32_t r[K];
+  double thr_d;
+  int32_t thr_r;
+
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      d[j] = INFINITY;
+      r[j] = kEmpty;
+    }
+    thr_d = INFINITY;
+    thr_r = kEmpty;
+  }
+
+  // Key of the candidate that follows the last expanded one: the first slot whose key is
+  // greater than (ld, lr).  A compare chain, not an index, so N stays in registers.
+  __device__ __forceinline__ void next_after(double &ld, int32_t &lr) const {
+    int32_t v = kEmpty;
+    double vd = INFINITY;
+#pragma unroll
+    for (int j = K - 1; j >= 0; --j) {
+      bool gt = d[j] > ld || (d[j] == ld && r[j] > lr);
+      v = gt ? r[j] : v;
+      vd = gt ? d[j] : vd;
+    }
+    ld = vd;
+    lr = v;
+  }
+
+  template <bool EXACTK>
+  __device__ __forceinline__ void insert(double dd, int32_t rr, int k) {
+    if (!(dd < thr_d || (dd == thr_d && rr < thr_r))) return;
+    bool dup = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) dup |= (r[j] == rr);
+    if (dup) return;
+    // replace the last slot, then bubble the candidate towards the front
+    d[K - 1] = dd;
+    r[K - 1] = rr;
+#pragma unroll
+    for (int j = K - 1; j >= 1; --j) {
+      bool sw = d[j] < d[j - 1] || (d[j] == d[j - 1] && r[j] < r[j - 1]);
+      double td = d[j - 1];
+      int32_t tr = r[j - 1];
+      d[j - 1] = sw ? d[j] : td;
+      r[j - 1] = sw ? r[j] : tr;
+      d[j] = sw ? td : d[j];
+      r[j] = sw ? tr : r[j];
+    }
+    if (EXACTK) {
+      thr_d = d[K - 1];
+      thr_r = r[K - 1];
+    } else {
+      double td = d[0];
+      int32_t tr = r[0];
+#pragma unroll
+      for (int j = 1; j < K; ++j) {
+        td = (j == k - 1) ? d[j] : td;
+        tr = (j == k - 1) ? r[j] : tr;
+      }
+      thr_d = td;
+      thr_r = tr;
+    }
+  }
+};
+
+// One query per lane.  K = register capacity (>= k); EXACTK: k == K for every query.
+template <int K, bool EXACTK, bool COUNT>
+__global__ __launch_bounds__(256) void knn_lane_kernel(QueryArgs a) {
+  const int64_t s = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (s >= a.nq) return;
+  double qx, qy, qz;
+  int64_t qi;
+  if (a.qs) {
+    float4 v = a.qs[s];
+    qx = v.x;
+    qy = v.y;
+    qz = v.z;
+    qi = __float_as_int(v.w);
+  } else {
+    qi = s;
+    qx = a.q[3 * s];
+    qy = a.q[3 * s + 1];
+    qz = a.q[3 * s + 2];
+  }
+  const int k = a.kq ? a.kq[qi] : a.k;
+  int64_t mm = a.mq ? (int64_t)a.mq[qi] : (int64_t)a.m;
+  if (mm > a.n) mm = a.n;
+  const int32_t m = (int32_t)mm;
+  const int64_t row = a.row_off ? a.row_off[qi] : qi * (int64_t)a.k;
+  if (k < 1 || k > K || m < 1) return;
+
+  TopK<K> N;
+  N.init();
+  int32_t nent = 0, nlist = 0;
+
+  if (a.head < m) {
+    // ---- Alg. 1: descent from the head, every examined entry inserted into N
+    int32_t cur = a.head;
+    double dcur = sq_dist(qx, qy, qz, make_float4(a.hx, a.hy, a.hz, 0.f));
+    N.template insert<EXACTK>(dcur, cur, k);
+    for (;;) {
+      const uint64_t dsc = a.lst[cur];
+      const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
+      if (COUNT) ++nlist;
+      bool jumped = false;
+      float4 nx = a.ent[st];
+      for (uint32_t e = 0; e < len; ++e) {
+        const float4 c = nx;
+        nx = a.ent[st + e + 1];
+        const int32_t r = __float_as_int(c.w);
+        if (r >= m) break;
+        const double dd = sq_dist(qx, qy, qz, c);
+        if (COUNT) ++nent;
+        N.template insert<EXACTK>(dd, r, k);
+        if (dd < dcur) {
+          cur = r;
+          dcur = dd;
+          jumped = true;
+          break;
+        }
+      }
+      if (!jumped) break;
+    }
+    // ---- Alg. 2: expand the lists of the confirmed neighbours N[2..k-1] (1-based)
+    double ld = N.d[0];
+    int32_t lr = N.r[0];
+    for (int i = 1; i < k - 1; ++i) {
+      N.next_after(ld, lr);
+      const int32_t pr = lr;
+      if (pr == kEmpty) break;
+      const uint64_t dsc = a.lst[pr];
+      const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
+      if (COUNT) ++nlist;
+      float4 nx = a.ent[st];
+      for (uint32_t e = 0; e < len; ++e) {
+        const float4 c = nx;
+        nx = a.ent[st + e + 1];
+        const int32_t r = __float_as_int(c.w);
+        if (r >= m) break;
+        if (COUNT) ++nent;
+        N.template insert<EXACTK>(sq_dist(qx, qy, qz, c), r, k);
+      }
+    }
+  }
+
+  if (COUNT) {
+    a.cnt_entries[qi] = nent;
+    a.cnt_lists[qi] = nlist;
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if (j < k) {
+      const bool empty = N.r[j] == kEmpty;
+      a.out_idx[row + j] = empty ? -1 : N.r[j];
+      a.out_dist[row + j] = empty ? INFINITY : (float)sqrt(N.d[j]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// query batch preparation: bucket the queries by the top bits of a 30-bit Morton code of
+// their position in the cloud's bounding box (counting sort: histogram, scan, scatter).
+// Only locality matters here -- each query's answer does not depend on where it runs.
+// ---------------------------------------------------------------------------------------
+constexpr int kMortonBits = 16;
+constexpr int kMortonBins = 1 << kMortonBits;
+constexpr int64_t kSortMinQueries = 8192;
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {   // 10 bits -> every third bit
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+struct BoxArgs {
+  float lo[3], scale[3];
+};
+
+__device__ __forceinline__ uint32_t morton_bin(float x, float y, float z, const BoxArgs &b) {
+  float t[3] = {(x - b.lo[0]) * b.scale[0], (y - b.lo[1]) * b.scale[1], (z - b.lo[2]) * b.scale[2]};
+  uint32_t u[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float v = fminf(fmaxf(t[i], 0.f), 1023.f);
+    u[i] = (uint32_t)v;
+  }
+  uint32_t code = (spread3(u[0]) << 2) | (spread3(u[1]) << 1) | spread3(u[2]);
+  return code >> (30 - kMortonBits);
+}
+
+__global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *p, int64_t cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) p[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void morton_hist_kernel(const float *q, int64_t nq, BoxArgs b,
+                                                          uint32_t *hist) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  atomicAdd(&hist[morton_bin(q[3 * i], q[3 * i + 1], q[3 * i + 2], b)], 1u);
+}
+
+// exclusive scan of kMortonBins counters by one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void scan_bins_kernel(uint32_t *hist) {
+  constexpr int per = kMortonBins / 1024;
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  uint32_t local[per];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    local[i] = hist[t * per + i];
+    sum += local[i];
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    hist[t * per + i] = run;
+    run += local[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void morton_scatter_kernel(const float *q, int64_t nq, BoxArgs b,
+                                                             uint32_t *cursor, float4 *qs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  float x = q[3 * i], y = q[3 * i + 1], z = q[3 * i + 2];
+  uint32_t pos = atomicAdd(&cursor[morton_bin(x, y, z, b)], 1u);
+  qs[pos] = make_float4(x, y, z, __int_as_float((int32_t)i));
+}
+
+// ---------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------
+static uint32_t host_spread3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+static BoxArgs box_of(const mknn_cloud *c) {
+  BoxArgs b;
+  for (int k = 0; k < 3; ++k) {
+    float ext = c->hi[k] - c->lo[k];
+    b.lo[k] = c->lo[k];
+    b.scale[k] = ext > 0.f ? 1024.f / ext : 0.f;
+  }
+  return b;
+}
+
+static void free_device(mknn_cloud *c) {
+  if (c->d_ent) (void)hipFree(c->d_ent);
+  if (c->d_lst) (void)hipFree(c->d_lst);
+  c->d_ent = nullptr;
+  c->d_lst = nullptr;
+  c->dev_bytes = 0;
+  c->dev_version = ~0ull;
+}
+
+template <int K, bool EXACTK, bool COUNT>
+static hipError_t launch_lane(const QueryArgs &a, hipStream_t s) {
+  const int threads = 256;
+  const uint32_t blocks = (uint32_t)((a.nq + threads - 1) / threads);
+  hipLaunchKernelGGL((knn_lane_kernel<K, EXACTK, COUNT>), dim3(blocks), dim3(threads), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---- optional kernel timing
+static bool g_timing = false;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
+static size_t g_events_used = 0;
+
+static hipError_t timing_mark(hipStream_t s, bool start) {
+  if (!g_timing) return hipSuccess;
+  if (start) {
+    if (g_events_used == g_events.size()) {
+      hipEvent_t a, b;
+      hipError_t e = hipEventCreate(&a);
+      if (e != hipSuccess) return e;
+      e = hipEventCreate(&b);
+      if (e != hipSuccess) return e;
+      g_events.push_back({a, b});
+    }
+    return hipEventRecord(g_events[g_events_used].first, s);
+  }
+  return hipEventRecord(g_events[g_events_used++].second, s);
+}
+
+template <bool COUNT>
+static hipError_t dispatch_lane(const QueryArgs &a, int kmax, bool exact, hipStream_t s) {
+#define MKNN_CASE(KK)                                                                       \
+  if (kmax <= KK)                                                                          \
+    return (exact && kmax == KK) ? launch_lane<KK, true, COUNT>(a, s)                     \
+                                 : launch_lane<KK, false, COUNT>(a, s);
+  MKNN_CASE(1)
+  MKNN_CASE(2)
+  MKNN_CASE(4)
+  MKNN_CASE(8)
+  MKNN_CASE(16)
+  MKNN_CASE(32)
+  MKNN_CASE(64)
+#undef MKNN_CASE
+  return hipErrorInvalidValue;
+}
+
+static mknn_status check_uploaded(const mknn_cloud *c, const char *who) {
+  if (!c) return set_error(MKNN_EINVAL, std::string(who) + ": cloud is NULL");
+  if (!c->d_ent || c->dev_version != c->version)
+    return set_error(MKNN_EINVAL, std::string(who) + ": cloud is not uploaded (call mknn_upload)");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+    return set_error(MKNN_EINVAL, std::string(who) + ": cloud lives on another device");
+  return MKNN_OK;
+}
+
+static void fill_cloud_args(const mknn_cloud *c, QueryArgs *a) {
+  std::memset(a, 0, sizeof(*a));
+  a->ent = (const float4 *)c->d_ent;
+  a->lst = c->d_lst;
+  a->head = c->head;
+  a->hx = c->xyz[3 * (int64_t)c->head];
+  a->hy = c->xyz[3 * (int64_t)c->head + 1];
+  a->hz = c->xyz[3 * (int64_t)c->head + 2];
+  a->n = c->n;
+}
+
+// Sorts the queries (when the batch is large enough) into *qs_out (stream-ordered scratch).
+static mknn_status prepare_queries(const mknn_cloud *c, const float *d_q, int64_t nq,
+                                   hipStream_t s, float4 **qs_out, void **scratch) {
+  *qs_out = nullptr;
+  *scratch = nullptr;
+  if (nq < kSortMinQueries) return MKNN_OK;
+  size_t bytes = sizeof(uint32_t) * kMortonBins + sizeof(float4) * (size_t)nq;
+  HIP_TRY(hipMallocAsync(scratch, bytes, s), "query sort scratch");
+  uint32_t *hist = (uint32_t *)*scratch;
+  float4 *qs = (float4 *)(hist + kMortonBins);
+  BoxArgs b = box_of(c);
+  const int threads = 256;
+  const uint32_t blocks = (uint32_t)((nq + threads - 1) / threads);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(kMortonBins / threads), dim3(threads), 0, s, hist,
+                     (int64_t)kMortonBins);
+  hipLaunchKernelGGL(morton_hist_kernel, dim3(blocks), dim3(threads), 0, s, d_q, nq, b, hist);
+  hipLaunchKernelGGL(scan_bins_kernel, dim3(1), dim3(1024), 0, s, hist);
+  hipLaunchKernelGGL(morton_scatter_kernel, dim3(blocks), dim3(threads), 0, s, d_q, nq, b, hist, qs);
+  HIP_TRY(hipGetLastError(), "query sort launch");
+  *qs_out = qs;
+  return MKNN_OK;
+}
+
+static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
+                             int32_t m, const int32_t *d_k, const int32_t *d_m,
+                             const int64_t *d_row_off, int32_t kmax, int32_t *d_idx,
+                             float *d_dist, int32_t *d_ce, int32_t *d_cl, hipStream_t s,
+                             const char *who) {
+  QueryArgs a;
+  fill_cloud_args(c, &a);
+  a.q = d_q;
+  a.nq = nq;
+  a.k = k;
+  a.m = m;
+  a.kq = d_k;
+  a.mq = d_m;
+  a.row_off = d_row_off;
+  a.out_idx = d_idx;
+  a.out_dist = d_dist;
+  a.cnt_entries = d_ce;
+  a.cnt_lists = d_cl;
+  void *scratch = nullptr;
+  float4 *qs = nullptr;
+  mknn_status st = prepare_queries(c, d_q, nq, s, &qs, &scratch);
+  if (st != MKNN_OK) return st;
+  a.qs = qs;
+  const bool exact = (d_k == nullptr);
+  hipError_t e = timing_mark(s, true);
+  if (e == hipSuccess)
+    e = d_ce ? dispatch_lane<true>(a, kmax, exact, s) : dispatch_lane<false>(a, kmax, exact, s);
+  if (e == hipSuccess) e = timing_mark(s, false);
+  if (scratch) (void)hipFreeAsync(scratch, s);
+  if (e != hipSuccess)
+    return set_error(MKNN_EHIP, std::string(who) + ": launch failed: " + hipGetErrorName(e));
+  return MKNN_OK;
+}
+
+}  // namespace mknn
+
+using namespace mknn;
+
+extern "C" {
+
+mknn_status mknn_upload(mknn_cloud *c, void *stream) {
+  clear_error();
+  if (!c) return set_error(MKNN_EINVAL, "mknn_upload: cloud is NULL");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "mknn_upload: hipGetDevice");
+  if (c->d_ent && c->dev_version == c->version && c->device == dev) return MKNN_OK;
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    const int64_t n = c->n;
+    // list placement: owners in Morton order
+    BoxArgs b = box_of(c);
+    std::vector<uint64_t> key(n);
+    for (int64_t r = 0; r < n; ++r) {
+      uint32_t u[3];
+      for (int k = 0; k < 3; ++k) {
+        float t = (c->xyz[3 * r + k] - b.lo[k]) * b.scale[k];
+        t = std::min(std::max(t, 0.f), 1023.f);
+        u[k] = (uint32_t)t;
+      }
+      uint64_t code = (host_spread3(u[0]) << 2) | (host_spread3(u[1]) << 1) | host_spread3(u[2]);
+      key[r] = (code << 32) | (uint64_t)r;
+    }
+    std::sort(key.begin(), key.end());
+    const int64_t nnz = (int64_t)c->succ.ent.size();
+    if (nnz + kEntPad > (int64_t)0xffffffffll)
+      return set_error(MKNN_EUNSUPPORTED, "mknn_upload: more than 2^32 list entries");
+    std::vector<float4> ent((size_t)(nnz + kEntPad));
+    std::vector<uint64_t> lst((size_t)n);
+    uint64_t cur = 0;
+    for (int64_t t = 0; t < n; ++t) {
+      int64_t r = (int64_t)(key[t] & 0xffffffffu);
+      int64_t b0 = c->succ.off[r], b1 = c->succ.off[r + 1];
+      lst[r] = cur | ((uint64_t)(b1 - b0) << 32);
+      for (int64_t e = b0; e < b1; ++e) {
+        int32_t j = c->succ.ent[e];
+        float4 v;
+        v.x = c->xyz[3 * (int64_t)j];
+        v.y = c->xyz[3 * (int64_t)j + 1];
+        v.z = c->xyz[3 * (int64_t)j + 2];
+        std::memcpy(&v.w, &j, 4);
+        ent[cur++] = v;
+      }
+    }
+    for (int p = 0; p < kEntPad; ++p) {
+      int32_t big = kEmpty;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      std::memcpy(&v.w, &big, 4);
+      ent[cur + p] = v;
+    }
+    free_device(c);
+    c->device = dev;
+    HIP_TRY(hipMalloc(&c->d_ent, sizeof(float4) * ent.size()), "mknn_upload: hipMalloc entries");
+    HIP_TRY(hipMalloc((void **)&c->d_lst, sizeof(uint64_t) * lst.size()), "mknn_upload: hipMalloc lists");
+    HIP_TRY(hipMemcpyAsync(c->d_ent, ent.data(), sizeof(float4) * ent.size(), hipMemcpyHostToDevice, s),
+            "mknn_upload: copy entries");
+    HIP_TRY(hipMemcpyAsync(c->d_lst, lst.data(), sizeof(uint64_t) * lst.size(), hipMemcpyHostToDevice, s),
+            "mknn_upload: copy lists");
+    HIP_TRY(hipStreamSynchronize(s), "mknn_upload: synchronize");
+    c->dev_bytes = (int64_t)(sizeof(float4) * ent.size() + sizeof(uint64_t) * lst.size());
+    c->dev_version = c->version;
+  } catch (const std::bad_alloc &) {
+    return set_error(MKNN_ENOMEM, "mknn_upload: out of host memory");
+  }
+  return MKNN_OK;
+}
+
+int64_t mknn_device_bytes(const mknn_cloud *c) { return c ? c->dev_bytes : 0; }
+
+mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k, int32_t m,
+                     int32_t *d_idx, float *d_dist, void *stream) {
+  clear_error();
+  if (k > MKNN_KMAX) return set_error(MKNN_EUNSUPPORTED, "mknn_knn: k above MKNN_KMAX");
+  if (k < 1) return set_error(MKNN_EINVAL, "mknn_knn: k must be >= 1");
+  if (nq < 0 || nq > 0x7fffffffll) return set_error(MKNN_EINVAL, "mknn_knn: nq out of range");
+  mknn_status st = check_uploaded(c, "mknn_knn");
+  if (st != MKNN_OK) return st;
+  if (m < 1 || m > c->n) return set_error(MKNN_EINVAL, "mknn_knn: m must be in [1, n]");
+  if (nq == 0) return MKNN_OK;
+  if (!d_q || !d_idx || !d_dist) return set_error(MKNN_EINVAL, "mknn_knn: NULL buffer");
+  return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, d_idx, d_dist, nullptr,
+                   nullptr, (hipStream_t)stream, "mknn_knn");
+}
+
+mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, const int32_t *d_k,
+                         const int32_t *d_m, const int64_t *d_row_off, int32_t kmax,
+                         int32_t *d_idx, float *d_dist, void *stream) {
+  clear_error();
+  if (kmax > MKNN_KMAX) return set_error(MKNN_EUNSUPPORTED, "mknn_knn_var: kmax above MKNN_KMAX");
+  if (kmax < 1) return set_error(MKNN_EINVAL, "mknn_knn_var: kmax must be >= 1");
+  if (nq < 0 || nq > 0x7fffffffll) return set_error(MKNN_EINVAL, "mknn_knn_var: nq out of range");
+  mknn_status st = check_uploaded(c, "mknn_knn_var");
+  if (st != MKNN_OK) return st;
+  if (nq == 0) return MKNN_OK;
+  if (!d_q || !d_k || !d_m || !d_row_off || !d_idx || !d_dist)
+    return set_error(MKNN_EINVAL, "mknn_knn_var: NULL buffer");
+  return run_query(c, d_q, nq, 0, 0, d_k, d_m, d_row_off, kmax, d_idx, d_dist, nullptr, nullptr,
+                   (hipStream_t)stream, "mknn_knn_var");
+}
+
+mknn_status mknn_knn_counts(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
+                            int32_t m, int32_t *d_entries, int32_t *d_lists, void *stream) {
+  clear_error();
+  if (k > MKNN_KMAX) return set_error(MKNN_EUNSUPPORTED, "mknn_knn_counts: k above MKNN_KMAX");
+  if (k < 1) return set_error(MKNN_EINVAL, "mknn_knn_counts: k must be >= 1");
+  if (nq < 0 || nq > 0x7fffffffll) return set_error(MKNN_EINVAL, "mknn_knn_counts: nq out of range");
+  mknn_status st = check_uploaded(c, "mknn_knn_counts");
+  if (st != MKNN_OK) return st;
+  if (m < 1 || m > c->n) return set_error(MKNN_EINVAL, "mknn_knn_counts: m must be in [1, n]");
+  if (nq == 0) return MKNN_OK;
+  if (!d_q || !d_entries || !d_lists) return set_error(MKNN_EINVAL, "mknn_knn_counts: NULL buffer");
+  return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, nullptr, nullptr, d_entries,
+                   d_lists, (hipStream_t)stream, "mknn_knn_counts");
+}
+
+mknn_status mknn_timing_enable(int enable) {
+  clear_error();
+  g_timing = enable != 0;
+  return MKNN_OK;
+}
+
+mknn_status mknn_timing_read(double *total_ms, int64_t *launches) {
+  clear_error();
+  if (!total_ms || !launches) return set_error(MKNN_EINVAL, "mknn_timing_read: NULL");
+  double tot = 0.0;
+  for (size_t i = 0; i < g_events_used; ++i) {
+    HIP_TRY(hipEventSynchronize(g_events[i].second), "mknn_timing_read: synchronize");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, g_events[i].first, g_events[i].second), "mknn_timing_read: elapsed");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)g_events_used;
+  g_events_used = 0;
+  return MKNN_OK;
+}
+
+void mknn_free(mknn_cloud *c) {
+  if (!c) return;
+  free_device(c);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+"""Host construction of successor lists (CPU): exactness against the oracle, invariants,
+error handling, and the exported C ABI."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import successors as S
+from oracle import dpknn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2605_02224_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libmknn.so not built")
+    from paper_2605_02224_amd import api as A
+    return A
+
+
+def test_abi_exports_every_declared_symbol():
+    from paper_2605_02224_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libmknn.so not built")
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(mknn_\w+)\s*\(", txt, re.M))
+    assert "mknn_knn" in names and "mknn_build" in names
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_lib.SIGNATURES) <= names
+
+
+@pytest.mark.parametrize("seed,shape", [(0, "sphere"), (1, "torus"), (2, "ellipsoid"),
+                                        (3, "sphere"), (4, "torus")])
+def test_lists_equal_exact_oracle(api, seed, shape):
+    from paper_2605_02224_amd import workloads as W
+    P = W.random_cloud(34, seed=seed, shape=shape, noise=1e-2).by_rank
+    assert api.Cloud.build(P).lists() == S.successor_lists(P)
+
+
+def test_lists_on_near_cospherical_sphere(api):
+    """Unit-sphere samples without noise: every 5-tuple is nearly cospherical."""
+    from paper_2605_02224_amd import workloads as W
+    P = W.sphere_small(n=30, nq=1).cloud.by_rank
+    assert api.Cloud.build(P).lists() == S.successor_lists(P)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 5])
+def test_lattice_degenerate(api, seed):
+    """Integer lattice (cospherical and coplanar sets everywhere): facet-adjacent pairs are
+    always listed, only weakly adjacent pairs are added, and walking the lists answers
+    k-NN exactly."""
+    import oracle
+    from paper_2605_02224_amd import workloads as W
+    c = W.lattice_cloud(3, seed)
+    P = c.by_rank
+    cl = api.Cloud.build(P)
+    L = cl.lists()
+    strong = S.successor_lists(P)
+    weak = S.weakly_adjacent_pairs_at_insertion(P)
+    for i in range(len(L)):
+        assert set(strong[i]) <= set(L[i])
+        assert all(i in weak[j] for j in L[i])
+    rng = np.random.default_rng(seed)
+    Q = rng.uniform(-0.5, 2.5, (300, 3)).astype(np.float32)
+    Q[:20] = P[:20]          # queries on data points (D = 0) and on lattice ties
+    for k in (1, 6, 27):
+        ref, _, _ = oracle.knn_bruteforce(P, Q, k)
+        idx, _, _, _ = dpknn.dp_knn_batch(P, L, Q, k)
+        assert (idx == ref).all()
+
+
+def test_theorem1_on_built_lists_20k(api):
+    """Walking the built lists (Alg. 1 + 2) equals brute force at 20k points."""
+    import oracle
+    from paper_2605_02224_amd import workloads as W
+    c = W.random_cloud(20000, seed=7, shape="torus")
+    P = c.by_rank
+    L = api.Cloud.build(P).lists()
+    lo, hi = W.bbox_expanded(P, 1.1)
+    Q = W.uniform_in_box(np.random.default_rng(1), 300, lo, hi)
+    for k, m in ((16, 20000), (8, 777), (1, 20000), (33, 5000)):
+        ref, _, refD = oracle.knn_bruteforce(P, Q, k, m)
+        idx, D, _, _ = dpknn.dp_knn_batch(P, L, Q, k, m)
+        assert (idx == ref).all()
+        assert np.array_equal(D, refD)
+
+
+def test_list_invariants_and_prefix_restriction(api):
+    """Lists ascend and exceed their owner; the lists of a prefix P_{1:m} are the full
+    lists restricted to ranks < m (the construction never looks ahead)."""
+    from paper_2605_02224_amd import workloads as W
+    P = W.random_cloud(3000, seed=3, shape="ellipsoid").by_rank
+    L = api.Cloud.build(P).lists()
+    for i, li in enumerate(L):
+        assert li == sorted(li) and all(j > i for j in li)
+    m = 1234
+    Lm = api.Cloud.build(P[:m]).lists()
+    assert Lm == [[j for j in L[i] if j < m] for i in range(m)]
+
+
+def test_order_argument_and_points_by_rank(api):
+    rng = np.random.default_rng(0)
+    P = rng.standard_normal((200, 3)).astype(np.float32)
+    order = rng.permutation(200).astype(np.int32)
+    a = api.Cloud.build(P, order)
+    b = api.Cloud.build(P[order])
+    assert a.lists() == b.lists()
+    assert np.array_equal(a.points_by_rank(), P[order])
+
+
+def test_tiny_clouds(api):
+    for P in ([[0, 0, 0]], [[0, 0, 0], [1, 0, 0]], [[0, 0, 0], [2, 0, 0], [1, 0, 0]],
+              [[0, 0, 0], [1, 0, 0], [2, 0, 0]], [[0, 0, 0], [1, 0, 0], [0, 1, 0]]):
+        P = np.array(P, np.float32)
+        assert api.Cloud.build(P).lists() == S.successor_lists(P)
+
+
+def test_errors(api):
+    from paper_2605_02224_amd._lib import MknnError, EDUPLICATE, ENONFINITE, EUNSUPPORTED, EINVAL
+    rng = np.random.default_rng(0)
+    P = rng.standard_normal((50, 3)).astype(np.float32)
+    Q = P.copy()
+    Q[30] = Q[7]
+    with pytest.raises(MknnError) as e:
+        api.Cloud.build(Q)
+    assert e.value.status == EDUPLICATE
+    Q = P.copy()
+    Q[3, 1] = np.nan
+    with pytest.raises(MknnError) as e:
+        api.Cloud.build(Q)
+    assert e.value.status == ENONFINITE
+    Q = P.copy()
+    Q[:4, 2] = 0.0     # first four ranks coplanar
+    with pytest.raises(MknnError) as e:
+        api.Cloud.build(Q)
+    assert e.value.status == EUNSUPPORTED
+    with pytest.raises(MknnError) as e:
+        api.Cloud.build(P, np.zeros(50, np.int32))
+    assert e.value.status == EINVAL
