@@ -64,6 +64,9 @@ def main() -> int:
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the context measurements")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -96,12 +99,14 @@ def main() -> int:
 
     # algorithmic bytes per query: 16 B per list entry examined, 8 B per list opened,
     # 12 B query, 8 B per output neighbour (rank + distance)
-    ce, cn = cl.knn_counts(q, k)
+    ce, cn, ci = cl.knn_counts(q, k, inserts=True)
     torch.cuda.synchronize()
     E = ce.double().mean().item()
     L = cn.double().mean().item()
+    INS = ci.double().mean().item()
     bytes_per_q = 16.0 * E + 8.0 * L + 12.0 + 8.0 * k
-    log(f"per query: {E:.1f} entries, {L:.2f} lists -> {bytes_per_q:.0f} algorithmic bytes")
+    log(f"per query: {E:.1f} entries, {L:.2f} lists, {INS:.1f} inserts -> "
+        f"{bytes_per_q:.0f} algorithmic bytes")
 
     for _ in range(args.warmup):
         cl.knn(q, k, out=(idx, dist))
@@ -129,8 +134,11 @@ def main() -> int:
     # context numbers (not the headline): k=1 and the on-surface query set
     extras = {"build_s": round(build_s, 2), "device_bytes": cl.device_bytes,
               "entries_per_query": round(E, 2), "lists_per_query": round(L, 3),
+              "inserts_per_query": round(INS, 2),
               "kernel_ms": round(kern_ms, 4)}
-    for name, qq, kk in (("volume_k1", q, 1), ("surface_k16", qb, 16), ("surface_k1", qb, 1)):
+    extra_runs = () if args.no_extras else (("volume_k1", q, 1), ("surface_k16", qb, 16),
+                                            ("surface_k1", qb, 1))
+    for name, qq, kk in extra_runs:
         i2 = torch.empty((nq, kk), dtype=torch.int32, device="cuda")
         d2 = torch.empty((nq, kk), dtype=torch.float32, device="cuda")
         for _ in range(2):
@@ -143,6 +151,14 @@ def main() -> int:
         torch.cuda.synchronize()
         extras[name + "_qps"] = round(nq * reps / (time.perf_counter() - t0), 1)
     log(f"extras: {extras}")
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 1 GiB read + 1 GiB written")
 
     cpu = None
     if not args.no_cpu_baseline:

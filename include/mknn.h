@@ -126,11 +126,14 @@ mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, cons
  * Work counters (diagnostics for the memory roofline).
  *
  * mknn_knn_counts: runs the same query path as mknn_knn and writes, per query, the number of
- * list entries examined E and of lists opened L (int32 [nq] each, device).  The final list
- * of the descent, which Alg. 2's first iteration would scan again, is counted once.
+ * list entries examined E and of lists opened L (int32 [nq] each, device), counted as the
+ * sequential Alg. 1 + Alg. 2 would: descent scans stop at the jump entry, and the final
+ * list of the descent, which Alg. 2's first iteration would scan again, is counted once.
+ * d_inserts (optional, may be NULL): candidates actually inserted into N per query.
  */
 mknn_status mknn_knn_counts(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
-                            int32_t m, int32_t *d_entries, int32_t *d_lists, void *stream);
+                            int32_t m, int32_t *d_entries, int32_t *d_lists,
+                            int32_t *d_inserts, void *stream);
 
 /* ---------------------------------------------------------------------------------------
  * Kernel timing (diagnostics for the memory roofline).

@@ -28,7 +28,7 @@ SIGNATURES = {
     "mknn_device_bytes": (_I64, [_P]),
     "mknn_knn": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P]),
     "mknn_knn_var": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P]),
-    "mknn_knn_counts": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P]),
+    "mknn_knn_counts": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P, _P]),
     "mknn_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "mknn_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "mknn_free": (None, [_P]),

@@ -126,14 +126,16 @@ class Cloud:
                                       kmax, _ptr(idx), _ptr(dist), _stream(stream)))
         return idx, dist, row_off
 
-    def knn_counts(self, q, k: int, m: Optional[int] = None, stream=None):
-        """Per-query work: (entries examined E, lists opened L) as int32 tensors."""
+    def knn_counts(self, q, k: int, m: Optional[int] = None, stream=None,
+                   inserts: bool = False):
+        """Per-query work: (entries examined E, lists opened L[, inserts]) as int32 tensors."""
         import torch
         q = q.contiguous()
         nq = q.shape[0]
         m = self.n if m is None else int(m)
         ce = torch.empty(nq, dtype=torch.int32, device=q.device)
         cl = torch.empty(nq, dtype=torch.int32, device=q.device)
+        ci = torch.empty(nq, dtype=torch.int32, device=q.device) if inserts else None
         check(_lib.lib().mknn_knn_counts(self._h, _ptr(q), nq, int(k), m, _ptr(ce), _ptr(cl),
-                                         _stream(stream)))
-        return ce, cl
+                                         _ptr(ci), _stream(stream)))
+        return (ce, cl, ci) if inserts else (ce, cl)

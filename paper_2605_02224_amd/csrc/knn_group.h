@@ -1,0 +1,274 @@
+// Group-per-query variant of the query kernel: 16 lanes (one DPP row) serve one query, four
+// queries per 64-wide wavefront.
+//
+// Why: a list averages ~15 entries.  With 16 lanes a whole list arrives in one coalesced
+// 256-byte load, all its distances are computed in parallel, and the descent's "first entry
+// closer than the current site" (Alg. 1) is the lowest set bit of a ballot -- one memory
+// round trip per list instead of one per entry, and no divergence between entries of a
+// list.  The candidate list N (Alg. 2) is spread across the row: lane l holds slots
+// l, 16 + l, 32 + l, 48 + l (S slots per lane, k <= 16 S).  Inserting a candidate is a
+// row-wide compare, a population count for its position and a one-slot shift through the
+// row done with DPP row moves; only candidates that beat the current k-th key are inserted.
+//
+// Descent and seeding (Alg. 1): when a chunk of L_cur holds an entry closer than the current
+// site, only that transition site is offered to N and the walk jumps; a chunk without such
+// an entry belongs to the final list of the descent (or to a long list that is about to
+// jump later) and all its entries are offered -- the final list doubles as Alg. 2's first
+// iteration.  Offering extra true sites to N never changes the result.
+//
+// Every branch a cross-lane operation depends on is uniform across the 16 lanes of a row.
+#pragma once
+#include "knn_kernels.h"
+
+namespace mknn {
+
+__device__ __forceinline__ uint32_t row_bits(uint64_t ballot, int g) {
+  return (uint32_t)(ballot >> (16 * g)) & 0xffffu;
+}
+
+__device__ __forceinline__ bool key_less(double da, int32_t ra, double db, int32_t rb) {
+  return da < db || (da == db && ra < rb);
+}
+
+// DPP row moves (within each row of 16 lanes):
+//   row_shr:1        lane l reads lane l-1 (lane 0 keeps `old`)
+//   row_newbcast:15  every lane reads lane 15 of its row
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowBcast15 = 0x15F;
+
+template <int CTRL>
+__device__ __forceinline__ int32_t dpp_i32(int32_t old, int32_t x) {
+  return __builtin_amdgcn_update_dpp(old, x, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double old, double x) {
+  const int64_t o = __double_as_longlong(old), v = __double_as_longlong(x);
+  const int32_t lo = dpp_i32<CTRL>((int32_t)o, (int32_t)v);
+  const int32_t hi = dpp_i32<CTRL>((int32_t)(o >> 32), (int32_t)(v >> 32));
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+template <int S, bool EXACTK>
+struct RowTopK {
+  double d[S];
+  int32_t r[S];
+  double thr_d;    // key of slot k-1 (uniform in the row)
+  int32_t thr_r;
+
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      d[s] = INFINITY;
+      r[s] = kEmpty;
+    }
+    thr_d = INFINITY;
+    thr_r = kEmpty;
+  }
+
+  // slot j (row-uniform) broadcast to the row
+  __device__ __forceinline__ void slot(int j, double &od, int32_t &orr) const {
+    const int s = j >> 4, src = j & 15;
+    double vd = d[0];
+    int32_t vr = r[0];
+#pragma unroll
+    for (int t = 1; t < S; ++t) {
+      vd = (t == s) ? d[t] : vd;
+      vr = (t == s) ? r[t] : vr;
+    }
+    od = __shfl(vd, src, 16);
+    orr = __shfl(vr, src, 16);
+  }
+
+  // Insert the row-uniform candidate (cd, cr) unless already present.  Only called for a
+  // candidate that beats the current k-th key.  Returns 1 if inserted.
+  __device__ __forceinline__ int insert(double cd, int32_t cr, int l, int g, int k) {
+    bool has = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s) has |= (r[s] == cr);
+    if (row_bits(__ballot(has), g)) return 0;
+    int pos = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      pos += __popc(row_bits(__ballot(key_less(d[s], r[s], cd, cr)), g));
+    // slot 16 s + l takes slot 16 s + l - 1 when it lies after the insertion point
+    double pd[S];
+    int32_t pr[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      pd[s] = dpp_f64<kDppRowShr1>(d[s], d[s]);
+      pr[s] = dpp_i32<kDppRowShr1>(r[s], r[s]);
+      if (s > 0) {
+        const double wd = dpp_f64<kDppRowBcast15>(d[s - 1], d[s - 1]);
+        const int32_t wr = dpp_i32<kDppRowBcast15>(r[s - 1], r[s - 1]);
+        pd[s] = (l == 0) ? wd : pd[s];
+        pr[s] = (l == 0) ? wr : pr[s];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int j = 16 * s + l;
+      d[s] = j > pos ? pd[s] : (j == pos ? cd : d[s]);
+      r[s] = j > pos ? pr[s] : (j == pos ? cr : r[s]);
+    }
+    if (EXACTK) {
+      thr_d = dpp_f64<kDppRowBcast15>(d[S - 1], d[S - 1]);
+      thr_r = dpp_i32<kDppRowBcast15>(r[S - 1], r[S - 1]);
+    } else {
+      slot(k - 1, thr_d, thr_r);
+    }
+    return 1;
+  }
+
+  // Offer every lane's (dd, rr) with `better` set; updates the threshold as it goes.
+  __device__ __forceinline__ int insert_all(bool better, double dd, int32_t rr, int l, int g,
+                                            int k) {
+    int ins = 0;
+    uint32_t mask = row_bits(__ballot(better), g);
+    while (mask) {
+      const int j = __ffs(mask) - 1;
+      const double cd = __shfl(dd, j, 16);
+      const int32_t cr = __shfl(rr, j, 16);
+      ins += insert(cd, cr, l, g, k);
+      better = better && l != j && key_less(dd, rr, thr_d, thr_r);
+      mask = row_bits(__ballot(better), g);
+    }
+    return ins;
+  }
+};
+
+struct ScanState {
+  int32_t nent = 0, nins = 0;
+};
+
+// Scan one list chunk by chunk.  DESCENT: stop at the first entry strictly closer than the
+// current site and jump to it.  Returns true if the descent jumped.
+template <int S, bool EXACTK, bool DESCENT, bool COUNT>
+__device__ __forceinline__ bool scan_list(const QueryArgs &a, RowTopK<S, EXACTK> &N,
+                                          uint64_t dsc, double qx, double qy, double qz,
+                                          int32_t m, int k, int l, int g, int32_t &cur,
+                                          double &dcur, ScanState &cs) {
+  const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
+  for (uint32_t base = 0; base < len; base += 16) {
+    const uint32_t e = base + (uint32_t)l;
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (e < len) c = a.ent[st + e];
+    const int32_t r = __float_as_int(c.w);
+    const bool valid = e < len && r < m;
+    double dd = INFINITY;
+    if (valid) {
+      const double dx = qx - (double)c.x, dy = qy - (double)c.y, dz = qz - (double)c.z;
+      dd = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    }
+    const uint32_t vmask = row_bits(__ballot(valid), g);
+    if (DESCENT) {
+      const uint32_t jm = row_bits(__ballot(valid && dd < dcur), g);
+      if (jm) {
+        const int j = __ffs(jm) - 1;
+        if (COUNT) cs.nent += j + 1;
+        dcur = __shfl(dd, j, 16);
+        cur = __shfl(r, j, 16);
+        // the transition site joins N (Alg. 1); entries before it were not closer
+        if (key_less(dcur, cur, N.thr_d, N.thr_r)) {
+          const int ins = N.insert(dcur, cur, l, g, k);
+          if (COUNT) cs.nins += ins;
+        }
+        return true;
+      }
+    }
+    if (COUNT) cs.nent += __popc(vmask);
+    const int ins = N.insert_all(valid && key_less(dd, r, N.thr_d, N.thr_r), dd, r, l, g, k);
+    if (COUNT) cs.nins += ins;
+    if (vmask != 0xffffu) break;   // end of the list or of the prefix
+  }
+  return false;
+}
+
+template <int S, bool EXACTK, bool COUNT>
+__global__ __launch_bounds__(256) void knn_group_kernel(QueryArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int l = lane & 15, g = lane >> 4;
+  const int64_t wave =
+      ((int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t s = wave * 4 + g;
+  if (s >= a.nq) return;            // whole rows leave together
+  double qx, qy, qz;
+  int64_t qi;
+  if (a.qs) {
+    const float4 v = a.qs[s];
+    qx = v.x;
+    qy = v.y;
+    qz = v.z;
+    qi = __float_as_int(v.w);
+  } else {
+    qi = s;
+    qx = a.q[3 * s];
+    qy = a.q[3 * s + 1];
+    qz = a.q[3 * s + 2];
+  }
+  const int k = a.kq ? a.kq[qi] : a.k;
+  int64_t mm = a.mq ? (int64_t)a.mq[qi] : (int64_t)a.m;
+  if (mm > a.n) mm = a.n;
+  const int32_t m = (int32_t)mm;
+  const int64_t row = a.row_off ? a.row_off[qi] : qi * (int64_t)a.k;
+  if (k < 1 || k > 16 * S || m < 1) return;
+
+  RowTopK<S, EXACTK> N;
+  N.init();
+  ScanState cs;
+  int32_t nlist = 0;
+  if (a.head < m) {
+    // ---- Alg. 1: descent from the head
+    int32_t cur = a.head;
+    double dcur;
+    {
+      const double dx = qx - (double)a.hx, dy = qy - (double)a.hy, dz = qz - (double)a.hz;
+      dcur = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    }
+    if (l == 0) {
+      N.d[0] = dcur;
+      N.r[0] = cur;
+    }
+    if (k == 1) {
+      N.thr_d = dcur;
+      N.thr_r = cur;
+    }
+    for (;;) {
+      if (COUNT) ++nlist;
+      if (!scan_list<S, EXACTK, true, COUNT>(a, N, a.lst[cur], qx, qy, qz, m, k, l, g, cur,
+                                             dcur, cs))
+        break;
+    }
+    // ---- Alg. 2: expand the lists of the confirmed neighbours N[2..k-1] (1-based)
+    for (int i = 1; i < k - 1; ++i) {
+      double pd;
+      int32_t pr;
+      N.slot(i, pd, pr);
+      if (pr == kEmpty) break;
+      if (COUNT) ++nlist;
+      int32_t dummy_c = 0;
+      double dummy_d = 0.0;
+      scan_list<S, EXACTK, false, COUNT>(a, N, a.lst[pr], qx, qy, qz, m, k, l, g, dummy_c,
+                                         dummy_d, cs);
+    }
+  }
+  if (COUNT) {
+    if (l == 0) {
+      a.cnt_entries[qi] = cs.nent;
+      a.cnt_lists[qi] = nlist;
+      if (a.cnt_inserts) a.cnt_inserts[qi] = cs.nins;
+    }
+    return;
+  }
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    const int j = 16 * t + l;
+    if (j < k) {
+      const bool empty = N.r[t] == kEmpty;
+      a.out_idx[row + j] = empty ? -1 : N.r[t];
+      a.out_dist[row + j] = empty ? INFINITY : (float)sqrt(N.d[t]);
+    }
+  }
+}
+
+}  // namespace mknn

@@ -33,6 +33,7 @@ struct QueryArgs {
   int32_t *out_idx;
   float *out_dist;
   int32_t *cnt_entries, *cnt_lists;   // diagnostics (COUNT variant only)
+  int32_t *cnt_inserts;               // optional diagnostic: candidates inserted into N
 };
 
 }  // namespace mknn

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -52,6 +53,10 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
   return x * q8 + (x < r8 ? x : r8) + i;
 }
 
+}  // namespace mknn
+#include "knn_group.h"
+namespace mknn {
+
 template <int K>
 struct TopK {
   double d[K];
@@ -85,12 +90,12 @@ struct TopK {
   }
 
   template <bool EXACTK>
-  __device__ __forceinline__ void insert(double dd, int32_t rr, int k) {
-    if (!(dd < thr_d || (dd == thr_d && rr < thr_r))) return;
+  __device__ __forceinline__ int insert(double dd, int32_t rr, int k) {
+    if (!(dd < thr_d || (dd == thr_d && rr < thr_r))) return 0;
     bool dup = false;
 #pragma unroll
     for (int j = 0; j < K; ++j) dup |= (r[j] == rr);
-    if (dup) return;
+    if (dup) return 0;
     // replace the last slot, then bubble the candidate towards the front
     d[K - 1] = dd;
     r[K - 1] = rr;
@@ -118,6 +123,7 @@ struct TopK {
       thr_d = td;
       thr_r = tr;
     }
+    return 1;
   }
 };
 
@@ -149,13 +155,13 @@ __global__ __launch_bounds__(256) void knn_lane_kernel(QueryArgs a) {
 
   TopK<K> N;
   N.init();
-  int32_t nent = 0, nlist = 0;
+  int32_t nent = 0, nlist = 0, nins = 0;
 
   if (a.head < m) {
     // ---- Alg. 1: descent from the head, every examined entry inserted into N
     int32_t cur = a.head;
     double dcur = sq_dist(qx, qy, qz, make_float4(a.hx, a.hy, a.hz, 0.f));
-    N.template insert<EXACTK>(dcur, cur, k);
+    nins += N.template insert<EXACTK>(dcur, cur, k);
     for (;;) {
       const uint64_t dsc = a.lst[cur];
       const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
@@ -169,7 +175,7 @@ __global__ __launch_bounds__(256) void knn_lane_kernel(QueryArgs a) {
         if (r >= m) break;
         const double dd = sq_dist(qx, qy, qz, c);
         if (COUNT) ++nent;
-        N.template insert<EXACTK>(dd, r, k);
+        nins += N.template insert<EXACTK>(dd, r, k);
         if (dd < dcur) {
           cur = r;
           dcur = dd;
@@ -196,7 +202,7 @@ __global__ __launch_bounds__(256) void knn_lane_kernel(QueryArgs a) {
         const int32_t r = __float_as_int(c.w);
         if (r >= m) break;
         if (COUNT) ++nent;
-        N.template insert<EXACTK>(sq_dist(qx, qy, qz, c), r, k);
+        nins += N.template insert<EXACTK>(sq_dist(qx, qy, qz, c), r, k);
       }
     }
   }
@@ -204,6 +210,7 @@ __global__ __launch_bounds__(256) void knn_lane_kernel(QueryArgs a) {
   if (COUNT) {
     a.cnt_entries[qi] = nent;
     a.cnt_lists[qi] = nlist;
+    if (a.cnt_inserts) a.cnt_inserts[qi] = nins;
     return;
   }
 #pragma unroll
@@ -359,6 +366,43 @@ static hipError_t timing_mark(hipStream_t s, bool start) {
   return hipEventRecord(g_events[g_events_used++].second, s);
 }
 
+template <int S, bool EXACTK, bool COUNT>
+static hipError_t launch_group(const QueryArgs &a, hipStream_t s) {
+  const int threads = 256;   // 4 waves x 4 queries
+  const uint32_t blocks = (uint32_t)((a.nq + 15) / 16);
+  hipLaunchKernelGGL((knn_group_kernel<S, EXACTK, COUNT>), dim3(blocks), dim3(threads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <bool COUNT>
+static hipError_t dispatch_group(const QueryArgs &a, int kmax, bool exact, hipStream_t s) {
+#define MKNN_GCASE(SS)                                                                      \
+  if (kmax <= 16 * SS)                                                                     \
+    return (exact && kmax == 16 * SS) ? launch_group<SS, true, COUNT>(a, s)               \
+                                      : launch_group<SS, false, COUNT>(a, s);
+  MKNN_GCASE(1)
+  MKNN_GCASE(2)
+  MKNN_GCASE(3)
+  MKNN_GCASE(4)
+#undef MKNN_GCASE
+  return hipErrorInvalidValue;
+}
+
+// kernel family: 0 = automatic, 1 = one query per lane, 2 = 16 lanes per query
+static int g_family = 0;
+
+static int family_for(int kmax) {
+  if (g_family) return g_family;
+  static int env = -1;
+  if (env < 0) {
+    const char *v = getenv("MKNN_KERNEL");
+    env = (v && v[0] == 'l') ? 1 : (v && v[0] == 'g') ? 2 : 0;
+  }
+  if (env) return env;
+  (void)kmax;
+  return 2;
+}
+
 template <bool COUNT>
 static hipError_t dispatch_lane(const QueryArgs &a, int kmax, bool exact, hipStream_t s) {
 #define MKNN_CASE(KK)                                                                       \
@@ -423,8 +467,8 @@ static mknn_status prepare_queries(const mknn_cloud *c, const float *d_q, int64_
 static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
                              int32_t m, const int32_t *d_k, const int32_t *d_m,
                              const int64_t *d_row_off, int32_t kmax, int32_t *d_idx,
-                             float *d_dist, int32_t *d_ce, int32_t *d_cl, hipStream_t s,
-                             const char *who) {
+                             float *d_dist, int32_t *d_ce, int32_t *d_cl, int32_t *d_ci,
+                             hipStream_t s, const char *who) {
   QueryArgs a;
   fill_cloud_args(c, &a);
   a.q = d_q;
@@ -438,6 +482,7 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
   a.out_dist = d_dist;
   a.cnt_entries = d_ce;
   a.cnt_lists = d_cl;
+  a.cnt_inserts = d_ci;
   void *scratch = nullptr;
   float4 *qs = nullptr;
   mknn_status st = prepare_queries(c, d_q, nq, s, &qs, &scratch);
@@ -446,7 +491,9 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
   const bool exact = (d_k == nullptr);
   hipError_t e = timing_mark(s, true);
   if (e == hipSuccess)
-    e = d_ce ? dispatch_lane<true>(a, kmax, exact, s) : dispatch_lane<false>(a, kmax, exact, s);
+    e = family_for(kmax) == 1
+            ? (d_ce ? dispatch_lane<true>(a, kmax, exact, s) : dispatch_lane<false>(a, kmax, exact, s))
+            : (d_ce ? dispatch_group<true>(a, kmax, exact, s) : dispatch_group<false>(a, kmax, exact, s));
   if (e == hipSuccess) e = timing_mark(s, false);
   if (scratch) (void)hipFreeAsync(scratch, s);
   if (e != hipSuccess)
@@ -540,7 +587,7 @@ mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t 
   if (nq == 0) return MKNN_OK;
   if (!d_q || !d_idx || !d_dist) return set_error(MKNN_EINVAL, "mknn_knn: NULL buffer");
   return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, d_idx, d_dist, nullptr,
-                   nullptr, (hipStream_t)stream, "mknn_knn");
+                   nullptr, nullptr, (hipStream_t)stream, "mknn_knn");
 }
 
 mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, const int32_t *d_k,
@@ -556,11 +603,12 @@ mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, cons
   if (!d_q || !d_k || !d_m || !d_row_off || !d_idx || !d_dist)
     return set_error(MKNN_EINVAL, "mknn_knn_var: NULL buffer");
   return run_query(c, d_q, nq, 0, 0, d_k, d_m, d_row_off, kmax, d_idx, d_dist, nullptr, nullptr,
-                   (hipStream_t)stream, "mknn_knn_var");
+                   nullptr, (hipStream_t)stream, "mknn_knn_var");
 }
 
 mknn_status mknn_knn_counts(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
-                            int32_t m, int32_t *d_entries, int32_t *d_lists, void *stream) {
+                            int32_t m, int32_t *d_entries, int32_t *d_lists, int32_t *d_inserts,
+                            void *stream) {
   clear_error();
   if (k > MKNN_KMAX) return set_error(MKNN_EUNSUPPORTED, "mknn_knn_counts: k above MKNN_KMAX");
   if (k < 1) return set_error(MKNN_EINVAL, "mknn_knn_counts: k must be >= 1");
@@ -571,7 +619,7 @@ mknn_status mknn_knn_counts(const mknn_cloud *c, const float *d_q, int64_t nq, i
   if (nq == 0) return MKNN_OK;
   if (!d_q || !d_entries || !d_lists) return set_error(MKNN_EINVAL, "mknn_knn_counts: NULL buffer");
   return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, nullptr, nullptr, d_entries,
-                   d_lists, (hipStream_t)stream, "mknn_knn_counts");
+                   d_lists, d_inserts, (hipStream_t)stream, "mknn_knn_counts");
 }
 
 mknn_status mknn_timing_enable(int enable) {
