@@ -26,8 +26,9 @@ __device__ __forceinline__ uint32_t row_bits(uint64_t ballot, int g) {
   return (uint32_t)(ballot >> (16 * g)) & 0xffffu;
 }
 
+// (da, ra) < (db, rb) lexicographically; bitwise operators keep it free of branches
 __device__ __forceinline__ bool key_less(double da, int32_t ra, double db, int32_t rb) {
-  return da < db || (da == db && ra < rb);
+  return (da < db) | ((da == db) & (ra < rb));
 }
 
 // DPP row moves (within each row of 16 lanes):

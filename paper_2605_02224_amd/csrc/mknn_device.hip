@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
@@ -366,11 +367,22 @@ static hipError_t timing_mark(hipStream_t s, bool start) {
   return hipEventRecord(g_events[g_events_used++].second, s);
 }
 
+// Optional dynamic LDS per workgroup, used only to cap occupancy in tuning experiments.
+static size_t lds_pad() {
+  static long v = -1;
+  if (v < 0) {
+    const char *e = getenv("MKNN_LDS_PAD");
+    v = e ? atol(e) : 0;
+  }
+  return (size_t)v;
+}
+
 template <int S, bool EXACTK, bool COUNT>
 static hipError_t launch_group(const QueryArgs &a, hipStream_t s) {
   const int threads = 256;   // 4 waves x 4 queries
   const uint32_t blocks = (uint32_t)((a.nq + 15) / 16);
-  hipLaunchKernelGGL((knn_group_kernel<S, EXACTK, COUNT>), dim3(blocks), dim3(threads), 0, s, a);
+  hipLaunchKernelGGL((knn_group_kernel<S, EXACTK, COUNT>), dim3(blocks), dim3(threads), lds_pad(),
+                     s, a);
   return hipGetLastError();
 }
 
@@ -386,6 +398,18 @@ static hipError_t dispatch_group(const QueryArgs &a, int kmax, bool exact, hipSt
   MKNN_GCASE(4)
 #undef MKNN_GCASE
   return hipErrorInvalidValue;
+}
+
+[[maybe_unused]] static int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+  }
+  return cus;
 }
 
 // kernel family: 0 = automatic, 1 = one query per lane, 2 = 16 lanes per query
@@ -441,7 +465,8 @@ static void fill_cloud_args(const mknn_cloud *c, QueryArgs *a) {
   a->n = c->n;
 }
 
-// Sorts the queries (when the batch is large enough) into *qs_out (stream-ordered scratch).
+// Morton bucketing of the queries into stream-ordered scratch, for batches large enough
+// to pay for it.
 static mknn_status prepare_queries(const mknn_cloud *c, const float *d_q, int64_t nq,
                                    hipStream_t s, float4 **qs_out, void **scratch) {
   *qs_out = nullptr;
@@ -489,11 +514,14 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
   if (st != MKNN_OK) return st;
   a.qs = qs;
   const bool exact = (d_k == nullptr);
+  const int fam = family_for(kmax);
   hipError_t e = timing_mark(s, true);
-  if (e == hipSuccess)
-    e = family_for(kmax) == 1
-            ? (d_ce ? dispatch_lane<true>(a, kmax, exact, s) : dispatch_lane<false>(a, kmax, exact, s))
-            : (d_ce ? dispatch_group<true>(a, kmax, exact, s) : dispatch_group<false>(a, kmax, exact, s));
+  if (e == hipSuccess) {
+    if (fam == 1)
+      e = d_ce ? dispatch_lane<true>(a, kmax, exact, s) : dispatch_lane<false>(a, kmax, exact, s);
+    else
+      e = d_ce ? dispatch_group<true>(a, kmax, exact, s) : dispatch_group<false>(a, kmax, exact, s);
+  }
   if (e == hipSuccess) e = timing_mark(s, false);
   if (scratch) (void)hipFreeAsync(scratch, s);
   if (e != hipSuccess)
@@ -556,10 +584,12 @@ mknn_status mknn_upload(mknn_cloud *c, void *stream) {
       std::memcpy(&v.w, &big, 4);
       ent[cur + p] = v;
     }
+
     free_device(c);
     c->device = dev;
     HIP_TRY(hipMalloc(&c->d_ent, sizeof(float4) * ent.size()), "mknn_upload: hipMalloc entries");
     HIP_TRY(hipMalloc((void **)&c->d_lst, sizeof(uint64_t) * lst.size()), "mknn_upload: hipMalloc lists");
+
     HIP_TRY(hipMemcpyAsync(c->d_ent, ent.data(), sizeof(float4) * ent.size(), hipMemcpyHostToDevice, s),
             "mknn_upload: copy entries");
     HIP_TRY(hipMemcpyAsync(c->d_lst, lst.data(), sizeof(uint64_t) * lst.size(), hipMemcpyHostToDevice, s),
