@@ -123,6 +123,56 @@ mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, cons
                          int32_t *d_idx, float *d_dist, void *stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Batched form: many clouds with their own query sets, k and prefixes in one persistent
+ * launch per register class (k <= 16, 32, 48, 64).  Same per-query semantics as mknn_knn
+ * (Alg. 1 + Alg. 2, Sec. 4.2).
+ *
+ * Each request is cut into tiles of `tile_queries` queries.  Requests are assigned to 8
+ * per-XCD queues (largest estimated cost first, all tiles of a cloud on one queue).
+ * Persistent workgroups claim tiles from their own queue with an atomic counter and steal
+ * from the other queues when it runs dry.  The queries of all requests are bucketed
+ * together by (request, Morton code) unless MKNN_BATCH_NO_SORT is set.
+ */
+typedef struct {
+  const mknn_cloud *cloud;   /* an uploaded cloud */
+  const float *d_q;          /* device float32 [nq][3] */
+  int64_t nq;                /* >= 0 */
+  int32_t k;                 /* 1..MKNN_KMAX */
+  int32_t m;                 /* prefix size in [1, n]; 0 means n */
+  int32_t *d_idx;            /* device int32 [nq][k], rows as in mknn_knn */
+  float *d_dist;             /* device float32 [nq][k] */
+} mknn_request;
+
+typedef struct mknn_batch_plan mknn_batch_plan; /* opaque, owned by the library */
+
+#define MKNN_BATCH_NO_SORT 1   /* skip the Morton bucketing of the queries */
+#define MKNN_BATCH_NO_GRAPH 2  /* launch eagerly instead of replaying a captured hipGraph */
+
+/* mknn_batch_plan_create: device buffers for up to max_requests requests and max_queries
+ * queries in total (max_queries < 2^31), plus pinned host staging.  Unless
+ * MKNN_BATCH_NO_GRAPH is set, the first run captures the whole sequence (descriptor copy,
+ * counter clear, query bucketing, the four class launches) into a hipGraph.  Later runs
+ * update the descriptors in the pinned staging area and replay the graph: every kernel reads
+ * its sizes from device memory and uses a fixed grid.  A plan belongs to the device that was
+ * current at creation.  Errors: EINVAL, ENOMEM, EHIP. */
+mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries,
+                                   int32_t tile_queries, int32_t flags, mknn_batch_plan **out);
+
+/* mknn_batch_plan_run: enqueue one batch on `stream`.  The request array (host) is read
+ * before returning.  Outputs are written asynchronously.  A run waits for the previous
+ * run of the same plan to finish using the staging area.  Errors: EINVAL (bad request or
+ * over capacity), EUNSUPPORTED (k > MKNN_KMAX), EHIP.  Requests with nq = 0 are skipped. */
+mknn_status mknn_batch_plan_run(mknn_batch_plan *plan, const mknn_request *reqs, int32_t nreq,
+                                void *stream);
+
+/* Release a plan (waits for its last run). */
+void mknn_batch_plan_destroy(mknn_batch_plan *plan);
+
+/* Convenience form: runs the batch on a plan the library keeps per process and grows on
+ * demand.  Not thread-safe. */
+mknn_status mknn_batch_knn(const mknn_request *reqs, int32_t nreq, void *stream);
+
+/* ---------------------------------------------------------------------------------------
  * Work counters (diagnostics for the memory roofline).
  *
  * mknn_knn_counts: runs the same query path as mknn_knn and writes, per query, the number of

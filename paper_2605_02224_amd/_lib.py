@@ -36,6 +36,23 @@ SIGNATURES = {
     "mknn_version": (ctypes.c_char_p, []),
 }
 
+class Request(ctypes.Structure):
+    """mknn_request of mknn.h"""
+    _fields_ = [("cloud", ctypes.c_void_p), ("d_q", ctypes.c_void_p), ("nq", ctypes.c_int64),
+                ("k", ctypes.c_int32), ("m", ctypes.c_int32), ("d_idx", ctypes.c_void_p),
+                ("d_dist", ctypes.c_void_p)]
+
+
+BATCH_NO_SORT = 1
+BATCH_NO_GRAPH = 2
+
+SIGNATURES.update({
+    "mknn_batch_plan_create": (ctypes.c_int, [_I64, _I64, _I32, _I32, _PP]),
+    "mknn_batch_plan_run": (ctypes.c_int, [_P, ctypes.POINTER(Request), _I32, _P]),
+    "mknn_batch_plan_destroy": (None, [_P]),
+    "mknn_batch_knn": (ctypes.c_int, [ctypes.POINTER(Request), _I32, _P]),
+})
+
 _lib = None
 
 

@@ -139,3 +139,59 @@ class Cloud:
         check(_lib.lib().mknn_knn_counts(self._h, _ptr(q), nq, int(k), m, _ptr(ce), _ptr(cl),
                                          _ptr(ci), _stream(stream)))
         return (ce, cl, ci) if inserts else (ce, cl)
+
+
+def _requests(items):
+    """items: sequence of (cloud, q, k, m, idx, dist) -> ctypes array of mknn_request."""
+    arr = (_lib.Request * max(1, len(items)))()
+    for i, (cloud, q, k, m, idx, dist) in enumerate(items):
+        arr[i].cloud = cloud.handle.value
+        arr[i].d_q = q.data_ptr() if q.numel() else None
+        arr[i].nq = q.shape[0]
+        arr[i].k = int(k)
+        arr[i].m = 0 if m is None else int(m)
+        arr[i].d_idx = idx.data_ptr() if idx.numel() else None
+        arr[i].d_dist = dist.data_ptr() if dist.numel() else None
+    return arr
+
+
+def alloc_outputs(items):
+    """items: (cloud, q, k, m) -> same plus freshly allocated (idx, dist) device tensors."""
+    import torch
+    out = []
+    for cloud, q, k, m in items:
+        idx = torch.empty((q.shape[0], k), dtype=torch.int32, device=q.device)
+        dist = torch.empty((q.shape[0], k), dtype=torch.float32, device=q.device)
+        out.append((cloud, q, k, m, idx, dist))
+    return out
+
+
+class BatchPlan:
+    """Device buffers + captured hipGraph for batches of many clouds (mknn_batch_plan_*)."""
+
+    def __init__(self, max_requests: int, max_queries: int, tile_queries: int = 1024,
+                 sort: bool = True, graph: bool = True):
+        flags = (0 if sort else _lib.BATCH_NO_SORT) | (0 if graph else _lib.BATCH_NO_GRAPH)
+        h = ctypes.c_void_p()
+        check(_lib.lib().mknn_batch_plan_create(int(max_requests), int(max_queries),
+                                                int(tile_queries), flags, ctypes.byref(h)))
+        self._h = h
+
+    def run(self, items, stream=None):
+        """items: sequence of (cloud, q, k, m, idx, dist); enqueues the batch."""
+        self._keep = _requests(items)
+        check(_lib.lib().mknn_batch_plan_run(self._h, self._keep, len(items), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().mknn_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def batch_knn(items, stream=None):
+    """Convenience form of the batched call (library-owned plan)."""
+    arr = _requests(items)
+    check(_lib.lib().mknn_batch_knn(arr, len(items), _stream(stream)))

@@ -1,0 +1,103 @@
+// Helpers shared by the HIP translation units (plain queries and batched queries).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "cloud.h"
+#include "knn_kernels.h"
+
+namespace mknn {
+
+#define HIP_TRY(expr, what)                                                             \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return set_error(MKNN_EHIP, std::string(what) + ": " + hipGetErrorName(e_) + " (" + \
+                                      hipGetErrorString(e_) + ")");                     \
+  } while (0)
+
+// ---- Morton codes over a bounding box (query bucketing and list placement)
+struct BoxArgs {
+  float lo[3], scale[3];   // scale maps the box extent to [0, 1024)
+};
+
+__host__ __device__ __forceinline__ uint32_t spread3(uint32_t v) {   // 10 bits -> every 3rd bit
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// 30-bit Morton code of a point, clamped into the box
+__host__ __device__ __forceinline__ uint32_t morton30(float x, float y, float z,
+                                                      const BoxArgs &b) {
+  const float t[3] = {(x - b.lo[0]) * b.scale[0], (y - b.lo[1]) * b.scale[1],
+                      (z - b.lo[2]) * b.scale[2]};
+  uint32_t u[3];
+  for (int i = 0; i < 3; ++i) {
+    float v = t[i] < 0.f ? 0.f : (t[i] > 1023.f ? 1023.f : t[i]);
+    u[i] = (uint32_t)v;
+  }
+  return (spread3(u[0]) << 2) | (spread3(u[1]) << 1) | spread3(u[2]);
+}
+
+inline BoxArgs box_of(const mknn_cloud *c) {
+  BoxArgs b;
+  for (int k = 0; k < 3; ++k) {
+    float ext = c->hi[k] - c->lo[k];
+    b.lo[k] = c->lo[k];
+    b.scale[k] = ext > 0.f ? 1024.f / ext : 0.f;
+  }
+  return b;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fill_kernel(T *p, int64_t cnt, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---- host helpers
+inline int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+inline mknn_status check_uploaded(const mknn_cloud *c, const char *who) {
+  if (!c) return set_error(MKNN_EINVAL, std::string(who) + ": cloud is NULL");
+  if (!c->d_ent || c->dev_version != c->version)
+    return set_error(MKNN_EINVAL, std::string(who) + ": cloud is not uploaded (call mknn_upload)");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+    return set_error(MKNN_EINVAL, std::string(who) + ": cloud lives on another device");
+  return MKNN_OK;
+}
+
+inline void fill_cloud_args(const mknn_cloud *c, QueryArgs *a) {
+  std::memset(a, 0, sizeof(*a));
+  a->ent = (const float4 *)c->d_ent;
+  a->lst = c->d_lst;
+  a->head = c->head;
+  a->hx = c->xyz[3 * (int64_t)c->head];
+  a->hy = c->xyz[3 * (int64_t)c->head + 1];
+  a->hz = c->xyz[3 * (int64_t)c->head + 2];
+  a->n = c->n;
+}
+
+// Optional HIP-event timing of the main query kernels (defined in mknn_device.hip).
+hipError_t timing_mark(hipStream_t s, bool start);
+bool timing_enabled();
+
+}  // namespace mknn

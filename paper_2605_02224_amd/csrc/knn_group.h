@@ -185,14 +185,9 @@ __device__ __forceinline__ bool scan_list(const QueryArgs &a, RowTopK<S, EXACTK>
   return false;
 }
 
+// One query (sorted position s of request a) on one 16-lane row.  Row-uniform control.
 template <int S, bool EXACTK, bool COUNT>
-__global__ __launch_bounds__(256) void knn_group_kernel(QueryArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int l = lane & 15, g = lane >> 4;
-  const int64_t wave =
-      ((int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
-  const int64_t s = wave * 4 + g;
-  if (s >= a.nq) return;            // whole rows leave together
+__device__ __forceinline__ void group_query(const QueryArgs &a, int64_t s, int l, int g) {
   double qx, qy, qz;
   int64_t qi;
   if (a.qs) {
@@ -270,6 +265,18 @@ __global__ __launch_bounds__(256) void knn_group_kernel(QueryArgs a) {
       a.out_dist[row + j] = empty ? INFINITY : (float)sqrt(N.d[t]);
     }
   }
+}
+
+// Plain launch: one row per query, queries in (sorted) order, XCD-contiguous tiles.
+template <int S, bool EXACTK, bool COUNT>
+__global__ __launch_bounds__(256) void knn_group_kernel(QueryArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int l = lane & 15, g = lane >> 4;
+  const int64_t wave =
+      ((int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t s = wave * 4 + g;
+  if (s >= a.nq) return;            // whole rows leave together
+  group_query<S, EXACTK, COUNT>(a, s, l, g);
 }
 
 }  // namespace mknn

@@ -36,4 +36,20 @@ struct QueryArgs {
   int32_t *cnt_inserts;               // optional diagnostic: candidates inserted into N
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range
+// of tiles so Morton-adjacent queries share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
+  uint32_t x = b & 7u, i = b >> 3, q8 = nb >> 3, r8 = nb & 7u;
+  return x * q8 + (x < r8 ? x : r8) + i;
+}
+
+// Squared distance exactly as the brute-force definition: float64 from float32 inputs,
+// every operation rounded, no fused multiply-add.
+__device__ __forceinline__ double sq_dist(double qx, double qy, double qz, float4 c) {
+  const double dx = qx - (double)c.x;
+  const double dy = qy - (double)c.y;
+  const double dz = qz - (double)c.z;
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
 }  // namespace mknn

@@ -1,0 +1,471 @@
+// Batched form: many clouds, each with its own query set, k and prefix, answered by one
+// persistent launch per register-capacity class.
+//
+// Work decomposition.  Every request (cloud, queries, k, m) is cut into tiles of T queries.
+// Requests are placed on 8 queues -- one per XCD, workgroups are dispatched round-robin over
+// the XCDs so blockIdx % 8 names the XCD -- by a largest-processing-time-first rule on an
+// estimated cost (queries x (k + 8) x log2 n), keeping all tiles of a cloud on one queue so
+// its lists stay in that XCD's L2.  A persistent workgroup claims tiles from its own queue
+// with one atomic per tile and steals from the other queues when its own is empty; every
+// workgroup leaves once all 8 queues are exhausted.  Inside a tile the 16 rows of the
+// workgroup run the group-per-query walk (Alg. 1 + Alg. 2, knn_group.h) on the tile's
+// queries.
+//
+// Query preparation.  The queries of all requests are bucketed together by (request,
+// 12-bit Morton code in the request's cloud box) with one counting sort -- histogram, one
+// scan workgroup per request, scatter -- into one contiguous sorted array.
+//
+// Graph.  A plan owns device buffers sized for a capacity (requests, queries, tiles) and a
+// pinned host staging area.  All per-call data (descriptors, tiles, offsets) are written to
+// the staging area and copied to the device by the first node, and every kernel reads its
+// sizes from device memory with a fixed grid, so one captured hipGraph replays any batch
+// within the capacity.  Counters are cleared by a fill kernel, not by a memset node.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "device_common.h"
+#include "knn_group.h"
+
+namespace mknn {
+
+constexpr int kQueues = 8;
+constexpr int kClasses = 4;              // S = 1..4 slots per lane (k <= 16, 32, 48, 64)
+constexpr int kSegBits = 12;             // Morton bits per request in the batch sort
+constexpr int kSegBins = 1 << kSegBits;
+
+struct BatchTile {
+  int32_t req;
+  int32_t pad;
+  int64_t begin, end;       // sorted query positions within the request
+};
+
+struct BatchHeader {
+  int32_t nreq;
+  int32_t sorted;
+  int64_t total_q;
+  int32_t qbound[kClasses][kQueues + 1];   // tile index ranges per (class, queue)
+};
+
+// ---------------------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int32_t request_of(const int64_t *qoff, int32_t nreq, int64_t i) {
+  int32_t lo = 0, hi = nreq;   // qoff[lo] <= i < qoff[hi]
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (qoff[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void seg_hist_kernel(const BatchHeader *h, const QueryArgs *reqs,
+                                                       const int64_t *qoff, const BoxArgs *boxes,
+                                                       uint32_t *bins) {
+  if (!h->sorted) return;
+  const int64_t total = h->total_q;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = request_of(qoff, h->nreq, i);
+    const float *q = reqs[r].q + 3 * (i - qoff[r]);
+    const uint32_t bin = morton30(q[0], q[1], q[2], boxes[r]) >> (30 - kSegBits);
+    atomicAdd(&bins[(int64_t)r * kSegBins + bin], 1u);
+  }
+}
+
+// one workgroup per request: exclusive scan of its bins, offset by the request's start
+__global__ __launch_bounds__(1024) void seg_scan_kernel(const BatchHeader *h, const int64_t *qoff,
+                                                        uint32_t *bins) {
+  const int32_t r = blockIdx.x;
+  if (!h->sorted || r >= h->nreq) return;
+  constexpr int per = kSegBins / 1024;
+  __shared__ uint32_t part[1024];
+  uint32_t *b = bins + (int64_t)r * kSegBins;
+  const int t = threadIdx.x;
+  uint32_t local[per];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    local[i] = b[t * per + i];
+    sum += local[i];
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = (uint32_t)qoff[r] + part[t] - sum;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    b[t * per + i] = run;
+    run += local[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void seg_scatter_kernel(const BatchHeader *h,
+                                                          const QueryArgs *reqs,
+                                                          const int64_t *qoff,
+                                                          const BoxArgs *boxes, uint32_t *bins,
+                                                          float4 *qs) {
+  if (!h->sorted) return;
+  const int64_t total = h->total_q;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = request_of(qoff, h->nreq, i);
+    const int64_t local = i - qoff[r];
+    const float *q = reqs[r].q + 3 * local;
+    const uint32_t bin = morton30(q[0], q[1], q[2], boxes[r]) >> (30 - kSegBits);
+    const uint32_t pos = atomicAdd(&bins[(int64_t)r * kSegBins + bin], 1u);
+    qs[pos] = make_float4(q[0], q[1], q[2], __int_as_float((int32_t)local));
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void knn_batch_kernel(const BatchHeader *h,
+                                                        const QueryArgs *reqs,
+                                                        const BatchTile *tiles,
+                                                        uint32_t *counters, int cls) {
+  __shared__ int32_t s_tile;
+  const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+  const int home = blockIdx.x % kQueues;
+  int tried = 0;   // used by thread 0: queues found empty so far
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int32_t t = -1;
+      while (tried < kQueues) {
+        const int x = (home + tried) % kQueues;
+        const int32_t b0 = h->qbound[cls][x], b1 = h->qbound[cls][x + 1];
+        if (b0 < b1) {
+          const uint32_t v = atomicAdd(&counters[cls * kQueues + x], 1u);
+          if ((int64_t)b0 + v < (int64_t)b1) {
+            t = b0 + (int32_t)v;
+            break;
+          }
+        }
+        ++tried;
+      }
+      s_tile = t;
+    }
+    __syncthreads();
+    const int32_t t = s_tile;
+    __syncthreads();
+    if (t < 0) return;
+    const BatchTile tile = tiles[t];
+    const QueryArgs &a = reqs[tile.req];
+    for (int64_t s0 = tile.begin + 4 * w; s0 < tile.end; s0 += 16) {
+      const int64_t s = s0 + g;
+      if (s < tile.end) group_query<S, false, false>(a, s, l, g);
+    }
+  }
+}
+
+template <int S>
+static int resident_batch_blocks() {
+  static int nb = 0;
+  if (!nb) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void *>(&knn_batch_kernel<S>), 256, 0) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+  }
+  return nb;
+}
+
+}  // namespace mknn
+
+using namespace mknn;
+
+// ---------------------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------------------
+struct mknn_batch_plan {
+  int device = -1;
+  int64_t max_req = 0, max_q = 0, max_tiles = 0;
+  int32_t tile_q = 1024;
+  bool sort = true, use_graph = true;
+  // device: staging mirror | counters | bins | sorted queries
+  char *d_base = nullptr;
+  size_t off_hdr = 0, off_reqs = 0, off_tiles = 0, off_boxes = 0, off_qoff = 0, stage_bytes = 0;
+  uint32_t *d_counters = nullptr;
+  uint32_t *d_bins = nullptr;
+  float4 *d_qs = nullptr;
+  char *h_stage = nullptr;          // pinned
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  uint32_t grid_batch[kClasses] = {1, 1, 1, 1};
+  uint32_t grid_stream = 1;
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static void plan_release(mknn_batch_plan *p) {
+  if (p->pending && p->done) (void)hipEventSynchronize(p->done);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->done) (void)hipEventDestroy(p->done);
+  if (p->d_base) (void)hipFree(p->d_base);
+  if (p->h_stage) (void)hipHostFree(p->h_stage);
+  delete p;
+}
+
+// Enqueue the whole batch sequence on stream s (captured into the graph or run eagerly).
+static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s) {
+  const BatchHeader *hdr = (const BatchHeader *)(p->d_base + p->off_hdr);
+  const QueryArgs *reqs = (const QueryArgs *)(p->d_base + p->off_reqs);
+  const BatchTile *tiles = (const BatchTile *)(p->d_base + p->off_tiles);
+  const BoxArgs *boxes = (const BoxArgs *)(p->d_base + p->off_boxes);
+  const int64_t *qoff = (const int64_t *)(p->d_base + p->off_qoff);
+  hipError_t e = hipMemcpyAsync(p->d_base, p->h_stage, p->stage_bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(1), dim3(64), 0, s, p->d_counters,
+                     (int64_t)(kClasses * kQueues), 0u);
+  if (p->sort) {
+    const int64_t nb = p->max_req * kSegBins;
+    const uint32_t gb = (uint32_t)std::min<int64_t>(4096, (nb + 255) / 256);
+    hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(gb), dim3(256), 0, s, p->d_bins, nb, 0u);
+    const uint32_t gq = p->grid_stream;
+    hipLaunchKernelGGL(seg_hist_kernel, dim3(gq), dim3(256), 0, s, hdr, reqs, qoff, boxes,
+                       p->d_bins);
+    hipLaunchKernelGGL(seg_scan_kernel, dim3((uint32_t)p->max_req), dim3(1024), 0, s, hdr, qoff,
+                       p->d_bins);
+    hipLaunchKernelGGL(seg_scatter_kernel, dim3(gq), dim3(256), 0, s, hdr, reqs, qoff, boxes,
+                       p->d_bins, p->d_qs);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = timing_mark(s, true);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(knn_batch_kernel<1>, dim3(p->grid_batch[0]), dim3(256), 0, s, hdr, reqs,
+                     tiles, p->d_counters, 0);
+  hipLaunchKernelGGL(knn_batch_kernel<2>, dim3(p->grid_batch[1]), dim3(256), 0, s, hdr, reqs,
+                     tiles, p->d_counters, 1);
+  hipLaunchKernelGGL(knn_batch_kernel<3>, dim3(p->grid_batch[2]), dim3(256), 0, s, hdr, reqs,
+                     tiles, p->d_counters, 2);
+  hipLaunchKernelGGL(knn_batch_kernel<4>, dim3(p->grid_batch[3]), dim3(256), 0, s, hdr, reqs,
+                     tiles, p->d_counters, 3);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return timing_mark(s, false);
+}
+
+extern "C" {
+
+mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, int32_t tile_queries,
+                                   int32_t flags, mknn_batch_plan **out) {
+  clear_error();
+  if (!out) return set_error(MKNN_EINVAL, "mknn_batch_plan_create: out is NULL");
+  *out = nullptr;
+  if (max_requests < 1 || max_requests > (1 << 20) || max_queries < 1 ||
+      max_queries > (int64_t)0x7fffffff)
+    return set_error(MKNN_EINVAL, "mknn_batch_plan_create: capacity out of range");
+  if (tile_queries < 16 || tile_queries > (1 << 20))
+    return set_error(MKNN_EINVAL, "mknn_batch_plan_create: tile_queries out of range [16, 2^20]");
+  mknn_batch_plan *p = new (std::nothrow) mknn_batch_plan();
+  if (!p) return set_error(MKNN_ENOMEM, "mknn_batch_plan_create: out of host memory");
+  p->max_req = max_requests;
+  p->max_q = max_queries;
+  p->tile_q = tile_queries;
+  p->max_tiles = max_queries / tile_queries + max_requests + 1;
+  p->sort = !(flags & MKNN_BATCH_NO_SORT);
+  p->use_graph = !(flags & MKNN_BATCH_NO_GRAPH);
+  hipError_t e = hipGetDevice(&p->device);
+  size_t o = 0;
+  p->off_hdr = o;
+  o = align256(o + sizeof(BatchHeader));
+  p->off_reqs = o;
+  o = align256(o + sizeof(QueryArgs) * (size_t)p->max_req);
+  p->off_tiles = o;
+  o = align256(o + sizeof(BatchTile) * (size_t)p->max_tiles);
+  p->off_boxes = o;
+  o = align256(o + sizeof(BoxArgs) * (size_t)p->max_req);
+  p->off_qoff = o;
+  o = align256(o + sizeof(int64_t) * (size_t)(p->max_req + 1));
+  p->stage_bytes = o;
+  const size_t counters_at = o;
+  o = align256(o + sizeof(uint32_t) * kClasses * kQueues);
+  const size_t bins_at = o;
+  if (p->sort) o = align256(o + sizeof(uint32_t) * (size_t)p->max_req * kSegBins);
+  const size_t qs_at = o;
+  if (p->sort) o = align256(o + sizeof(float4) * (size_t)p->max_q);
+  if (e == hipSuccess) e = hipMalloc((void **)&p->d_base, o);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_stage, p->stage_bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+  if (e == hipSuccess && p->use_graph) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    const std::string msg = std::string("mknn_batch_plan_create: ") + hipGetErrorName(e);
+    plan_release(p);
+    return set_error(e == hipErrorOutOfMemory ? MKNN_ENOMEM : MKNN_EHIP, msg);
+  }
+  std::memset(p->h_stage, 0, p->stage_bytes);
+  const uint32_t cus = (uint32_t)device_cus();
+  p->grid_batch[0] = cus * resident_batch_blocks<1>();
+  p->grid_batch[1] = cus * resident_batch_blocks<2>();
+  p->grid_batch[2] = cus * resident_batch_blocks<3>();
+  p->grid_batch[3] = cus * resident_batch_blocks<4>();
+  p->grid_stream = cus * 8;
+  p->d_counters = (uint32_t *)(p->d_base + counters_at);
+  p->d_bins = p->sort ? (uint32_t *)(p->d_base + bins_at) : nullptr;
+  p->d_qs = p->sort ? (float4 *)(p->d_base + qs_at) : nullptr;
+  *out = p;
+  return MKNN_OK;
+}
+
+void mknn_batch_plan_destroy(mknn_batch_plan *p) {
+  if (p) plan_release(p);
+}
+
+mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
+                                void *stream) {
+  clear_error();
+  if (!p) return set_error(MKNN_EINVAL, "mknn_batch_plan_run: plan is NULL");
+  if (nreq < 0 || (nreq > 0 && !reqs))
+    return set_error(MKNN_EINVAL, "mknn_batch_plan_run: bad request array");
+  if (nreq > p->max_req)
+    return set_error(MKNN_EINVAL, "mknn_batch_plan_run: more requests than the plan holds");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "mknn_batch_plan_run: hipGetDevice");
+  if (dev != p->device) return set_error(MKNN_EINVAL, "mknn_batch_plan_run: plan on another device");
+  // ---- validate and describe every request
+  std::vector<int64_t> qoff((size_t)nreq + 1, 0);
+  std::vector<int> cls((size_t)nreq, 0);
+  for (int32_t r = 0; r < nreq; ++r) {
+    const mknn_request &q = reqs[r];
+    const std::string who = "mknn_batch_plan_run: request " + std::to_string(r);
+    mknn_status st = check_uploaded(q.cloud, who.c_str());
+    if (st != MKNN_OK) return st;
+    if (q.k > MKNN_KMAX) return set_error(MKNN_EUNSUPPORTED, who + ": k above MKNN_KMAX");
+    if (q.k < 1) return set_error(MKNN_EINVAL, who + ": k must be >= 1");
+    if (q.m < 0 || q.m > q.cloud->n) return set_error(MKNN_EINVAL, who + ": m out of [0, n]");
+    if (q.nq < 0) return set_error(MKNN_EINVAL, who + ": nq < 0");
+    if (q.nq > 0 && (!q.d_q || !q.d_idx || !q.d_dist))
+      return set_error(MKNN_EINVAL, who + ": NULL buffer");
+    qoff[r + 1] = qoff[r] + q.nq;
+    cls[r] = (q.k + 15) / 16 - 1;
+  }
+  if (qoff[nreq] > p->max_q)
+    return set_error(MKNN_EINVAL, "mknn_batch_plan_run: more queries than the plan holds");
+  // ---- tiles: requests on queues by largest-processing-time first, per class
+  std::vector<double> cost((size_t)nreq);
+  for (int32_t r = 0; r < nreq; ++r)
+    cost[r] = (double)reqs[r].nq * (reqs[r].k + 8) * std::log2((double)reqs[r].cloud->n + 2.0);
+  std::vector<int32_t> order((size_t)nreq);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+  std::vector<std::vector<int32_t>> queue_reqs((size_t)kClasses * kQueues);
+  double load[kClasses][kQueues] = {};
+  for (int32_t r : order) {
+    if (reqs[r].nq == 0) continue;
+    const int c = cls[r];
+    int best = 0;
+    for (int x = 1; x < kQueues; ++x)
+      if (load[c][x] < load[c][best]) best = x;
+    load[c][best] += cost[r];
+    queue_reqs[(size_t)c * kQueues + best].push_back(r);
+  }
+  p->pending = false;
+  HIP_TRY(hipEventSynchronize(p->done), "mknn_batch_plan_run: wait for the previous run");
+  BatchHeader *hdr = (BatchHeader *)(p->h_stage + p->off_hdr);
+  QueryArgs *args = (QueryArgs *)(p->h_stage + p->off_reqs);
+  BatchTile *tiles = (BatchTile *)(p->h_stage + p->off_tiles);
+  BoxArgs *boxes = (BoxArgs *)(p->h_stage + p->off_boxes);
+  int64_t *d_qoff = (int64_t *)(p->h_stage + p->off_qoff);
+  int64_t nt = 0;
+  for (int c = 0; c < kClasses; ++c) {
+    for (int x = 0; x < kQueues; ++x) {
+      hdr->qbound[c][x] = (int32_t)nt;
+      for (int32_t r : queue_reqs[(size_t)c * kQueues + x]) {
+        for (int64_t b = 0; b < reqs[r].nq; b += p->tile_q) {
+          if (nt >= p->max_tiles)
+            return set_error(MKNN_EINVAL, "mknn_batch_plan_run: tile table overflow");
+          tiles[nt].req = r;
+          tiles[nt].pad = 0;
+          tiles[nt].begin = b;
+          tiles[nt].end = std::min<int64_t>(reqs[r].nq, b + p->tile_q);
+          ++nt;
+        }
+      }
+    }
+    hdr->qbound[c][kQueues] = (int32_t)nt;
+  }
+  hdr->nreq = nreq;
+  hdr->sorted = p->sort ? 1 : 0;
+  hdr->total_q = qoff[nreq];
+  for (int32_t r = 0; r < nreq; ++r) {
+    const mknn_request &q = reqs[r];
+    fill_cloud_args(q.cloud, &args[r]);
+    args[r].q = q.d_q;
+    args[r].qs = p->sort ? p->d_qs + qoff[r] : nullptr;
+    args[r].nq = q.nq;
+    args[r].k = q.k;
+    args[r].m = q.m == 0 ? (int32_t)q.cloud->n : q.m;
+    args[r].out_idx = q.d_idx;
+    args[r].out_dist = q.d_dist;
+    boxes[r] = box_of(q.cloud);
+  }
+  for (int32_t r = 0; r <= nreq; ++r) d_qoff[r] = qoff[r];
+  // ---- run (graph replay or eager)
+  hipStream_t s = (hipStream_t)stream;
+  if (p->use_graph && !timing_enabled()) {
+    if (!p->exec) {
+      HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal),
+              "mknn_batch_plan_run: begin capture");
+      hipError_t e = plan_enqueue(p, p->cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return set_error(MKNN_EHIP, std::string("mknn_batch_plan_run: capture failed: ") +
+                                        hipGetErrorName(e != hipSuccess ? e : e2));
+      }
+      p->graph = g;
+      HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0),
+              "mknn_batch_plan_run: instantiate");
+    }
+    HIP_TRY(hipGraphLaunch(p->exec, s), "mknn_batch_plan_run: graph launch");
+  } else {
+    HIP_TRY(plan_enqueue(p, s), "mknn_batch_plan_run: launch");
+  }
+  HIP_TRY(hipEventRecord(p->done, s), "mknn_batch_plan_run: record");
+  p->pending = true;
+  return MKNN_OK;
+}
+
+// One plan per process, grown on demand (the convenience entry point is not thread-safe).
+static mknn_batch_plan *g_plan = nullptr;
+
+mknn_status mknn_batch_knn(const mknn_request *reqs, int32_t nreq, void *stream) {
+  clear_error();
+  if (nreq < 0 || (nreq > 0 && !reqs)) return set_error(MKNN_EINVAL, "mknn_batch_knn: bad request array");
+  int64_t tq = 0;
+  for (int32_t r = 0; r < nreq; ++r) tq += reqs[r].nq > 0 ? reqs[r].nq : 0;
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "mknn_batch_knn: hipGetDevice");
+  if (g_plan && (g_plan->device != dev || g_plan->max_req < nreq || g_plan->max_q < tq)) {
+    mknn_batch_plan_destroy(g_plan);
+    g_plan = nullptr;
+  }
+  if (!g_plan) {
+    mknn_status st = mknn_batch_plan_create(std::max<int64_t>(nreq, 64),
+                                            std::max<int64_t>(tq, (int64_t)1 << 20), 1024, 0,
+                                            &g_plan);
+    if (st != MKNN_OK) return st;
+  }
+  return mknn_batch_plan_run(g_plan, reqs, nreq, stream);
+}
+
+}  // extern "C"

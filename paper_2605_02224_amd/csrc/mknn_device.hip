@@ -24,39 +24,13 @@
 #include <string>
 #include <vector>
 
-#include "cloud.h"
-#include "knn_kernels.h"
-
-namespace mknn {
-
-#define HIP_TRY(expr, what)                                                             \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return set_error(MKNN_EHIP, std::string(what) + ": " + hipGetErrorName(e_) + " (" + \
-                                      hipGetErrorString(e_) + ")");                     \
-  } while (0)
-
-// ---------------------------------------------------------------------------------------
-// device helpers
-// ---------------------------------------------------------------------------------------
-__device__ __forceinline__ double sq_dist(double qx, double qy, double qz, float4 c) {
-  double dx = qx - (double)c.x;
-  double dy = qy - (double)c.y;
-  double dz = qz - (double)c.z;
-  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range
-// of tiles so Morton-adjacent queries share that XCD's L2.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
-  uint32_t x = b & 7u, i = b >> 3, q8 = nb >> 3, r8 = nb & 7u;
-  return x * q8 + (x < r8 ? x : r8) + i;
-}
-
-}  // namespace mknn
+#include "device_common.h"
 #include "knn_group.h"
+
 namespace mknn {
+
+
+
 
 template <int K>
 struct TopK {
@@ -233,41 +207,15 @@ constexpr int kMortonBits = 16;
 constexpr int kMortonBins = 1 << kMortonBits;
 constexpr int64_t kSortMinQueries = 8192;
 
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {   // 10 bits -> every third bit
-  v &= 0x3ffu;
-  v = (v | (v << 16)) & 0x030000ffu;
-  v = (v | (v << 8)) & 0x0300f00fu;
-  v = (v | (v << 4)) & 0x030c30c3u;
-  v = (v | (v << 2)) & 0x09249249u;
-  return v;
-}
 
-struct BoxArgs {
-  float lo[3], scale[3];
-};
 
-__device__ __forceinline__ uint32_t morton_bin(float x, float y, float z, const BoxArgs &b) {
-  float t[3] = {(x - b.lo[0]) * b.scale[0], (y - b.lo[1]) * b.scale[1], (z - b.lo[2]) * b.scale[2]};
-  uint32_t u[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    float v = fminf(fmaxf(t[i], 0.f), 1023.f);
-    u[i] = (uint32_t)v;
-  }
-  uint32_t code = (spread3(u[0]) << 2) | (spread3(u[1]) << 1) | spread3(u[2]);
-  return code >> (30 - kMortonBits);
-}
 
-__global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *p, int64_t cnt) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) p[i] = 0u;
-}
 
 __global__ __launch_bounds__(256) void morton_hist_kernel(const float *q, int64_t nq, BoxArgs b,
                                                           uint32_t *hist) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nq) return;
-  atomicAdd(&hist[morton_bin(q[3 * i], q[3 * i + 1], q[3 * i + 2], b)], 1u);
+  atomicAdd(&hist[morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], b) >> (30 - kMortonBits)], 1u);
 }
 
 // exclusive scan of kMortonBins counters by one workgroup of 1024 threads
@@ -303,31 +251,14 @@ __global__ __launch_bounds__(256) void morton_scatter_kernel(const float *q, int
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nq) return;
   float x = q[3 * i], y = q[3 * i + 1], z = q[3 * i + 2];
-  uint32_t pos = atomicAdd(&cursor[morton_bin(x, y, z, b)], 1u);
+  uint32_t pos = atomicAdd(&cursor[morton30(x, y, z, b) >> (30 - kMortonBits)], 1u);
   qs[pos] = make_float4(x, y, z, __int_as_float((int32_t)i));
 }
 
 // ---------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------
-static uint32_t host_spread3(uint32_t v) {
-  v &= 0x3ffu;
-  v = (v | (v << 16)) & 0x030000ffu;
-  v = (v | (v << 8)) & 0x0300f00fu;
-  v = (v | (v << 4)) & 0x030c30c3u;
-  v = (v | (v << 2)) & 0x09249249u;
-  return v;
-}
 
-static BoxArgs box_of(const mknn_cloud *c) {
-  BoxArgs b;
-  for (int k = 0; k < 3; ++k) {
-    float ext = c->hi[k] - c->lo[k];
-    b.lo[k] = c->lo[k];
-    b.scale[k] = ext > 0.f ? 1024.f / ext : 0.f;
-  }
-  return b;
-}
 
 static void free_device(mknn_cloud *c) {
   if (c->d_ent) (void)hipFree(c->d_ent);
@@ -338,20 +269,14 @@ static void free_device(mknn_cloud *c) {
   c->dev_version = ~0ull;
 }
 
-template <int K, bool EXACTK, bool COUNT>
-static hipError_t launch_lane(const QueryArgs &a, hipStream_t s) {
-  const int threads = 256;
-  const uint32_t blocks = (uint32_t)((a.nq + threads - 1) / threads);
-  hipLaunchKernelGGL((knn_lane_kernel<K, EXACTK, COUNT>), dim3(blocks), dim3(threads), 0, s, a);
-  return hipGetLastError();
-}
-
 // ---- optional kernel timing
 static bool g_timing = false;
 static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
 static size_t g_events_used = 0;
 
-static hipError_t timing_mark(hipStream_t s, bool start) {
+bool timing_enabled() { return g_timing; }
+
+hipError_t timing_mark(hipStream_t s, bool start) {
   if (!g_timing) return hipSuccess;
   if (start) {
     if (g_events_used == g_events.size()) {
@@ -366,6 +291,15 @@ static hipError_t timing_mark(hipStream_t s, bool start) {
   }
   return hipEventRecord(g_events[g_events_used++].second, s);
 }
+
+template <int K, bool EXACTK, bool COUNT>
+static hipError_t launch_lane(const QueryArgs &a, hipStream_t s) {
+  const int threads = 256;
+  const uint32_t blocks = (uint32_t)((a.nq + threads - 1) / threads);
+  hipLaunchKernelGGL((knn_lane_kernel<K, EXACTK, COUNT>), dim3(blocks), dim3(threads), 0, s, a);
+  return hipGetLastError();
+}
+
 
 // Optional dynamic LDS per workgroup, used only to cap occupancy in tuning experiments.
 static size_t lds_pad() {
@@ -400,17 +334,6 @@ static hipError_t dispatch_group(const QueryArgs &a, int kmax, bool exact, hipSt
   return hipErrorInvalidValue;
 }
 
-[[maybe_unused]] static int device_cus() {
-  static int cus = 0;
-  if (!cus) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-  }
-  return cus;
-}
 
 // kernel family: 0 = automatic, 1 = one query per lane, 2 = 16 lanes per query
 static int g_family = 0;
@@ -444,26 +367,7 @@ static hipError_t dispatch_lane(const QueryArgs &a, int kmax, bool exact, hipStr
   return hipErrorInvalidValue;
 }
 
-static mknn_status check_uploaded(const mknn_cloud *c, const char *who) {
-  if (!c) return set_error(MKNN_EINVAL, std::string(who) + ": cloud is NULL");
-  if (!c->d_ent || c->dev_version != c->version)
-    return set_error(MKNN_EINVAL, std::string(who) + ": cloud is not uploaded (call mknn_upload)");
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
-    return set_error(MKNN_EINVAL, std::string(who) + ": cloud lives on another device");
-  return MKNN_OK;
-}
 
-static void fill_cloud_args(const mknn_cloud *c, QueryArgs *a) {
-  std::memset(a, 0, sizeof(*a));
-  a->ent = (const float4 *)c->d_ent;
-  a->lst = c->d_lst;
-  a->head = c->head;
-  a->hx = c->xyz[3 * (int64_t)c->head];
-  a->hy = c->xyz[3 * (int64_t)c->head + 1];
-  a->hz = c->xyz[3 * (int64_t)c->head + 2];
-  a->n = c->n;
-}
 
 // Morton bucketing of the queries into stream-ordered scratch, for batches large enough
 // to pay for it.
@@ -479,8 +383,8 @@ static mknn_status prepare_queries(const mknn_cloud *c, const float *d_q, int64_
   BoxArgs b = box_of(c);
   const int threads = 256;
   const uint32_t blocks = (uint32_t)((nq + threads - 1) / threads);
-  hipLaunchKernelGGL(zero_u32_kernel, dim3(kMortonBins / threads), dim3(threads), 0, s, hist,
-                     (int64_t)kMortonBins);
+  hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(kMortonBins / threads), dim3(threads), 0, s,
+                     hist, (int64_t)kMortonBins, 0u);
   hipLaunchKernelGGL(morton_hist_kernel, dim3(blocks), dim3(threads), 0, s, d_q, nq, b, hist);
   hipLaunchKernelGGL(scan_bins_kernel, dim3(1), dim3(1024), 0, s, hist);
   hipLaunchKernelGGL(morton_scatter_kernel, dim3(blocks), dim3(threads), 0, s, d_q, nq, b, hist, qs);
@@ -548,13 +452,7 @@ mknn_status mknn_upload(mknn_cloud *c, void *stream) {
     BoxArgs b = box_of(c);
     std::vector<uint64_t> key(n);
     for (int64_t r = 0; r < n; ++r) {
-      uint32_t u[3];
-      for (int k = 0; k < 3; ++k) {
-        float t = (c->xyz[3 * r + k] - b.lo[k]) * b.scale[k];
-        t = std::min(std::max(t, 0.f), 1023.f);
-        u[k] = (uint32_t)t;
-      }
-      uint64_t code = (host_spread3(u[0]) << 2) | (host_spread3(u[1]) << 1) | host_spread3(u[2]);
+      const uint64_t code = morton30(c->xyz[3 * r], c->xyz[3 * r + 1], c->xyz[3 * r + 2], b);
       key[r] = (code << 32) | (uint64_t)r;
     }
     std::sort(key.begin(), key.end());

@@ -1,0 +1,121 @@
+"""GPU parity of the batched form: many clouds in one persistent launch per class, against
+the oracle and bit-for-bit against the plain per-cloud launch."""
+import numpy as np
+import pytest
+
+from tests._compare import compare_rows
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    oracle.build(force=False)
+    from paper_2605_02224_amd import api as A
+    from paper_2605_02224_amd import workloads as W
+    rng = np.random.default_rng(42)
+    clouds = []
+    for i in range(18):
+        n = int(np.exp(rng.uniform(np.log(300), np.log(40000))))
+        c = W.random_cloud(n, seed=100 + i, shape=W.SHAPES[i % 3])
+        P = c.by_rank
+        clouds.append((P, A.Cloud.build(P).upload()))
+    return torch, oracle, A, W, clouds
+
+
+def _make_batch(env, seed, k_choices=(1, 4, 10, 16, 17, 33, 64)):
+    torch, oracle, A, W, clouds = env
+    rng = np.random.default_rng(seed)
+    items, host = [], []
+    for i, (P, cl) in enumerate(clouds):
+        if rng.uniform() < 0.15:
+            continue
+        nq = int(rng.choice([0, 1, 37, 500, 3000, 9000]))
+        k = int(rng.choice(k_choices))
+        m = 0 if rng.uniform() < 0.5 else int(rng.integers(1, P.shape[0] + 1))
+        lo, hi = W.bbox_expanded(P, 1.05)
+        Q = W.uniform_in_box(rng, nq, lo, hi)
+        items.append((cl, torch.from_numpy(Q).cuda(), k, m))
+        host.append((P, Q, k, m))
+    return A.alloc_outputs(items), host
+
+
+def _check(env, items, host, sample=400):
+    torch, oracle, A, W, clouds = env
+    rng = np.random.default_rng(0)
+    ex = 0
+    for (cl, q, k, m, idx, dist), (P, Q, _, _) in zip(items, host):
+        if Q.shape[0] == 0:
+            continue
+        mm = P.shape[0] if m == 0 else m
+        sel = rng.choice(Q.shape[0], min(sample, Q.shape[0]), replace=False)
+        ri, _, rD = oracle.knn_bruteforce(P, Q[sel], k + 1, mm)
+        ex += compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k],
+                           rD[:, :k], rD[:, k])
+    return ex
+
+
+@pytest.mark.parametrize("sort,graph", [(True, True), (False, True), (True, False)])
+def test_batch_matches_oracle_and_plain(env, sort, graph):
+    torch, oracle, A, W, clouds = env
+    items, host = _make_batch(env, seed=1)
+    plan = A.BatchPlan(64, 200000, tile_queries=256, sort=sort, graph=graph)
+    plan.run(items)
+    torch.cuda.synchronize()
+    assert _check(env, items, host) <= 3
+    # the plain launch runs the same per-query walk: identical bits
+    for cl, q, k, m, idx, dist in items:
+        if q.shape[0] == 0:
+            continue
+        pi, pd = cl.knn(q, k, None if m == 0 else m)
+        assert torch.equal(pi, idx) and torch.equal(pd, dist)
+
+
+def test_graph_replays_with_changing_batches(env):
+    """One captured graph replays different batches; between replays the program does its
+    own eager work and synchronises; every replay equals the eager result."""
+    torch, oracle, A, W, clouds = env
+    plan = A.BatchPlan(64, 200000, tile_queries=512, sort=True, graph=True)
+    eager = A.BatchPlan(64, 200000, tile_queries=512, sort=True, graph=False)
+    for rep in range(4):
+        items, host = _make_batch(env, seed=10 + rep)
+        plan.run(items)
+        torch.cuda.synchronize()
+        got = [(i.clone(), d.clone()) for (_, _, _, _, i, d) in items]
+        _ = torch.randn(1000, device="cuda").sum().item()      # unrelated eager work
+        eager.run(items)
+        torch.cuda.synchronize()
+        for (gi, gd), (_, _, _, _, i, d) in zip(got, items):
+            assert torch.equal(gi, i) and torch.equal(gd, d)
+        if rep == 0:
+            assert _check(env, items, host, sample=200) <= 3
+
+
+def test_convenience_entry_and_empty(env):
+    torch, oracle, A, W, clouds = env
+    A.batch_knn([])
+    items, host = _make_batch(env, seed=5, k_choices=(10,))
+    A.batch_knn(items)
+    torch.cuda.synchronize()
+    assert _check(env, items, host, sample=200) <= 3
+
+
+def test_batch_errors(env):
+    torch, oracle, A, W, clouds = env
+    from paper_2605_02224_amd._lib import MknnError
+    P, cl = clouds[0]
+    q = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
+    plan = A.BatchPlan(2, 100, tile_queries=16)
+    with pytest.raises(MknnError):
+        plan.run(A.alloc_outputs([(cl, q, 65, 0)]))
+    with pytest.raises(MknnError):
+        plan.run(A.alloc_outputs([(cl, q, 4, P.shape[0] + 1)]))
+    with pytest.raises(MknnError):
+        plan.run(A.alloc_outputs([(cl, q, 4, 0)] * 3))          # over request capacity
+    big = torch.zeros((101, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(MknnError):
+        plan.run(A.alloc_outputs([(cl, big, 4, 0)]))            # over query capacity
