@@ -197,6 +197,33 @@ mknn_status mknn_knn_counts(const mknn_cloud *c, const float *d_q, int64_t nq, i
 mknn_status mknn_timing_enable(int enable);
 mknn_status mknn_timing_read(double *total_ms, int64_t *launches);
 
+/* ---------------------------------------------------------------------------------------
+ * Deletion (Sec. 4.3, Alg. 3).
+ *
+ * mknn_delete: removes the given live ranks, one after the other.  Afterwards the successor
+ * lists equal those of the remaining points inserted in the original relative order.
+ * Method: prune the deleted rank from its predecessors' lists (Lemma 1).  Then, for every
+ * entry k of its list, rebuild the local Delaunay triangulation of its former neighbours
+ * and add each pair (j, k) whose shared Voronoi facet reaches into the deleted site's old
+ * cell (Lemma 2).  Ranks keep their numbers; deleted ranks disappear from all lists, and
+ * the head moves to the oldest live rank.  m keeps counting original ranks.
+ * If the cloud is uploaded, the changed lists are copied on write into fresh segments of
+ * the device arena and their descriptors are switched by a kernel on `stream`.  Work
+ * enqueued later on that stream sees the new lists; work already running keeps reading
+ * the old segments.  When the arena's slack runs out, the lists are packed again.  The
+ * call synchronises `stream` before returning.
+ *   ranks  host int32 [count]
+ * Errors: ENOTFOUND (unknown, deleted or repeated rank; nothing is changed), EINVAL (the
+ * last live point), EUNSUPPORTED (the local set starts with four coplanar points; ranks of
+ * the batch before the failing one stay deleted), EHIP, ENOMEM.  Not thread-safe per
+ * cloud: queries on other streams must be ordered around a deletion by the caller.
+ */
+mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void *stream);
+
+/* Number of live points, and the oldest live rank (where every descent starts). */
+int64_t mknn_live_count(const mknn_cloud *c);
+int32_t mknn_head(const mknn_cloud *c);
+
 /* Release a cloud and all its host and device memory (device frees synchronise). */
 void mknn_free(mknn_cloud *c);
 

@@ -51,6 +51,9 @@ SIGNATURES.update({
     "mknn_batch_plan_run": (ctypes.c_int, [_P, ctypes.POINTER(Request), _I32, _P]),
     "mknn_batch_plan_destroy": (None, [_P]),
     "mknn_batch_knn": (ctypes.c_int, [ctypes.POINTER(Request), _I32, _P]),
+    "mknn_delete": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "mknn_live_count": (_I64, [_P]),
+    "mknn_head": (_I32, [_P]),
 })
 
 _lib = None

@@ -84,6 +84,22 @@ class Cloud:
         return np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_float)),
                                      (self.n, 3)).copy()
 
+    def delete(self, ranks, stream=None) -> None:
+        """Delete live ranks (Alg. 3); updates the device lists too when uploaded."""
+        r = np.ascontiguousarray(np.asarray(ranks, dtype=np.int32).reshape(-1))
+        st = None
+        if self.device_bytes:
+            st = _stream(stream)
+        check(_lib.lib().mknn_delete(self._h, _ptr(r), r.shape[0], st))
+
+    @property
+    def live_count(self) -> int:
+        return int(_lib.lib().mknn_live_count(self._h))
+
+    @property
+    def head(self) -> int:
+        return int(_lib.lib().mknn_head(self._h))
+
     # ---- device side
     def upload(self, stream=None) -> "Cloud":
         check(_lib.lib().mknn_upload(self._h, _stream(stream)))

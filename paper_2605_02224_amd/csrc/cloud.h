@@ -7,6 +7,26 @@
 #include "delaunay.h"
 #include "mknn.h"
 
+namespace mknn {
+// Successor (or predecessor) lists that can be edited in place: list r occupies
+// pool[start[r] .. start[r] + len[r]), ascending, with room for cap[r] entries; a list that
+// outgrows its room moves to the end of the pool.
+struct DynLists {
+  std::vector<int64_t> start;
+  std::vector<int32_t> len, cap;
+  std::vector<int32_t> pool;
+
+  void from_csr(const Csr &c, int64_t n);
+  void to_csr(Csr *c, int64_t n) const;
+  const int32_t *begin(int64_t r) const { return pool.data() + start[r]; }
+  int32_t size(int64_t r) const { return len[r]; }
+  bool contains(int64_t r, int32_t v) const;
+  void insert_sorted(int64_t r, int32_t v);
+  bool erase(int64_t r, int32_t v);
+  void clear(int64_t r) { len[r] = 0; }
+};
+}  // namespace mknn
+
 struct mknn_cloud {
   int64_t n = 0;
   std::vector<float> xyz;          // n x 3 float32 by rank
@@ -14,6 +34,9 @@ struct mknn_cloud {
   mknn::Csr succ;                  // successor lists (ranks ascending)
   mknn::Csr pred;                  // Delaunay neighbours at insertion (transpose of succ)
   std::vector<uint8_t> live;       // 1 = present
+  bool editable = false;           // dsucc/dpred hold the lists (after the first deletion)
+  bool csr_dirty = false;          // succ/pred CSR views are stale
+  mknn::DynLists dsucc, dpred;
   int32_t head = 0;                // smallest live rank
   int64_t nlive = 0;
   float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};   // bounding box of all points
@@ -23,6 +46,7 @@ struct mknn_cloud {
   int device = -1;
   void *d_ent = nullptr;           // 16-byte records {x, y, z, rank}, padded
   uint64_t *d_lst = nullptr;       // per rank: start | (length << 32)
+  int64_t ent_used = 0, ent_cap = 0;   // records in use / allocated (slack takes deltas)
   int64_t dev_bytes = 0;
   uint64_t dev_version = ~0ull;
 };
@@ -30,4 +54,9 @@ struct mknn_cloud {
 namespace mknn {
 mknn_status set_error(mknn_status s, const std::string &msg);
 void clear_error();
+// Deletes ranks[0..count) from the host lists (Alg. 3).  On success, *changed receives
+// every rank whose successor list changed (for the device update).
+mknn_status delete_ranks_host(mknn_cloud *c, const int32_t *ranks, int64_t count,
+                              std::vector<int32_t> *changed);
+void refresh_csr(mknn_cloud *c);
 }  // namespace mknn

@@ -65,12 +65,13 @@ void DelaunayBuilder::append(int32_t owner, int32_t rank) {
 // A tetrahedron conflicts with the new (newest) site p when p lies inside or on its
 // circumsphere; a ghost tetrahedron (hull facet F plus the vertex at infinity) conflicts
 // when p lies strictly beyond F, or in F's plane inside or on F's circumcircle.
-bool DelaunayBuilder::conflict(int32_t t, const double *p) const {
+bool DelaunayBuilder::conflict(int32_t t, const double *p, bool strict) const {
   const int32_t *v = &tv_[4 * (int64_t)t];
   int inf = -1;
   for (int i = 0; i < 4; ++i)
     if (v[i] == kInf) inf = i;
-  if (inf < 0) return insphere(pt(v[0]), pt(v[1]), pt(v[2]), pt(v[3]), p) >= 0;
+  const int need = strict ? 1 : 0;
+  if (inf < 0) return insphere(pt(v[0]), pt(v[1]), pt(v[2]), pt(v[3]), p) >= need;
   const double *q[4];
   for (int i = 0; i < 4; ++i) q[i] = (i == inf) ? p : pt(v[i]);
   int o = orient3d(q[0], q[1], q[2], q[3]);
@@ -84,7 +85,7 @@ bool DelaunayBuilder::conflict(int32_t t, const double *p) const {
       f[k] = s == 0 ? a[k] + 1.0 : a[k] - 1.0;
       const double *r[4];
       for (int i = 0; i < 4; ++i) r[i] = (i == inf) ? f : pt(v[i]);
-      if (orient3d(r[0], r[1], r[2], r[3]) > 0) return insphere(r[0], r[1], r[2], r[3], p) >= 0;
+      if (orient3d(r[0], r[1], r[2], r[3]) > 0) return insphere(r[0], r[1], r[2], r[3], p) >= need;
     }
   }
   return false;  // unreachable for a non-degenerate facet
@@ -93,8 +94,10 @@ bool DelaunayBuilder::conflict(int32_t t, const double *p) const {
 // 1-NN of p among the inserted sites by the descent over the lists built so far: start at
 // rank 0 and jump to the first list entry strictly closer (key = (D, rank)).
 int32_t DelaunayBuilder::nearest_inserted(const double *p, double *dbest) const {
-  int32_t cur = 0;
-  double dcur = sqd(p, pt(0));
+  // the lists hold, in insertion order, the later neighbours of each vertex, so the walk
+  // starts from the first inserted vertex
+  int32_t cur = order_[0];
+  double dcur = sqd(p, pt(cur));
   for (;;) {
     const int32_t *l = &pool_[lstart_[cur]];
     int32_t len = llen_[cur];
@@ -151,11 +154,26 @@ int32_t DelaunayBuilder::locate(int32_t near, const double *p) {
   return -1;
 }
 
+bool DelaunayBuilder::start_with(const int32_t first4[4]) {
+  if (n_ < 4 || ninserted_ != 0) return false;
+  order_.clear();
+  done_.assign(n_, 0);
+  for (int i = 0; i < 4; ++i) {
+    order_.push_back(first4[i]);
+    done_[first4[i]] = 1;
+  }
+  for (int64_t v = 0; v < n_; ++v)
+    if (!done_[v]) order_.push_back((int32_t)v);
+  return orient3d(pt(first4[0]), pt(first4[1]), pt(first4[2]), pt(first4[3])) != 0;
+}
+
 bool DelaunayBuilder::init_first_tet() {
   if (n_ < 4) return false;
-  int o = orient3d(pt(0), pt(1), pt(2), pt(3));
+  if (order_.empty())
+    for (int64_t v = 0; v < n_; ++v) order_.push_back((int32_t)v);
+  int32_t v[4] = {order_[0], order_[1], order_[2], order_[3]};
+  int o = orient3d(pt(v[0]), pt(v[1]), pt(v[2]), pt(v[3]));
   if (o == 0) return false;
-  int32_t v[4] = {0, 1, 2, 3};
   if (o < 0) std::swap(v[2], v[3]);
   int32_t t = alloc_tet();
   int32_t g[4];
@@ -191,10 +209,35 @@ bool DelaunayBuilder::init_first_tet() {
   }
   for (int i = 0; i < 4; ++i) vtet_[v[i]] = t;
   // lists: with four affinely independent sites every pair is Voronoi-adjacent
-  for (int32_t j = 1; j < 4; ++j)
-    for (int32_t i = 0; i < j; ++i) append(i, j);
+  for (int j = 1; j < 4; ++j)
+    for (int i = 0; i < j; ++i) append(order_[i], order_[j]);
+  nbrs_.assign(order_.begin(), order_.begin() + 3);
+  std::sort(nbrs_.begin(), nbrs_.end());
   ninserted_ = 4;
   return true;
+}
+
+bool DelaunayBuilder::edge_in_conflict(int32_t a, int32_t b, const double *p) {
+  // walk the star of b (tetrahedra through b), keep those that also contain a
+  uint32_t ep = ++epoch_;
+  star_.clear();
+  int32_t t0 = vtet_[b];
+  star_.push_back(t0);
+  stamp_[t0] = ep;
+  for (size_t s = 0; s < star_.size(); ++s) {
+    int32_t t = star_[s];
+    const int32_t *v = &tv_[4 * (int64_t)t];
+    if ((v[0] == a || v[1] == a || v[2] == a || v[3] == a) && conflict(t, p, true)) return true;
+    for (int h = 0; h < 4; ++h) {
+      if (v[h] == b) continue;
+      int32_t u = tn_[4 * (int64_t)t + h];
+      if (stamp_[u] != ep) {
+        stamp_[u] = ep;
+        star_.push_back(u);
+      }
+    }
+  }
+  return false;
 }
 
 BuildStatus DelaunayBuilder::insert_next() {
@@ -202,7 +245,7 @@ BuildStatus DelaunayBuilder::insert_next() {
     if (!init_first_tet()) return kBuildDegenerateStart;
     return kBuildOk;
   }
-  const int32_t j = (int32_t)ninserted_;
+  const int32_t j = order_[ninserted_];
   const double *p = pt(j);
   double dnear;
   int32_t near = nearest_inserted(p, &dnear);
@@ -381,7 +424,8 @@ bool DelaunayBuilder::validate(std::string *why) const {
       }
     }
   }
-  for (int64_t v = 0; v < ninserted_; ++v) {
+  for (int64_t pos = 0; pos < ninserted_; ++pos) {
+    const int32_t v = order_[pos];
     int32_t t = vtet_[v];
     bool ok = t >= 0 && !dead[t];
     if (ok) {
@@ -405,7 +449,8 @@ bool DelaunayBuilder::validate_empty_spheres(std::string *why) const {
     bool ghost = false;
     for (int i = 0; i < 4; ++i) ghost |= v[i] == kInf;
     if (ghost) continue;
-    for (int64_t q = 0; q < ninserted_; ++q) {
+    for (int64_t pos = 0; pos < ninserted_; ++pos) {
+      const int32_t q = order_[pos];
       if (q == v[0] || q == v[1] || q == v[2] || q == v[3]) continue;
       int s = insphere(pt(v[0]), pt(v[1]), pt(v[2]), pt(v[3]), pt((int32_t)q));
       // a site exactly on the sphere is allowed only if it is older than some vertex

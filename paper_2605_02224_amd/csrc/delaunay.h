@@ -56,6 +56,19 @@ class DelaunayBuilder {
   int64_t num_tets() const;
   int64_t exact_fallbacks() const;
 
+  // Finite Delaunay neighbours of the vertex inserted last (ascending ids).
+  const std::vector<int32_t> &last_neighbors() const { return nbrs_; }
+
+  // True when some tetrahedron (finite or ghost) incident to edge (a, b) has p strictly inside
+  // its circumsphere (a ghost: p strictly beyond its hull facet, or in the facet's plane and
+  // strictly inside its circumcircle).  p need not be a vertex.
+  bool edge_in_conflict(int32_t a, int32_t b, const double *p);
+
+  // Start the triangulation from four given affinely independent vertices instead of the
+  // first four ids; the remaining ids are then inserted in increasing order (skipping
+  // these four).  Returns false if they are coplanar.
+  bool start_with(const int32_t first4[4]);
+
  private:
   const double *P_;
   int64_t n_;
@@ -86,7 +99,9 @@ class DelaunayBuilder {
 
   const double *pt(int32_t v) const { return P_ + 3 * (int64_t)v; }
   int32_t alloc_tet();
-  bool conflict(int32_t t, const double *p) const;
+  bool conflict(int32_t t, const double *p, bool strict = false) const;
+  std::vector<int32_t> order_;      // insertion order of ids (identity unless start_with)
+  std::vector<char> done_;
   int32_t nearest_inserted(const double *p, double *dbest) const;
   int32_t locate(int32_t near, const double *p);
   void append(int32_t owner, int32_t rank);

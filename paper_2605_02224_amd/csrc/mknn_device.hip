@@ -269,6 +269,13 @@ static void free_device(mknn_cloud *c) {
   c->dev_version = ~0ull;
 }
 
+// Deletion deltas: point rank r[t] at its rewritten list segment.
+__global__ __launch_bounds__(256) void apply_descriptors_kernel(uint64_t *lst, const int32_t *r,
+                                                                const uint64_t *desc, int64_t cnt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < cnt) lst[r[t]] = desc[t];
+}
+
 // ---- optional kernel timing
 static bool g_timing = false;
 static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
@@ -456,8 +463,11 @@ mknn_status mknn_upload(mknn_cloud *c, void *stream) {
       key[r] = (code << 32) | (uint64_t)r;
     }
     std::sort(key.begin(), key.end());
+    refresh_csr(c);
     const int64_t nnz = (int64_t)c->succ.ent.size();
-    if (nnz + kEntPad > (int64_t)0xffffffffll)
+    // slack for list rewrites after deletions (copy-on-write segments)
+    const int64_t cap = nnz + std::max<int64_t>(nnz / 8, 1 << 16) + kEntPad;
+    if (cap > (int64_t)0xffffffffll)
       return set_error(MKNN_EUNSUPPORTED, "mknn_upload: more than 2^32 list entries");
     std::vector<float4> ent((size_t)(nnz + kEntPad));
     std::vector<uint64_t> lst((size_t)n);
@@ -485,7 +495,7 @@ mknn_status mknn_upload(mknn_cloud *c, void *stream) {
 
     free_device(c);
     c->device = dev;
-    HIP_TRY(hipMalloc(&c->d_ent, sizeof(float4) * ent.size()), "mknn_upload: hipMalloc entries");
+    HIP_TRY(hipMalloc(&c->d_ent, sizeof(float4) * (size_t)cap), "mknn_upload: hipMalloc entries");
     HIP_TRY(hipMalloc((void **)&c->d_lst, sizeof(uint64_t) * lst.size()), "mknn_upload: hipMalloc lists");
 
     HIP_TRY(hipMemcpyAsync(c->d_ent, ent.data(), sizeof(float4) * ent.size(), hipMemcpyHostToDevice, s),
@@ -493,7 +503,9 @@ mknn_status mknn_upload(mknn_cloud *c, void *stream) {
     HIP_TRY(hipMemcpyAsync(c->d_lst, lst.data(), sizeof(uint64_t) * lst.size(), hipMemcpyHostToDevice, s),
             "mknn_upload: copy lists");
     HIP_TRY(hipStreamSynchronize(s), "mknn_upload: synchronize");
-    c->dev_bytes = (int64_t)(sizeof(float4) * ent.size() + sizeof(uint64_t) * lst.size());
+    c->dev_bytes = (int64_t)(sizeof(float4) * (size_t)cap + sizeof(uint64_t) * lst.size());
+    c->ent_used = nnz;
+    c->ent_cap = cap - kEntPad;
     c->dev_version = c->version;
   } catch (const std::bad_alloc &) {
     return set_error(MKNN_ENOMEM, "mknn_upload: out of host memory");
@@ -571,6 +583,82 @@ mknn_status mknn_timing_read(double *total_ms, int64_t *launches) {
   g_events_used = 0;
   return MKNN_OK;
 }
+
+mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void *stream) {
+  clear_error();
+  if (!c) return set_error(MKNN_EINVAL, "mknn_delete: cloud is NULL");
+  if (count < 0 || (count > 0 && !ranks)) return set_error(MKNN_EINVAL, "mknn_delete: bad ranks");
+  if (count == 0) return MKNN_OK;
+  const bool on_device = c->d_ent && c->dev_version == c->version;
+  std::vector<int32_t> changed;
+  mknn_status st = delete_ranks_host(c, ranks, count, &changed);
+  if (st != MKNN_OK) {
+    if (on_device) c->dev_version = ~0ull;   // host moved on; a re-upload resynchronises
+    return st;
+  }
+  if (!on_device) return MKNN_OK;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t need = 0;
+  for (int32_t r : changed) need += c->dsucc.size(r);
+  if (c->ent_used + need > c->ent_cap) {
+    // out of slack: pack everything again (waits for work already on the stream)
+    HIP_TRY(hipStreamSynchronize(s), "mknn_delete: synchronize before re-pack");
+    c->dev_version = ~0ull;
+    return mknn_upload(c, stream);
+  }
+  try {
+    // copy-on-write: every changed list gets a fresh segment at the end of the arena, so
+    // work that already read the old descriptor keeps reading the old, untouched records
+    std::vector<float4> rec((size_t)need);
+    std::vector<int32_t> rr(changed.size());
+    std::vector<uint64_t> dd(changed.size());
+    int64_t cur = 0;
+    for (size_t t = 0; t < changed.size(); ++t) {
+      const int32_t r = changed[t];
+      const int32_t len = c->dsucc.size(r);
+      const int32_t *b = c->dsucc.begin(r);
+      rr[t] = r;
+      dd[t] = (uint64_t)(c->ent_used + cur) | ((uint64_t)len << 32);
+      for (int32_t e = 0; e < len; ++e) {
+        const int32_t j = b[e];
+        float4 v;
+        v.x = c->xyz[3 * (int64_t)j];
+        v.y = c->xyz[3 * (int64_t)j + 1];
+        v.z = c->xyz[3 * (int64_t)j + 2];
+        std::memcpy(&v.w, &j, 4);
+        rec[(size_t)(cur + e)] = v;
+      }
+      cur += len;
+    }
+    void *d_tmp = nullptr;
+    const size_t tmp_bytes = sizeof(int32_t) * rr.size() + sizeof(uint64_t) * dd.size() + 16;
+    HIP_TRY(hipMallocAsync(&d_tmp, tmp_bytes, s), "mknn_delete: scratch");
+    uint64_t *d_dd = (uint64_t *)d_tmp;
+    int32_t *d_rr = (int32_t *)(d_dd + dd.size());
+    if (need)
+      HIP_TRY(hipMemcpyAsync((float4 *)c->d_ent + c->ent_used, rec.data(), sizeof(float4) * rec.size(),
+                             hipMemcpyHostToDevice, s), "mknn_delete: copy records");
+    HIP_TRY(hipMemcpyAsync(d_dd, dd.data(), sizeof(uint64_t) * dd.size(), hipMemcpyHostToDevice, s),
+            "mknn_delete: copy descriptors");
+    HIP_TRY(hipMemcpyAsync(d_rr, rr.data(), sizeof(int32_t) * rr.size(), hipMemcpyHostToDevice, s),
+            "mknn_delete: copy ranks");
+    const uint32_t blocks = (uint32_t)((rr.size() + 255) / 256);
+    hipLaunchKernelGGL(apply_descriptors_kernel, dim3(blocks), dim3(256), 0, s, c->d_lst, d_rr,
+                       d_dd, (int64_t)rr.size());
+    HIP_TRY(hipGetLastError(), "mknn_delete: launch");
+    HIP_TRY(hipFreeAsync(d_tmp, s), "mknn_delete: free scratch");
+    HIP_TRY(hipStreamSynchronize(s), "mknn_delete: synchronize");
+    c->ent_used += need;
+    c->dev_version = c->version;
+  } catch (const std::bad_alloc &) {
+    return set_error(MKNN_ENOMEM, "mknn_delete: out of host memory");
+  }
+  return MKNN_OK;
+}
+
+int64_t mknn_live_count(const mknn_cloud *c) { return c ? c->nlive : 0; }
+
+int32_t mknn_head(const mknn_cloud *c) { return c ? c->head : -1; }
 
 void mknn_free(mknn_cloud *c) {
   if (!c) return;

@@ -161,6 +161,7 @@ mknn_status mknn_successors(const mknn_cloud *c, const int64_t **offsets, const 
                             int64_t *nnz) {
   clear_error();
   if (!c || !offsets || !ranks || !nnz) return set_error(MKNN_EINVAL, "mknn_successors: NULL");
+  refresh_csr(const_cast<mknn_cloud *>(c));
   *offsets = c->succ.off.data();
   *ranks = c->succ.ent.data();
   *nnz = (int64_t)c->succ.ent.size();
