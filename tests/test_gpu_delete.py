@@ -1,0 +1,87 @@
+"""GPU queries after deletions: device lists updated by copy-on-write deltas answer k-NN
+over the surviving prefix exactly (Sec. 4.3)."""
+import numpy as np
+import pytest
+
+from tests._compare import compare_rows
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    oracle.build(force=False)
+    from paper_2605_02224_amd import api as A
+    from paper_2605_02224_amd import workloads as W
+    return torch, oracle, A, W
+
+
+def _check(env, cl, P, live, Q, k, m=None):
+    torch, oracle, A, W = env
+    idx, dist = cl.knn(torch.from_numpy(Q).cuda(), k, m)
+    torch.cuda.synchronize()
+    ri, _, rD = oracle.knn_bruteforce(P, Q, k + 1, m, live=live)
+    return compare_rows(idx.cpu().numpy(), dist.cpu().numpy(), ri[:, :k], rD[:, :k], rD[:, k])
+
+
+def test_queries_after_deletion_batches(env):
+    torch, oracle, A, W = env
+    c = W.random_cloud(40000, seed=21, shape="ellipsoid")
+    P = c.by_rank
+    cl = A.Cloud.build(P).upload()
+    live = np.ones(40000, np.uint8)
+    rng = np.random.default_rng(3)
+    lo, hi = W.bbox_expanded(P, 1.1)
+    Q = W.uniform_in_box(rng, 12000, lo, hi)
+    order = rng.permutation(40000)
+    dead = np.concatenate([[0, 1, 2], order[:2000]])
+    dead = dead[np.sort(np.unique(dead, return_index=True)[1])]
+    for b in range(0, dead.size, 500):
+        cl.delete(dead[b:b + 500])
+        live[dead[b:b + 500]] = 0
+        for k, m in ((16, None), (8, 25000), (33, None)):
+            assert _check(env, cl, P, live, Q, k, m) <= 2
+    assert cl.head == int(np.flatnonzero(live)[0])
+
+
+def test_copy_on_write_keeps_earlier_work_on_the_old_lists(env):
+    """A query batch enqueued before a deletion on the same stream answers on the old
+    lists; one enqueued after answers on the new lists."""
+    torch, oracle, A, W = env
+    c = W.random_cloud(20000, seed=22, shape="torus")
+    P = c.by_rank
+    cl = A.Cloud.build(P).upload()
+    lo, hi = W.bbox_expanded(P, 1.1)
+    Q = W.uniform_in_box(np.random.default_rng(4), 50000, lo, hi)
+    qd = torch.from_numpy(Q).cuda()
+    before = cl.knn(qd, 10)                       # enqueued, not yet synchronised
+    dead = np.random.default_rng(5).choice(20000, 1000, replace=False)
+    cl.delete(dead)                               # same (current) stream
+    after = cl.knn(qd, 10)
+    torch.cuda.synchronize()
+    live = np.ones(20000, np.uint8)
+    ri, _, rD = oracle.knn_bruteforce(P, Q[:2000], 10)
+    compare_rows(before[0].cpu().numpy()[:2000], before[1].cpu().numpy()[:2000], ri, rD)
+    live[dead] = 0
+    ri, _, rD = oracle.knn_bruteforce(P, Q[:2000], 10, live=live)
+    compare_rows(after[0].cpu().numpy()[:2000], after[1].cpu().numpy()[:2000], ri, rD)
+
+
+def test_repack_when_slack_runs_out(env):
+    """Deleting most of a small cloud exhausts the arena slack and triggers a full re-pack."""
+    torch, oracle, A, W = env
+    c = W.random_cloud(3000, seed=23, shape="sphere")
+    P = c.by_rank
+    cl = A.Cloud.build(P).upload()
+    live = np.ones(3000, np.uint8)
+    rng = np.random.default_rng(6)
+    Q = W.uniform_in_box(rng, 3000, *W.bbox_expanded(P, 1.2))
+    dead = rng.permutation(3000)[:2500]
+    for b in range(0, 2500, 250):
+        cl.delete(dead[b:b + 250])
+        live[dead[b:b + 250]] = 0
+        assert _check(env, cl, P, live, Q, 12) <= 2
