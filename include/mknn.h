@@ -215,7 +215,8 @@ mknn_status mknn_timing_read(double *total_ms, int64_t *launches);
  *   ranks  host int32 [count]
  * Errors: ENOTFOUND (unknown, deleted or repeated rank; nothing is changed), EINVAL (the
  * last live point), EUNSUPPORTED (the local set starts with four coplanar points; ranks of
- * the batch before the failing one stay deleted), EHIP, ENOMEM.  Not thread-safe per
+ * the batch before the failing one stay deleted on the host, and the device copy must be
+ * uploaded again before the next query), EHIP, ENOMEM.  Not thread-safe per
  * cloud: queries on other streams must be ordered around a deletion by the caller.
  */
 mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void *stream);
@@ -223,6 +224,59 @@ mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void
 /* Number of live points, and the oldest live rank (where every descent starts). */
 int64_t mknn_live_count(const mknn_cloud *c);
 int32_t mknn_head(const mknn_cloud *c);
+
+/* ---------------------------------------------------------------------------------------
+ * Serving: continuous batching over resident clouds, deletions between batches.
+ *
+ * A server owns `nstreams` stream slots (default priority) and a scheduler thread.
+ * Requests and deletion batches are queued in arrival order.  Whenever a slot is free, the
+ * scheduler forms a wave from the waiting requests, in order, while the wave's queries fit
+ * the slot's share of `pool_queries` (admission by memory footprint) and it holds at most
+ * `max_wave_requests` requests.  The wave runs as one batched launch on that slot.  Waves
+ * on different slots overlap on the GPU, and requests arriving meanwhile join the next
+ * wave.  Deletion batches on one cloud run one at a time in arrival order: the host part
+ * (Alg. 3) on a worker thread while waves continue, then the device delta, ordered after
+ * the in-flight waves that read the cloud.  By default a request answers on exactly the
+ * deletions submitted before it (a deletion waits for earlier requests on its cloud to be
+ * launched, and later requests on that cloud wait for the deletion).  With
+ * MKNN_SERVER_BIND_AT_ADMISSION a request answers on the lists current when its wave is
+ * launched, and never waits for a deletion's host part.
+ * With MKNN_SERVER_PLAIN (the per-request baseline) every request is its own mknn_knn
+ * launch, back to back in arrival order on one stream, at most 64 in flight and together
+ * at most pool_queries queries; nstreams and max_wave_requests are then ignored.
+ * Request buffers are caller-owned and must stay valid until the request completes.  If
+ * h_idx/h_dist (pinned host memory, [nq][k]) are given, the results are copied there before
+ * the request counts as complete.
+ */
+typedef struct mknn_server mknn_server;
+
+#define MKNN_SERVER_PLAIN 1
+#define MKNN_SERVER_BIND_AT_ADMISSION 2
+
+mknn_status mknn_server_create(int64_t pool_queries, int32_t nstreams, int32_t max_wave_requests,
+                               int32_t flags, mknn_server **out);
+/* Queue a request; *ticket identifies it.  Errors: EINVAL, EUNSUPPORTED (k), EBUSY (a single
+ * request larger than a slot's pool). */
+mknn_status mknn_server_submit(mknn_server *s, const mknn_request *req, int32_t *h_idx,
+                               float *h_dist, uint64_t *ticket);
+/* Queue a deletion batch (host int32 ranks, copied). */
+mknn_status mknn_server_delete(mknn_server *s, mknn_cloud *c, const int32_t *ranks, int64_t count,
+                               uint64_t *ticket);
+/* *done = 1 once the operation has completed. */
+mknn_status mknn_server_poll(mknn_server *s, uint64_t ticket, int32_t *done);
+/* Block until the operation completes, then forget the ticket.  t_submit / t_done (may be
+ * NULL) receive the submission time and the time completion was observed, in seconds of
+ * mknn_server_now().  deletions_seen (may be NULL) receives, for a request, the number of
+ * deletion batches of this server applied to its cloud when it was launched.  Returns the
+ * operation's own status. */
+mknn_status mknn_server_wait(mknn_server *s, uint64_t ticket, double *t_submit, double *t_done,
+                             int64_t *deletions_seen);
+/* Waves launched so far and the requests they held. */
+mknn_status mknn_server_stats(mknn_server *s, int64_t *waves, int64_t *wave_requests);
+/* Monotonic clock of the server, in seconds. */
+double mknn_server_now(void);
+/* Finish every queued operation, then release the server. */
+void mknn_server_destroy(mknn_server *s);
 
 /* Release a cloud and all its host and device memory (device frees synchronise). */
 void mknn_free(mknn_cloud *c);

@@ -43,6 +43,8 @@ class Request(ctypes.Structure):
                 ("d_dist", ctypes.c_void_p)]
 
 
+SERVER_PLAIN = 1
+SERVER_BIND_AT_ADMISSION = 2
 BATCH_NO_SORT = 1
 BATCH_NO_GRAPH = 2
 
@@ -52,6 +54,16 @@ SIGNATURES.update({
     "mknn_batch_plan_destroy": (None, [_P]),
     "mknn_batch_knn": (ctypes.c_int, [ctypes.POINTER(Request), _I32, _P]),
     "mknn_delete": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "mknn_server_create": (ctypes.c_int, [_I64, _I32, _I32, _I32, _PP]),
+    "mknn_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(Request), _P, _P,
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "mknn_server_delete": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(ctypes.c_uint64)]),
+    "mknn_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_I32)]),
+    "mknn_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+    "mknn_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "mknn_server_now": (ctypes.c_double, []),
+    "mknn_server_destroy": (None, [_P]),
     "mknn_live_count": (_I64, [_P]),
     "mknn_head": (_I32, [_P]),
 })

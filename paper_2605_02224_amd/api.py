@@ -211,3 +211,74 @@ def batch_knn(items, stream=None):
     """Convenience form of the batched call (library-owned plan)."""
     arr = _requests(items)
     check(_lib.lib().mknn_batch_knn(arr, len(items), _stream(stream)))
+
+
+class Server:
+    """Continuous-batching request loop (mknn_server_*).  Request buffers are torch tensors
+    that must stay alive until the request completes; this wrapper keeps them until wait()."""
+
+    def __init__(self, pool_queries: int = 1 << 21, nstreams: int = 2,
+                 max_wave_requests: int = 256, plain: bool = False,
+                 bind_at_admission: bool = False):
+        flags = ((_lib.SERVER_PLAIN if plain else 0) |
+                 (_lib.SERVER_BIND_AT_ADMISSION if bind_at_admission else 0))
+        h = ctypes.c_void_p()
+        check(_lib.lib().mknn_server_create(int(pool_queries), int(nstreams),
+                                            int(max_wave_requests), flags, ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    @staticmethod
+    def now() -> float:
+        return float(_lib.lib().mknn_server_now())
+
+    def submit(self, cloud, q, k: int, m=None, idx=None, dist=None, h_idx=None, h_dist=None):
+        """Queue a request; returns its ticket.  Outputs are allocated when not given."""
+        import torch
+        if idx is None:
+            idx = torch.empty((q.shape[0], k), dtype=torch.int32, device=q.device)
+        if dist is None:
+            dist = torch.empty((q.shape[0], k), dtype=torch.float32, device=q.device)
+        req = _requests([(cloud, q, k, m, idx, dist)])
+        t = ctypes.c_uint64()
+        check(_lib.lib().mknn_server_submit(self._h, req, _ptr(h_idx), _ptr(h_dist),
+                                            ctypes.byref(t)))
+        self._keep[t.value] = (q, idx, dist, h_idx, h_dist)
+        return t.value
+
+    def delete(self, cloud, ranks):
+        r = np.ascontiguousarray(np.asarray(ranks, dtype=np.int32).reshape(-1))
+        t = ctypes.c_uint64()
+        check(_lib.lib().mknn_server_delete(self._h, cloud.handle, _ptr(r), r.shape[0],
+                                            ctypes.byref(t)))
+        self._keep[t.value] = (r,)
+        return t.value
+
+    def done(self, ticket) -> bool:
+        d = ctypes.c_int32()
+        check(_lib.lib().mknn_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket, with_seen: bool = False):
+        """Block until done; returns (submit_time, done_time, buffers[, deletions_seen])."""
+        a, b, v = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        st = _lib.lib().mknn_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(a),
+                                         ctypes.byref(b), ctypes.byref(v))
+        bufs = self._keep.pop(ticket, None)
+        check(st)
+        if with_seen:
+            return a.value, b.value, bufs, v.value
+        return a.value, b.value, bufs
+
+    def stats(self):
+        w, r = ctypes.c_int64(), ctypes.c_int64()
+        check(_lib.lib().mknn_server_stats(self._h, ctypes.byref(w), ctypes.byref(r)))
+        return w.value, r.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().mknn_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -1,5 +1,6 @@
 // Internal definition of a cloud handle, shared by the host and device translation units.
 #pragma once
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -25,6 +26,14 @@ struct DynLists {
   bool erase(int64_t r, int32_t v);
   void clear(int64_t r) { len[r] = 0; }
 };
+// List segments rewritten by a deletion batch, ready to be appended to the device arena.
+struct DeviceDelta {
+  bool on_device = false;
+  std::vector<int32_t> ranks;      // lists that changed
+  std::vector<uint32_t> lens;      // their new lengths
+  std::vector<float> rec;          // their new records {x, y, z, rank bits}, concatenated
+  std::vector<uint64_t> desc;      // new descriptors (filled when applied)
+};
 }  // namespace mknn
 
 struct mknn_cloud {
@@ -40,7 +49,10 @@ struct mknn_cloud {
   int32_t head = 0;                // smallest live rank
   int64_t nlive = 0;
   float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};   // bounding box of all points
-  uint64_t version = 0;            // bumped by every mutation
+  // Bumped by every mutation of the host lists.  A deletion on an uploaded cloud bumps it
+  // only when its device delta is applied, so the device copy stays usable (on the old
+  // lists) while the host part of the deletion runs on another thread.
+  std::atomic<uint64_t> version{0};
 
   // device residency
   int device = -1;
@@ -48,7 +60,8 @@ struct mknn_cloud {
   uint64_t *d_lst = nullptr;       // per rank: start | (length << 32)
   int64_t ent_used = 0, ent_cap = 0;   // records in use / allocated (slack takes deltas)
   int64_t dev_bytes = 0;
-  uint64_t dev_version = ~0ull;
+  std::atomic<uint64_t> dev_version{~0ull};
+  int32_t dev_head = 0;            // the head of the lists on the device
 };
 
 namespace mknn {

@@ -195,7 +195,12 @@ mknn_status delete_ranks_host(mknn_cloud *c, const int32_t *ranks, int64_t count
       adds.clear();
       mknn_status st = redistribute(c, i, P, &adds);
       if (st != MKNN_OK) {
-        c->csr_dirty = true;   // earlier ranks of the batch are already applied
+        if (i != del.front()) {
+          // earlier ranks of the batch are already applied: the host lists have moved on,
+          // and a device copy stays stale until the next upload
+          c->csr_dirty = true;
+          ++c->version;
+        }
         return st;
       }
       for (const NewEntry &e : adds) {
@@ -222,8 +227,9 @@ mknn_status delete_ranks_host(mknn_cloud *c, const int32_t *ranks, int64_t count
       }
     }
     c->csr_dirty = true;
-    ++c->version;
   } catch (const std::bad_alloc &) {
+    c->csr_dirty = true;
+    ++c->version;   // possibly half-applied: treat every device copy as stale
     return set_error(MKNN_ENOMEM, "mknn_delete: out of host memory");
   }
   return MKNN_OK;

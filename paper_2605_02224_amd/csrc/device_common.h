@@ -89,12 +89,20 @@ inline void fill_cloud_args(const mknn_cloud *c, QueryArgs *a) {
   std::memset(a, 0, sizeof(*a));
   a->ent = (const float4 *)c->d_ent;
   a->lst = c->d_lst;
-  a->head = c->head;
-  a->hx = c->xyz[3 * (int64_t)c->head];
-  a->hy = c->xyz[3 * (int64_t)c->head + 1];
-  a->hz = c->xyz[3 * (int64_t)c->head + 2];
+  a->head = c->dev_head;
+  a->hx = c->xyz[3 * (int64_t)c->dev_head];
+  a->hy = c->xyz[3 * (int64_t)c->dev_head + 1];
+  a->hz = c->xyz[3 * (int64_t)c->dev_head + 2];
   a->n = c->n;
 }
+
+// Deletion split in two: delete_prepare edits the host lists and gathers the rewritten
+// list segments; delete_apply enqueues their copy and the descriptor switch on a stream
+// (asynchronously, except that running out of arena slack re-packs synchronously).  The
+// delta must stay alive until the stream has executed the copies.
+mknn_status delete_prepare(mknn_cloud *c, const int32_t *ranks, int64_t count, DeviceDelta *d);
+mknn_status delete_apply(mknn_cloud *c, DeviceDelta *d, hipStream_t s);
+extern "C" mknn_status mknn_upload(mknn_cloud *c, void *stream);
 
 // Optional HIP-event timing of the main query kernels (defined in mknn_device.hip).
 hipError_t timing_mark(hipStream_t s, bool start);

@@ -276,6 +276,86 @@ __global__ __launch_bounds__(256) void apply_descriptors_kernel(uint64_t *lst, c
   if (t < cnt) lst[r[t]] = desc[t];
 }
 
+// ---- deletion: host preparation and device application of the list deltas
+mknn_status delete_prepare(mknn_cloud *c, const int32_t *ranks, int64_t count, DeviceDelta *d) {
+  d->on_device = c->d_ent && c->dev_version == c->version;
+  std::vector<int32_t> changed;
+  mknn_status st = delete_ranks_host(c, ranks, count, &changed);
+  if (st != MKNN_OK) return st;   // a half-applied batch has bumped c->version
+  if (!d->on_device) {
+    ++c->version;
+    return MKNN_OK;
+  }
+  // on the device the version moves when the delta is applied
+  try {
+    // copy-on-write: every changed list gets a fresh segment at the end of the arena, so
+    // work that already read the old descriptor keeps reading the old, untouched records
+    int64_t need = 0;
+    for (int32_t r : changed) need += c->dsucc.size(r);
+    d->ranks = changed;
+    d->lens.resize(changed.size());
+    d->rec.resize((size_t)need * 4);
+    int64_t cur = 0;
+    for (size_t t = 0; t < changed.size(); ++t) {
+      const int32_t r = changed[t];
+      const int32_t len = c->dsucc.size(r);
+      const int32_t *b = c->dsucc.begin(r);
+      d->lens[t] = (uint32_t)len;
+      for (int32_t e = 0; e < len; ++e) {
+        const int32_t j = b[e];
+        float *v = &d->rec[(size_t)(cur + e) * 4];
+        v[0] = c->xyz[3 * (int64_t)j];
+        v[1] = c->xyz[3 * (int64_t)j + 1];
+        v[2] = c->xyz[3 * (int64_t)j + 2];
+        std::memcpy(&v[3], &j, 4);
+      }
+      cur += len;
+    }
+  } catch (const std::bad_alloc &) {
+    return set_error(MKNN_ENOMEM, "mknn_delete: out of host memory");
+  }
+  return MKNN_OK;
+}
+
+mknn_status delete_apply(mknn_cloud *c, DeviceDelta *d, hipStream_t s) {
+  if (!d->on_device) return MKNN_OK;
+  ++c->version;   // the device copy is stale until the delta below is complete
+  const int64_t need = (int64_t)(d->rec.size() / 4);
+  if (c->ent_used + need > c->ent_cap) {
+    // out of slack: pack everything again once the stream's earlier work is done
+    HIP_TRY(hipStreamSynchronize(s), "mknn_delete: synchronize before re-pack");
+    d->rec.clear();
+    return mknn_upload(c, s);
+  }
+  d->desc.resize(d->ranks.size());
+  int64_t cur = 0;
+  for (size_t t = 0; t < d->ranks.size(); ++t) {
+    d->desc[t] = (uint64_t)(c->ent_used + cur) | ((uint64_t)d->lens[t] << 32);
+    cur += d->lens[t];
+  }
+  void *d_tmp = nullptr;
+  const size_t tmp_bytes = sizeof(int32_t) * d->ranks.size() + sizeof(uint64_t) * d->desc.size() + 16;
+  HIP_TRY(hipMallocAsync(&d_tmp, tmp_bytes, s), "mknn_delete: scratch");
+  uint64_t *d_dd = (uint64_t *)d_tmp;
+  int32_t *d_rr = (int32_t *)(d_dd + d->desc.size());
+  if (need)
+    HIP_TRY(hipMemcpyAsync((float4 *)c->d_ent + c->ent_used, d->rec.data(), sizeof(float) * d->rec.size(),
+                           hipMemcpyHostToDevice, s), "mknn_delete: copy records");
+  HIP_TRY(hipMemcpyAsync(d_dd, d->desc.data(), sizeof(uint64_t) * d->desc.size(), hipMemcpyHostToDevice, s),
+          "mknn_delete: copy descriptors");
+  HIP_TRY(hipMemcpyAsync(d_rr, d->ranks.data(), sizeof(int32_t) * d->ranks.size(), hipMemcpyHostToDevice, s),
+          "mknn_delete: copy ranks");
+  const uint32_t blocks = (uint32_t)((d->ranks.size() + 255) / 256);
+  hipLaunchKernelGGL(apply_descriptors_kernel, dim3(blocks), dim3(256), 0, s, c->d_lst, d_rr, d_dd,
+                     (int64_t)d->ranks.size());
+  HIP_TRY(hipGetLastError(), "mknn_delete: launch");
+  HIP_TRY(hipFreeAsync(d_tmp, s), "mknn_delete: free scratch");
+  c->ent_used += need;
+  c->dev_head = c->head;
+  c->dev_version = c->version.load();
+  return MKNN_OK;
+}
+
 // ---- optional kernel timing
 static bool g_timing = false;
 static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
@@ -506,7 +586,8 @@ mknn_status mknn_upload(mknn_cloud *c, void *stream) {
     c->dev_bytes = (int64_t)(sizeof(float4) * (size_t)cap + sizeof(uint64_t) * lst.size());
     c->ent_used = nnz;
     c->ent_cap = cap - kEntPad;
-    c->dev_version = c->version;
+    c->dev_head = c->head;
+    c->dev_version = c->version.load();
   } catch (const std::bad_alloc &) {
     return set_error(MKNN_ENOMEM, "mknn_upload: out of host memory");
   }
@@ -589,70 +670,14 @@ mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void
   if (!c) return set_error(MKNN_EINVAL, "mknn_delete: cloud is NULL");
   if (count < 0 || (count > 0 && !ranks)) return set_error(MKNN_EINVAL, "mknn_delete: bad ranks");
   if (count == 0) return MKNN_OK;
-  const bool on_device = c->d_ent && c->dev_version == c->version;
-  std::vector<int32_t> changed;
-  mknn_status st = delete_ranks_host(c, ranks, count, &changed);
-  if (st != MKNN_OK) {
-    if (on_device) c->dev_version = ~0ull;   // host moved on; a re-upload resynchronises
-    return st;
-  }
-  if (!on_device) return MKNN_OK;
+  DeviceDelta d;
+  mknn_status st = delete_prepare(c, ranks, count, &d);
+  if (st != MKNN_OK) return st;
+  if (!d.on_device) return MKNN_OK;
   hipStream_t s = (hipStream_t)stream;
-  int64_t need = 0;
-  for (int32_t r : changed) need += c->dsucc.size(r);
-  if (c->ent_used + need > c->ent_cap) {
-    // out of slack: pack everything again (waits for work already on the stream)
-    HIP_TRY(hipStreamSynchronize(s), "mknn_delete: synchronize before re-pack");
-    c->dev_version = ~0ull;
-    return mknn_upload(c, stream);
-  }
-  try {
-    // copy-on-write: every changed list gets a fresh segment at the end of the arena, so
-    // work that already read the old descriptor keeps reading the old, untouched records
-    std::vector<float4> rec((size_t)need);
-    std::vector<int32_t> rr(changed.size());
-    std::vector<uint64_t> dd(changed.size());
-    int64_t cur = 0;
-    for (size_t t = 0; t < changed.size(); ++t) {
-      const int32_t r = changed[t];
-      const int32_t len = c->dsucc.size(r);
-      const int32_t *b = c->dsucc.begin(r);
-      rr[t] = r;
-      dd[t] = (uint64_t)(c->ent_used + cur) | ((uint64_t)len << 32);
-      for (int32_t e = 0; e < len; ++e) {
-        const int32_t j = b[e];
-        float4 v;
-        v.x = c->xyz[3 * (int64_t)j];
-        v.y = c->xyz[3 * (int64_t)j + 1];
-        v.z = c->xyz[3 * (int64_t)j + 2];
-        std::memcpy(&v.w, &j, 4);
-        rec[(size_t)(cur + e)] = v;
-      }
-      cur += len;
-    }
-    void *d_tmp = nullptr;
-    const size_t tmp_bytes = sizeof(int32_t) * rr.size() + sizeof(uint64_t) * dd.size() + 16;
-    HIP_TRY(hipMallocAsync(&d_tmp, tmp_bytes, s), "mknn_delete: scratch");
-    uint64_t *d_dd = (uint64_t *)d_tmp;
-    int32_t *d_rr = (int32_t *)(d_dd + dd.size());
-    if (need)
-      HIP_TRY(hipMemcpyAsync((float4 *)c->d_ent + c->ent_used, rec.data(), sizeof(float4) * rec.size(),
-                             hipMemcpyHostToDevice, s), "mknn_delete: copy records");
-    HIP_TRY(hipMemcpyAsync(d_dd, dd.data(), sizeof(uint64_t) * dd.size(), hipMemcpyHostToDevice, s),
-            "mknn_delete: copy descriptors");
-    HIP_TRY(hipMemcpyAsync(d_rr, rr.data(), sizeof(int32_t) * rr.size(), hipMemcpyHostToDevice, s),
-            "mknn_delete: copy ranks");
-    const uint32_t blocks = (uint32_t)((rr.size() + 255) / 256);
-    hipLaunchKernelGGL(apply_descriptors_kernel, dim3(blocks), dim3(256), 0, s, c->d_lst, d_rr,
-                       d_dd, (int64_t)rr.size());
-    HIP_TRY(hipGetLastError(), "mknn_delete: launch");
-    HIP_TRY(hipFreeAsync(d_tmp, s), "mknn_delete: free scratch");
-    HIP_TRY(hipStreamSynchronize(s), "mknn_delete: synchronize");
-    c->ent_used += need;
-    c->dev_version = c->version;
-  } catch (const std::bad_alloc &) {
-    return set_error(MKNN_ENOMEM, "mknn_delete: out of host memory");
-  }
+  st = delete_apply(c, &d, s);
+  if (st != MKNN_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s), "mknn_delete: synchronize");
   return MKNN_OK;
 }
 

@@ -1,0 +1,517 @@
+// Serving runtime: continuous batching of k-NN requests over resident clouds, with deletions
+// applied between batches (Sec. 4.3) and per-request latency stamps.
+//
+// Clients submit requests (cloud, device queries, k, m, device outputs, optional pinned host
+// outputs) and deletion batches; every operation gets a ticket.  A scheduler thread keeps a
+// FIFO of pending operations and a few stream slots.  Whenever a slot is free it forms a wave
+// from the pending requests, in arrival order, as long as the wave's queries fit the slot's
+// share of the device pool -- admission by memory footprint -- and launches it as one
+// batched launch (mknn_batch_plan_run, a replayed hipGraph).  Requests that arrive while
+// waves run wait only until the next slot frees, and waves on different slots overlap on
+// the GPU.  A wave's completion event follows the copies of its results to host memory, and
+// the time the scheduler observes it is the request's completion time.
+//
+// Deletions on one cloud run one at a time, in arrival order.  A worker thread edits the
+// host lists (Alg. 3) while waves keep running.  The device delta (copy-on-write list
+// segments and a descriptor switch) is then enqueued on a deletion stream after the events
+// of the in-flight waves that read that cloud, and later waves on that cloud wait for the
+// delta's event.  Waves launched before the switch answer on the old lists, later ones on
+// the new lists.  Two orders are offered.  By default a request sees exactly the deletions
+// submitted before it: a deletion starts only once no earlier request on its cloud is still
+// waiting, and later requests on that cloud wait until it is applied.  With
+// MKNN_SERVER_BIND_AT_ADMISSION a request binds to the lists current when its wave is
+// launched, so requests never wait for the host part of a deletion.
+//
+// In plain mode (the baseline) every request is its own mknn_knn launch.  All of them go,
+// in FIFO order and back to back, onto one stream; up to kPlainSlots are in flight, each
+// with its own completion event, and the requests in flight hold at most the pool.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "device_common.h"
+
+namespace mknn {
+
+static double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct ServerOp {
+  uint64_t ticket = 0;
+  bool is_delete = false;
+  mknn_request req{};
+  int32_t *h_idx = nullptr;
+  float *h_dist = nullptr;
+  mknn_cloud *cloud = nullptr;
+  std::vector<int32_t> ranks;
+  DeviceDelta delta;
+  double t_submit = 0, t_done = 0;
+  int64_t seen = 0;                 // deletion batches applied to the cloud at launch
+  mknn_status status = MKNN_OK;
+  std::string err;
+  bool done = false;
+};
+using OpPtr = std::shared_ptr<ServerOp>;
+
+constexpr int kPlainSlots = 64;
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipEvent_t ev = nullptr;
+  mknn_batch_plan *plan = nullptr;
+  bool busy = false;
+  std::vector<OpPtr> ops;
+  std::unordered_set<mknn_cloud *> clouds;
+  int64_t queries = 0;
+};
+
+struct Applying {   // a deletion whose device delta is on the deletion stream
+  OpPtr op;
+  hipEvent_t ev;
+};
+
+}  // namespace mknn
+
+using namespace mknn;
+
+struct mknn_server {
+  int device = 0;
+  bool plain = false;
+  bool strict = true;               // requests see exactly the deletions submitted before them
+  int64_t slot_queries = 0;         // largest wave (queries) one slot takes
+  int64_t pool_queries = 0;
+  int64_t inflight_queries = 0;     // plain mode: queries of the requests in flight
+  int32_t max_wave = 0;
+  std::vector<Slot> slots;
+  hipStream_t del_stream = nullptr;
+  std::mutex mu;
+  std::condition_variable cv_sched, cv_done;
+  std::list<OpPtr> pending;         // arrival order
+  int64_t pending_deletes = 0;
+  std::unordered_map<uint64_t, OpPtr> ops;
+  std::unordered_set<mknn_cloud *> blocked;   // a deletion is in its host or device part
+  std::unordered_map<mknn_cloud *, int64_t> applied;   // deletion batches applied per cloud
+  std::unordered_map<mknn_cloud *, hipEvent_t> ready_ev;
+  std::deque<OpPtr> del_queue, del_done;
+  std::vector<Applying> applying;
+  std::vector<hipEvent_t> free_events;
+  std::vector<std::thread> workers;
+  std::thread sched;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  int64_t waves = 0, wave_requests = 0;
+};
+
+namespace mknn {
+
+static hipEvent_t take_event(mknn_server *s) {
+  if (!s->free_events.empty()) {
+    hipEvent_t e = s->free_events.back();
+    s->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+static void finish_op(mknn_server *s, const OpPtr &op, mknn_status st, const std::string &err) {
+  op->status = st;
+  op->err = err;
+  op->t_done = now_s();
+  op->done = true;
+  s->cv_done.notify_all();
+}
+
+// Launch one wave of requests on slot x (mu held).
+static void launch_wave(mknn_server *s, int x, std::vector<OpPtr> &wave) {
+  Slot &sl = s->slots[x];
+  sl.ops = wave;
+  sl.clouds.clear();
+  for (const OpPtr &op : wave) {
+    sl.clouds.insert(op->cloud);
+    auto it = s->applied.find(op->cloud);
+    op->seen = it == s->applied.end() ? 0 : it->second;
+  }
+  for (mknn_cloud *c : sl.clouds) {
+    auto it = s->ready_ev.find(c);
+    if (it != s->ready_ev.end()) (void)hipStreamWaitEvent(sl.stream, it->second, 0);
+  }
+  mknn_status st = MKNN_OK;
+  if (s->plain) {
+    const mknn_request &r = wave[0]->req;
+    st = mknn_knn(r.cloud, r.d_q, r.nq, r.k, r.m == 0 ? (int32_t)r.cloud->n : r.m, r.d_idx,
+                  r.d_dist, sl.stream);
+  } else {
+    std::vector<mknn_request> reqs;
+    reqs.reserve(wave.size());
+    for (const OpPtr &op : wave) reqs.push_back(op->req);
+    st = mknn_batch_plan_run(sl.plan, reqs.data(), (int32_t)reqs.size(), sl.stream);
+  }
+  const std::string err = st == MKNN_OK ? "" : mknn_last_error();
+  for (const OpPtr &op : wave) {
+    if (st != MKNN_OK) continue;
+    const mknn_request &r = op->req;
+    const size_t cnt = (size_t)r.nq * (size_t)r.k;
+    if (cnt && op->h_idx)
+      (void)hipMemcpyAsync(op->h_idx, r.d_idx, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, sl.stream);
+    if (cnt && op->h_dist)
+      (void)hipMemcpyAsync(op->h_dist, r.d_dist, cnt * sizeof(float), hipMemcpyDeviceToHost, sl.stream);
+  }
+  if (st != MKNN_OK) {
+    for (const OpPtr &op : wave) finish_op(s, op, st, err);
+    sl.ops.clear();
+    return;
+  }
+  (void)hipEventRecord(sl.ev, sl.stream);
+  sl.busy = true;
+  for (const OpPtr &op : wave) sl.queries += op->req.nq;
+  s->inflight_queries += sl.queries;
+  ++s->waves;
+  s->wave_requests += (int64_t)wave.size();
+}
+
+static void worker_loop(mknn_server *s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->cv_sched.wait(lk, [&] { return s->stop || !s->del_queue.empty(); });
+    if (s->del_queue.empty()) {
+      if (s->stop) return;
+      continue;
+    }
+    OpPtr op = s->del_queue.front();
+    s->del_queue.pop_front();
+    lk.unlock();
+    // host part of Alg. 3: the cloud is held back from new waves meanwhile
+    op->status = delete_prepare(op->cloud, op->ranks.data(), (int64_t)op->ranks.size(), &op->delta);
+    if (op->status != MKNN_OK) op->err = mknn_last_error();
+    lk.lock();
+    s->del_done.push_back(op);
+    s->cv_sched.notify_all();
+  }
+}
+
+static void scheduler_loop(mknn_server *s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    bool progress = false;
+    // ---- completions of waves
+    for (Slot &sl : s->slots) {
+      if (sl.busy && hipEventQuery(sl.ev) == hipSuccess) {
+        for (const OpPtr &op : sl.ops) finish_op(s, op, MKNN_OK, "");
+        sl.ops.clear();
+        sl.clouds.clear();
+        s->inflight_queries -= sl.queries;
+        sl.queries = 0;
+        sl.busy = false;
+        progress = true;
+      }
+    }
+    // ---- completions of applied deletions
+    for (size_t t = 0; t < s->applying.size();) {
+      if (hipEventQuery(s->applying[t].ev) == hipSuccess) {
+        finish_op(s, s->applying[t].op, MKNN_OK, "");
+        s->free_events.push_back(s->applying[t].ev);
+        s->applying.erase(s->applying.begin() + t);
+        progress = true;
+      } else {
+        ++t;
+      }
+    }
+    // ---- deletions whose host part finished: order the device delta after the waves that
+    //      still read the cloud, then release the cloud
+    while (!s->del_done.empty()) {
+      OpPtr op = s->del_done.front();
+      s->del_done.pop_front();
+      progress = true;
+      mknn_cloud *c = op->cloud;
+      if (op->status == MKNN_OK && op->delta.on_device) {
+        const int64_t need = (int64_t)(op->delta.rec.size() / 4);
+        const bool repack = c->ent_used + need > c->ent_cap;
+        for (Slot &sl : s->slots) {
+          if (!sl.busy || !sl.clouds.count(c)) continue;
+          if (repack) (void)hipEventSynchronize(sl.ev);   // the arena is replaced
+          else (void)hipStreamWaitEvent(s->del_stream, sl.ev, 0);
+        }
+        mknn_status st = delete_apply(c, &op->delta, s->del_stream);
+        if (st != MKNN_OK) {
+          op->status = st;
+          op->err = mknn_last_error();
+        }
+      }
+      s->blocked.erase(c);
+      if (op->status != MKNN_OK) {
+        finish_op(s, op, op->status, op->err);
+        continue;
+      }
+      ++s->applied[c];
+      hipEvent_t &rev = s->ready_ev[c];
+      if (!rev) rev = take_event(s);
+      hipEvent_t done_ev = take_event(s);
+      (void)hipEventRecord(rev, s->del_stream);
+      (void)hipEventRecord(done_ev, s->del_stream);
+      s->applying.push_back({op, done_ev});
+    }
+    // ---- form waves on the free slots, in arrival order
+    for (int x = 0; x < (int)s->slots.size(); ++x) {
+      if (s->slots[x].busy) continue;
+      std::unordered_set<mknn_cloud *> held;   // strict order: clouds with an earlier waiting op
+      std::vector<OpPtr> wave;
+      int64_t wq = 0;
+      for (auto it = s->pending.begin(); it != s->pending.end();) {
+        const OpPtr &op = *it;
+        mknn_cloud *c = op->cloud;
+        if (op->is_delete || (s->strict && (s->blocked.count(c) || held.count(c)))) {
+          if (s->strict) held.insert(c);
+          ++it;
+          continue;
+        }
+        const int64_t nq = op->req.nq;
+        const bool fits = s->plain ? wave.empty() && s->inflight_queries + nq <= s->pool_queries
+                                   : (int64_t)wave.size() < s->max_wave && wq + nq <= s->slot_queries;
+        if (!fits) break;   // later requests wait for the next wave, in arrival order
+        wave.push_back(op);
+        wq += nq;
+        it = s->pending.erase(it);
+      }
+      if (wave.empty()) break;   // the other free slots would find the same
+      launch_wave(s, x, wave);
+      progress = true;
+    }
+    // ---- start deletions: one at a time per cloud, in arrival order; in strict order only
+    //      once no earlier request on the cloud is still waiting
+    if (s->pending_deletes > 0) {
+      std::unordered_set<mknn_cloud *> held, del_held;
+      for (auto it = s->pending.begin(); it != s->pending.end();) {
+        const OpPtr &op = *it;
+        mknn_cloud *c = op->cloud;
+        if (!op->is_delete) {
+          held.insert(c);
+          ++it;
+          continue;
+        }
+        if (!s->blocked.count(c) && !del_held.count(c) && !(s->strict && held.count(c))) {
+          s->blocked.insert(c);
+          s->del_queue.push_back(op);
+          --s->pending_deletes;
+          s->cv_sched.notify_all();
+          it = s->pending.erase(it);
+          progress = true;
+        } else {
+          del_held.insert(c);
+          ++it;
+        }
+      }
+    }
+    bool idle = s->pending.empty() && s->del_queue.empty() && s->del_done.empty() &&
+                s->applying.empty();
+    for (const Slot &sl : s->slots) idle &= !sl.busy;
+    if (s->stop && idle) break;
+    if (progress) continue;
+    bool inflight = !s->applying.empty() || !s->del_done.empty();
+    for (const Slot &sl : s->slots) inflight |= sl.busy;
+    if (inflight) {
+      // poll the completion events; submitters and workers get the lock meanwhile
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    } else {
+      s->cv_sched.wait_for(lk, std::chrono::milliseconds(5));
+    }
+  }
+}
+
+}  // namespace mknn
+
+extern "C" {
+
+double mknn_server_now(void) { return now_s(); }
+
+mknn_status mknn_server_create(int64_t pool_queries, int32_t nstreams, int32_t max_wave_requests,
+                               int32_t flags, mknn_server **out) {
+  clear_error();
+  if (!out) return set_error(MKNN_EINVAL, "mknn_server_create: out is NULL");
+  *out = nullptr;
+  const bool plain = (flags & MKNN_SERVER_PLAIN) != 0;
+  const bool strict = (flags & MKNN_SERVER_BIND_AT_ADMISSION) == 0;
+  if (nstreams < 1 || nstreams > 8 || pool_queries < 1 || max_wave_requests < 1)
+    return set_error(MKNN_EINVAL, "mknn_server_create: bad capacity");
+  mknn_server *s = new (std::nothrow) mknn_server();
+  if (!s) return set_error(MKNN_ENOMEM, "mknn_server_create: out of host memory");
+  s->plain = plain;
+  s->strict = strict;
+  s->pool_queries = pool_queries;
+  s->slot_queries = plain ? pool_queries : std::max<int64_t>(1, pool_queries / nstreams);
+  s->max_wave = plain ? 1 : max_wave_requests;
+  hipError_t e = hipGetDevice(&s->device);
+  s->slots.resize(plain ? kPlainSlots : nstreams);
+  for (Slot &sl : s->slots) {
+    if (e == hipSuccess && (!plain || &sl == &s->slots[0])) {
+      e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+      sl.own_stream = true;
+    } else if (plain) {
+      sl.stream = s->slots[0].stream;
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+    if (e == hipSuccess && !plain) {
+      if (mknn_batch_plan_create(s->max_wave, s->slot_queries, 1024, 0, &sl.plan) != MKNN_OK) {
+        const std::string msg = mknn_last_error();
+        mknn_server_destroy(s);
+        return set_error(MKNN_ENOMEM, "mknn_server_create: " + msg);
+      }
+    }
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->del_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    mknn_server_destroy(s);
+    return set_error(MKNN_EHIP, std::string("mknn_server_create: ") + hipGetErrorName(e));
+  }
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int nworkers = (int)std::max(1u, std::min(8u, hw > 2 ? hw / 2 : 1u));
+  for (int w = 0; w < nworkers; ++w) s->workers.emplace_back(worker_loop, s);
+  s->sched = std::thread(scheduler_loop, s);
+  *out = s;
+  return MKNN_OK;
+}
+
+mknn_status mknn_server_submit(mknn_server *s, const mknn_request *req, int32_t *h_idx,
+                               float *h_dist, uint64_t *ticket) {
+  clear_error();
+  if (!s || !req || !ticket) return set_error(MKNN_EINVAL, "mknn_server_submit: NULL argument");
+  const mknn_request &r = *req;
+  if (!r.cloud || !r.cloud->d_ent)
+    return set_error(MKNN_EINVAL, "mknn_server_submit: cloud missing or never uploaded");
+  if (r.k > MKNN_KMAX) return set_error(MKNN_EUNSUPPORTED, "mknn_server_submit: k above MKNN_KMAX");
+  if (r.k < 1 || r.m < 0 || r.m > r.cloud->n || r.nq < 0)
+    return set_error(MKNN_EINVAL, "mknn_server_submit: k, m or nq out of range");
+  if (r.nq > 0 && (!r.d_q || !r.d_idx || !r.d_dist))
+    return set_error(MKNN_EINVAL, "mknn_server_submit: NULL buffer");
+  if (r.nq > s->slot_queries)
+    return set_error(MKNN_EBUSY, "mknn_server_submit: request larger than a stream slot's pool");
+  OpPtr op = std::make_shared<ServerOp>();
+  op->req = r;
+  op->h_idx = h_idx;
+  op->h_dist = h_dist;
+  op->cloud = const_cast<mknn_cloud *>(r.cloud);
+  op->t_submit = now_s();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return set_error(MKNN_EINVAL, "mknn_server_submit: server is stopping");
+  op->ticket = s->next_ticket++;
+  *ticket = op->ticket;
+  s->ops[op->ticket] = op;
+  if (r.nq == 0) {
+    finish_op(s, op, MKNN_OK, "");
+    return MKNN_OK;
+  }
+  s->pending.push_back(op);
+  s->cv_sched.notify_all();
+  return MKNN_OK;
+}
+
+mknn_status mknn_server_delete(mknn_server *s, mknn_cloud *c, const int32_t *ranks, int64_t count,
+                               uint64_t *ticket) {
+  clear_error();
+  if (!s || !c || !ticket || count < 0 || (count > 0 && !ranks))
+    return set_error(MKNN_EINVAL, "mknn_server_delete: bad argument");
+  OpPtr op = std::make_shared<ServerOp>();
+  op->is_delete = true;
+  op->cloud = c;
+  op->ranks.assign(ranks, ranks + count);
+  op->t_submit = now_s();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return set_error(MKNN_EINVAL, "mknn_server_delete: server is stopping");
+  op->ticket = s->next_ticket++;
+  *ticket = op->ticket;
+  s->ops[op->ticket] = op;
+  s->pending.push_back(op);
+  ++s->pending_deletes;
+  s->cv_sched.notify_all();
+  return MKNN_OK;
+}
+
+mknn_status mknn_server_poll(mknn_server *s, uint64_t ticket, int32_t *done) {
+  clear_error();
+  if (!s || !done) return set_error(MKNN_EINVAL, "mknn_server_poll: NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->ops.find(ticket);
+  if (it == s->ops.end()) return set_error(MKNN_ENOTFOUND, "mknn_server_poll: unknown ticket");
+  *done = it->second->done ? 1 : 0;
+  return MKNN_OK;
+}
+
+mknn_status mknn_server_wait(mknn_server *s, uint64_t ticket, double *t_submit, double *t_done,
+                             int64_t *deletions_seen) {
+  clear_error();
+  if (!s) return set_error(MKNN_EINVAL, "mknn_server_wait: server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->ops.find(ticket);
+  if (it == s->ops.end()) return set_error(MKNN_ENOTFOUND, "mknn_server_wait: unknown ticket");
+  OpPtr op = it->second;
+  s->cv_done.wait(lk, [&] { return op->done; });
+  s->ops.erase(ticket);
+  if (t_submit) *t_submit = op->t_submit;
+  if (t_done) *t_done = op->t_done;
+  if (deletions_seen) *deletions_seen = op->seen;
+  if (op->status != MKNN_OK) return set_error(op->status, op->err);
+  return MKNN_OK;
+}
+
+mknn_status mknn_server_stats(mknn_server *s, int64_t *waves, int64_t *wave_requests) {
+  clear_error();
+  if (!s) return set_error(MKNN_EINVAL, "mknn_server_stats: server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (waves) *waves = s->waves;
+  if (wave_requests) *wave_requests = s->wave_requests;
+  return MKNN_OK;
+}
+
+void mknn_server_destroy(mknn_server *s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_sched.notify_all();
+  }
+  if (s->sched.joinable()) s->sched.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->cv_sched.notify_all();
+  }
+  for (std::thread &t : s->workers)
+    if (t.joinable()) t.join();
+  for (Slot &sl : s->slots) {
+    if (sl.stream && sl.own_stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.plan) mknn_batch_plan_destroy(sl.plan);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+  }
+  for (Slot &sl : s->slots) {
+    if (sl.stream && sl.own_stream) (void)hipStreamDestroy(sl.stream);
+  }
+  if (s->del_stream) {
+    (void)hipStreamSynchronize(s->del_stream);
+    (void)hipStreamDestroy(s->del_stream);
+  }
+  for (auto &kv : s->ready_ev)
+    if (kv.second) (void)hipEventDestroy(kv.second);
+  for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
+  delete s;
+}
+
+}  // extern "C"
