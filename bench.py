@@ -13,6 +13,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import collections
 import json
 import os
 import sys
@@ -149,9 +150,239 @@ def bench_batched(args) -> int:
     return 0
 
 
+class _ServeRun:
+    """One serving run: a submitter (this thread) feeds requests and deletion batches to an
+    mknn server at scheduled times; a collector thread waits for them in order.  Request
+    outputs live in a ring arena of device and pinned host buffers whose regions are reused
+    once the request holding them has been collected."""
+
+    def __init__(self, reqs, qoff, qd, ring, clouds):
+        import ctypes
+        from paper_2605_02224_amd import _lib
+        self.L = _lib.lib()
+        self.reqs = reqs
+        d_idx, d_dist, h_idx, h_dist = ring
+        cap = d_idx.numel()
+        # ring layout: requests take consecutive regions of an unbounded stream of positions
+        # (skipping to the next multiple of the capacity rather than splitting a region);
+        # physical position = stream position mod capacity.  Request i may start once every
+        # request whose region starts less than one capacity before i's end is collected.
+        sz = np.array([r.queries.shape[0] * r.k for r in reqs], np.int64)
+        a = np.zeros(len(reqs), np.int64)
+        pos = 0
+        for i in range(len(reqs)):
+            if pos % cap + sz[i] > cap:
+                pos = (pos // cap + 1) * cap
+            a[i] = pos
+            pos += sz[i]
+        self.need = np.searchsorted(a, a + sz - cap, side="left")
+        self.start = a % cap
+        self.arr = (_lib.Request * len(reqs))()
+        self.hptr = []
+        for i, r in enumerate(reqs):
+            a = self.arr[i]
+            a.cloud = clouds[r.cloud].handle.value
+            a.d_q = qd.data_ptr() + int(qoff[i]) * 12
+            a.nq = r.queries.shape[0]
+            a.k = r.k
+            a.m = r.m
+            a.d_idx = d_idx.data_ptr() + int(self.start[i]) * 4
+            a.d_dist = d_dist.data_ptr() + int(self.start[i]) * 4
+            self.hptr.append((ctypes.c_void_p(h_idx.data_ptr() + int(self.start[i]) * 4),
+                              ctypes.c_void_p(h_dist.data_ptr() + int(self.start[i]) * 4)))
+        self.ctypes = ctypes
+
+    def run(self, srv, lo, hi, arrivals=None, deletions=(), clouds=None, label=""):
+        """Requests lo..hi-1; arrivals: offsets in seconds from the start (None = as fast as
+        the ring allows); deletions: (position, cloud, ranks) submitted just before the
+        request at that position.  Returns per-request latencies and the makespan."""
+        import queue
+        import threading
+        ct = self.ctypes
+        L = self.L
+        h = srv._h
+        q = queue.Queue()
+        n = hi - lo
+        lat = np.zeros(n)
+        t_done = np.zeros(n)
+        state = {"collected": lo, "err": None}
+        cv = threading.Condition()
+
+        def collect():
+            a, b, v = ct.c_double(), ct.c_double(), ct.c_int64()
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                i, tk, t_sched = item
+                st = L.mknn_server_wait(h, ct.c_uint64(tk), ct.byref(a), ct.byref(b), ct.byref(v))
+                if st != 0 and state["err"] is None:
+                    state["err"] = (i, st, L.mknn_last_error().decode())
+                if i >= 0:
+                    lat[i - lo] = b.value - t_sched
+                    t_done[i - lo] = b.value
+                    with cv:
+                        state["collected"] = i + 1
+                        cv.notify_all()
+                    if (i - lo + 1) % 5000 == 0:
+                        log(f"  {label}: {i - lo + 1}/{n} requests done")
+
+        th = threading.Thread(target=collect, daemon=True)
+        th.start()
+        dels = sorted(deletions, key=lambda d: d[0])
+        di = 0
+        tk = ct.c_uint64()
+        t0 = L.mknn_server_now() + 0.005
+        t_first = None
+        for i in range(lo, hi):
+            while di < len(dels) and dels[di][0] <= i:
+                _, ci, ranks = dels[di]
+                r = np.ascontiguousarray(ranks, dtype=np.int32)
+                st = L.mknn_server_delete(h, clouds[ci].handle, ct.c_void_p(r.ctypes.data),
+                                          r.shape[0], ct.byref(tk))
+                if st != 0:
+                    raise RuntimeError(L.mknn_last_error().decode())
+                q.put((-1, tk.value, 0.0))
+                srv._keep[tk.value] = (r,)
+                di += 1
+            if state["collected"] < self.need[i]:
+                with cv:
+                    cv.wait_for(lambda: state["collected"] >= self.need[i])
+            if arrivals is not None:
+                t_sched = t0 + arrivals[i - lo]
+                while True:
+                    d = t_sched - L.mknn_server_now()
+                    if d <= 0:
+                        break
+                    if d > 2e-4:
+                        time.sleep(d - 1e-4)
+            else:
+                t_sched = L.mknn_server_now()
+            if t_first is None:
+                t_first = t_sched
+            hp = self.hptr[i]
+            st = L.mknn_server_submit(h, ct.byref(self.arr[i]), hp[0], hp[1], ct.byref(tk))
+            if st != 0:
+                raise RuntimeError(L.mknn_last_error().decode())
+            q.put((i, tk.value, t_sched))
+        q.put(None)
+        th.join()
+        if state["err"] is not None:
+            raise RuntimeError(f"request {state['err']}")
+        return lat, t_done, t_first
+
+
+def bench_serving(args) -> int:
+    """Serving: 64 resident clouds (sizes log-uniform in [1e4, 2e6], about 24M points),
+    requests of 1..65536 queries (log-uniform), k in {4, 16, 64}, prefix m uniform in
+    [n/10, n]; open-loop Poisson arrivals at 0.7x the plain server's saturation rate; 1% of
+    the points deleted in batches of <= 1000 between requests.  The batched server
+    (continuous batching on stream slots) against the plain one (one launch per request)."""
+    import torch
+    from paper_2605_02224_amd import workloads as W
+    from paper_2605_02224_amd import api as A
+    t0 = time.perf_counter()
+    w = W.serving_clouds(num=args.clouds, n_hi=args.serving_n_hi)
+    npts = sum(c.n for c in w.clouds)
+    log(f"{len(w.clouds)} clouds, {npts} points generated in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    clouds = build_clouds(w.clouds)
+    build_s = time.perf_counter() - t0
+    log(f"built and uploaded in {build_s:.1f} s")
+    nwarm, nmeas, nsat = args.warm_requests, args.requests, args.sat_requests
+    total = nsat + nwarm + nmeas
+    reqs = [w.request() for _ in range(total)]
+    qoff = np.zeros(total + 1, np.int64)
+    qoff[1:] = np.cumsum([r.queries.shape[0] for r in reqs])
+    qd = torch.from_numpy(np.concatenate([r.queries for r in reqs])).cuda()
+    cap = 1 << 26
+    ring = (torch.empty(cap, dtype=torch.int32, device="cuda"),
+            torch.empty(cap, dtype=torch.float32, device="cuda"),
+            torch.empty(cap, dtype=torch.int32).pin_memory(),
+            torch.empty(cap, dtype=torch.float32).pin_memory())
+    torch.cuda.synchronize()
+    run = _ServeRun(reqs, qoff, qd, ring, clouds)
+    nq_of = np.diff(qoff)
+    pool = 1 << 22
+    kw = dict(pool_queries=pool, nstreams=args.slots, max_wave_requests=256,
+              bind_at_admission=True)
+
+    def server(plain):
+        return A.Server(plain=plain, **kw)
+
+    # saturation: the first nsat requests as fast as the ring allows, no deletions
+    sat = {}
+    for name in ("plain", "batched"):
+        srv = server(name == "plain")
+        run.run(srv, 0, min(500, nsat), label=f"{name} warm-up")
+        lat, t_done, t_first = run.run(srv, 0, nsat, label=f"{name} saturation")
+        span = float(t_done.max() - t_first)
+        w_, r_ = srv.stats()
+        srv.close()
+        sat[name] = float(nq_of[:nsat].sum() / span)
+        log(f"{name} saturation: {sat[name] / 1e6:.1f} M queries/s "
+            f"({nsat / span:.0f} requests/s, {r_ / max(w_, 1):.1f} requests per wave)")
+    # open loop at 0.7x the plain saturation rate, with deletions
+    lo, hi = nsat, total
+    mean_nq = float(nq_of[lo:hi].mean())
+    rate = args.load * sat["plain"] / mean_nq
+    rng = np.random.default_rng(11)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, hi - lo))
+    parts = w.deletion_plan(frac=0.01, batch=1000, parts=2)
+    res = {}
+    for p, name in enumerate(("plain", "batched")):
+        pos = np.sort(rng.integers(lo + nwarm, hi, len(parts[p])))
+        dels = [(int(pos[t]), ci, r) for t, (ci, r) in enumerate(parts[p])]
+        srv = server(name == "plain")
+        t0 = time.perf_counter()
+        lat, t_done, t_first = run.run(srv, lo, hi, arrivals=arrivals, deletions=dels,
+                                       clouds=clouds, label=f"{name} open loop")
+        w_, r_ = srv.stats()
+        srv.close()
+        m = lat[nwarm:]
+        t_meas = t_first + arrivals[nwarm] - arrivals[0]
+        served = float(nq_of[lo + nwarm:hi].sum() / (t_done[nwarm:].max() - t_meas))
+        res[name] = {"p50_ms": round(float(np.percentile(m, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(m, 99)) * 1e3, 3),
+                     "mean_ms": round(float(m.mean()) * 1e3, 3),
+                     "served_qps": round(served, 1),
+                     "requests_per_wave": round(r_ / max(w_, 1), 2),
+                     "deletion_batches": len(dels),
+                     "wall_s": round(time.perf_counter() - t0, 2)}
+        log(f"{name} open loop: p50 {res[name]['p50_ms']} ms, p99 {res[name]['p99_ms']} ms, "
+            f"{served / 1e6:.1f} M queries/s served")
+    line = {
+        "metric": "k-NN queries/sec (k=16, 1M-pt surface) + p50/p99 latency, batched vs plain",
+        "value": round(sat["batched"], 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": nsat, "warmup": 500,
+        "ms_per_step": round(1e3 * nq_of[:nsat].sum() / sat["batched"] / nsat, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving_{len(clouds)}_clouds", "clouds": len(clouds),
+                   "points": int(npts), "requests_saturation": nsat,
+                   "requests_open_loop": nmeas, "warmup_requests": nwarm,
+                   "mean_queries_per_request": round(mean_nq, 1), "k": [4, 16, 64],
+                   "offered_load": f"{args.load} x plain saturation",
+                   "offered_qps": round(args.load * sat["plain"], 1),
+                   "slots": args.slots, "pool_queries": pool,
+                   "order": "bind at admission"},
+        "extra": {"plain_saturation_qps": round(sat["plain"], 1),
+                  "speedup_vs_plain": round(sat["batched"] / sat["plain"], 3),
+                  "open_loop": res, "build_s": round(build_s, 2)},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="torus", choices=["torus", "batched"])
+    ap.add_argument("--workload", default="torus", choices=["torus", "batched", "serving"])
+    ap.add_argument("--requests", type=int, default=20000, help="serving: measured requests")
+    ap.add_argument("--warm-requests", type=int, default=1000)
+    ap.add_argument("--sat-requests", type=int, default=5000)
+    ap.add_argument("--load", type=float, default=0.7, help="serving: x plain saturation")
+    ap.add_argument("--slots", type=int, default=2, help="serving: stream slots")
+    ap.add_argument("--serving-n-hi", type=int, default=2_000_000)
     ap.add_argument("--clouds", type=int, default=256)
     ap.add_argument("--tile", type=int, default=1024)
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +407,10 @@ def main() -> int:
         return 2
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "serving":
+        if args.clouds == 256:
+            args.clouds = 64
+        return bench_serving(args)
     from paper_2605_02224_amd import workloads as W
     from paper_2605_02224_amd import _lib
     from paper_2605_02224_amd.api import Cloud

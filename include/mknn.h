@@ -127,8 +127,9 @@ mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, cons
  * launch per register class (k <= 16, 32, 48, 64).  Same per-query semantics as mknn_knn
  * (Alg. 1 + Alg. 2, Sec. 4.2).
  *
- * Each request is cut into tiles of `tile_queries` queries.  Requests are assigned to 8
- * per-XCD queues (largest estimated cost first, all tiles of a cloud on one queue).
+ * Each request is cut into tiles of at most `tile_queries` queries (shorter tiles when the
+ * batch is small, so that it still fills the chip).  Requests are assigned to 8 per-XCD
+ * queues (largest estimated cost first, all tiles of a request on one queue).
  * Persistent workgroups claim tiles from their own queue with an atomic counter and steal
  * from the other queues when it runs dry.  The queries of all requests are bucketed
  * together by (request, Morton code) unless MKNN_BATCH_NO_SORT is set.

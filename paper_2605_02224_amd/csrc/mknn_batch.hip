@@ -1,25 +1,28 @@
 // Batched form: many clouds, each with its own query set, k and prefix, answered by one
 // persistent launch per register-capacity class.
 //
-// Work decomposition.  Every request (cloud, queries, k, m) is cut into tiles of T queries.
-// Requests are placed on 8 queues -- one per XCD, workgroups are dispatched round-robin over
-// the XCDs so blockIdx % 8 names the XCD -- by a largest-processing-time-first rule on an
-// estimated cost (queries x (k + 8) x log2 n), keeping all tiles of a cloud on one queue so
-// its lists stay in that XCD's L2.  A persistent workgroup claims tiles from its own queue
-// with one atomic per tile and steals from the other queues when its own is empty; every
-// workgroup leaves once all 8 queues are exhausted.  Inside a tile the 16 rows of the
-// workgroup run the group-per-query walk (Alg. 1 + Alg. 2, knn_group.h) on the tile's
-// queries.
+// Work decomposition.  Every request (cloud, queries, k, m) is cut into tiles of T queries,
+// T chosen per class and batch as a power of two in [16, tile_queries] that gives about four
+// tiles per resident workgroup, so a small batch still fills the chip.  Requests are placed
+// on 8 queues -- one per XCD, workgroups are dispatched round-robin over the XCDs so
+// blockIdx % 8 names the XCD -- by a largest-processing-time-first rule on an estimated cost
+// (queries x (k + 8) x log2 n), all tiles of a request on one queue so its lists stay in
+// that XCD's L2.  A queue is a list of (request, first tile) entries.  A persistent
+// workgroup claims tiles from its own queue with one atomic per tile, finds the owning
+// request by binary search over the entries, and steals from the other queues when its own
+// is empty; every workgroup leaves once all 8 queues are exhausted.  Inside a tile the 16
+// rows of the workgroup run the group-per-query walk (Alg. 1 + Alg. 2, knn_group.h) on the
+// tile's queries.
 //
 // Query preparation.  The queries of all requests are bucketed together by (request,
 // 12-bit Morton code in the request's cloud box) with one counting sort -- histogram, one
 // scan workgroup per request, scatter -- into one contiguous sorted array.
 //
-// Graph.  A plan owns device buffers sized for a capacity (requests, queries, tiles) and a
-// pinned host staging area.  All per-call data (descriptors, tiles, offsets) are written to
-// the staging area and copied to the device by the first node, and every kernel reads its
-// sizes from device memory with a fixed grid, so one captured hipGraph replays any batch
-// within the capacity.  Counters are cleared by a fill kernel, not by a memset node.
+// Graph.  A plan owns device buffers sized for a capacity (requests, queries) and a pinned
+// host staging area.  All per-call data (descriptors, queue entries, offsets) are written
+// to the staging area and copied to the device by the first node, and every kernel reads
+// its sizes from device memory with a fixed grid, so one captured hipGraph replays any
+// batch within the capacity.  Counters are cleared by a fill kernel, not by a memset node.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,17 +45,20 @@ constexpr int kClasses = 4;              // S = 1..4 slots per lane (k <= 16, 32
 constexpr int kSegBits = 12;             // Morton bits per request in the batch sort
 constexpr int kSegBins = 1 << kSegBits;
 
-struct BatchTile {
+// A queue lists its requests; request e of a queue owns the queue's tiles
+// [first, first of the next entry), each `tile[class]` sorted queries long.
+struct BatchEntry {
   int32_t req;
-  int32_t pad;
-  int64_t begin, end;       // sorted query positions within the request
+  int32_t first;
 };
 
 struct BatchHeader {
   int32_t nreq;
   int32_t sorted;
   int64_t total_q;
-  int32_t qbound[kClasses][kQueues + 1];   // tile index ranges per (class, queue)
+  int32_t qbound[kClasses][kQueues + 1];   // entry index ranges per (class, queue)
+  int32_t qtiles[kClasses][kQueues];       // tiles per (class, queue)
+  int32_t tile[kClasses];                  // queries per tile, per class
 };
 
 // ---------------------------------------------------------------------------------------
@@ -134,38 +140,48 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(const BatchHeader *h,
 template <int S>
 __global__ __launch_bounds__(256) void knn_batch_kernel(const BatchHeader *h,
                                                         const QueryArgs *reqs,
-                                                        const BatchTile *tiles,
+                                                        const BatchEntry *ents,
                                                         uint32_t *counters, int cls) {
-  __shared__ int32_t s_tile;
+  __shared__ int32_t s_tile[2];
   const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
   const int home = blockIdx.x % kQueues;
+  const int64_t tq = h->tile[cls];
   int tried = 0;   // used by thread 0: queues found empty so far
   for (;;) {
     if (threadIdx.x == 0) {
-      int32_t t = -1;
+      int32_t req = -1, t = 0;
       while (tried < kQueues) {
         const int x = (home + tried) % kQueues;
-        const int32_t b0 = h->qbound[cls][x], b1 = h->qbound[cls][x + 1];
-        if (b0 < b1) {
+        const int32_t nt = h->qtiles[cls][x];
+        if (nt > 0) {
           const uint32_t v = atomicAdd(&counters[cls * kQueues + x], 1u);
-          if ((int64_t)b0 + v < (int64_t)b1) {
-            t = b0 + (int32_t)v;
+          if ((int64_t)v < (int64_t)nt) {
+            // the entry owning tile v: last one with first <= v
+            int32_t lo = h->qbound[cls][x], hi = h->qbound[cls][x + 1];
+            while (hi - lo > 1) {
+              const int32_t mid = (lo + hi) >> 1;
+              if (ents[mid].first <= (int32_t)v) lo = mid; else hi = mid;
+            }
+            req = ents[lo].req;
+            t = (int32_t)v - ents[lo].first;
             break;
           }
         }
         ++tried;
       }
-      s_tile = t;
+      s_tile[0] = req;
+      s_tile[1] = t;
     }
     __syncthreads();
-    const int32_t t = s_tile;
+    const int32_t req = s_tile[0];
+    const int64_t begin = (int64_t)s_tile[1] * tq;
     __syncthreads();
-    if (t < 0) return;
-    const BatchTile tile = tiles[t];
-    const QueryArgs &a = reqs[tile.req];
-    for (int64_t s0 = tile.begin + 4 * w; s0 < tile.end; s0 += 16) {
+    if (req < 0) return;
+    const QueryArgs &a = reqs[req];
+    const int64_t end = begin + tq < a.nq ? begin + tq : a.nq;
+    for (int64_t s0 = begin + 4 * w; s0 < end; s0 += 16) {
       const int64_t s = s0 + g;
-      if (s < tile.end) group_query<S, false, false>(a, s, l, g);
+      if (s < end) group_query<S, false, false>(a, s, l, g);
     }
   }
 }
@@ -191,12 +207,12 @@ using namespace mknn;
 // ---------------------------------------------------------------------------------------
 struct mknn_batch_plan {
   int device = -1;
-  int64_t max_req = 0, max_q = 0, max_tiles = 0;
+  int64_t max_req = 0, max_q = 0;
   int32_t tile_q = 1024;
   bool sort = true, use_graph = true;
   // device: staging mirror | counters | bins | sorted queries
   char *d_base = nullptr;
-  size_t off_hdr = 0, off_reqs = 0, off_tiles = 0, off_boxes = 0, off_qoff = 0, stage_bytes = 0;
+  size_t off_hdr = 0, off_reqs = 0, off_ents = 0, off_boxes = 0, off_qoff = 0, stage_bytes = 0;
   uint32_t *d_counters = nullptr;
   uint32_t *d_bins = nullptr;
   float4 *d_qs = nullptr;
@@ -227,7 +243,7 @@ static void plan_release(mknn_batch_plan *p) {
 static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s) {
   const BatchHeader *hdr = (const BatchHeader *)(p->d_base + p->off_hdr);
   const QueryArgs *reqs = (const QueryArgs *)(p->d_base + p->off_reqs);
-  const BatchTile *tiles = (const BatchTile *)(p->d_base + p->off_tiles);
+  const BatchEntry *ents = (const BatchEntry *)(p->d_base + p->off_ents);
   const BoxArgs *boxes = (const BoxArgs *)(p->d_base + p->off_boxes);
   const int64_t *qoff = (const int64_t *)(p->d_base + p->off_qoff);
   hipError_t e = hipMemcpyAsync(p->d_base, p->h_stage, p->stage_bytes, hipMemcpyHostToDevice, s);
@@ -251,13 +267,13 @@ static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s) {
   e = timing_mark(s, true);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(knn_batch_kernel<1>, dim3(p->grid_batch[0]), dim3(256), 0, s, hdr, reqs,
-                     tiles, p->d_counters, 0);
+                     ents, p->d_counters, 0);
   hipLaunchKernelGGL(knn_batch_kernel<2>, dim3(p->grid_batch[1]), dim3(256), 0, s, hdr, reqs,
-                     tiles, p->d_counters, 1);
+                     ents, p->d_counters, 1);
   hipLaunchKernelGGL(knn_batch_kernel<3>, dim3(p->grid_batch[2]), dim3(256), 0, s, hdr, reqs,
-                     tiles, p->d_counters, 2);
+                     ents, p->d_counters, 2);
   hipLaunchKernelGGL(knn_batch_kernel<4>, dim3(p->grid_batch[3]), dim3(256), 0, s, hdr, reqs,
-                     tiles, p->d_counters, 3);
+                     ents, p->d_counters, 3);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return timing_mark(s, false);
@@ -280,7 +296,6 @@ mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, in
   p->max_req = max_requests;
   p->max_q = max_queries;
   p->tile_q = tile_queries;
-  p->max_tiles = max_queries / tile_queries + max_requests + 1;
   p->sort = !(flags & MKNN_BATCH_NO_SORT);
   p->use_graph = !(flags & MKNN_BATCH_NO_GRAPH);
   hipError_t e = hipGetDevice(&p->device);
@@ -289,8 +304,8 @@ mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, in
   o = align256(o + sizeof(BatchHeader));
   p->off_reqs = o;
   o = align256(o + sizeof(QueryArgs) * (size_t)p->max_req);
-  p->off_tiles = o;
-  o = align256(o + sizeof(BatchTile) * (size_t)p->max_tiles);
+  p->off_ents = o;
+  o = align256(o + sizeof(BatchEntry) * (size_t)p->max_req);
   p->off_boxes = o;
   o = align256(o + sizeof(BoxArgs) * (size_t)p->max_req);
   p->off_qoff = o;
@@ -381,26 +396,33 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   HIP_TRY(hipEventSynchronize(p->done), "mknn_batch_plan_run: wait for the previous run");
   BatchHeader *hdr = (BatchHeader *)(p->h_stage + p->off_hdr);
   QueryArgs *args = (QueryArgs *)(p->h_stage + p->off_reqs);
-  BatchTile *tiles = (BatchTile *)(p->h_stage + p->off_tiles);
+  BatchEntry *ents = (BatchEntry *)(p->h_stage + p->off_ents);
   BoxArgs *boxes = (BoxArgs *)(p->h_stage + p->off_boxes);
   int64_t *d_qoff = (int64_t *)(p->h_stage + p->off_qoff);
-  int64_t nt = 0;
+  // tile length per class: about four tiles per resident workgroup, so that a small batch
+  // still spreads over the whole chip, a power of two in [16, tile_q]
+  int64_t class_q[kClasses] = {};
+  for (int32_t r = 0; r < nreq; ++r) class_q[cls[r]] += reqs[r].nq;
+  for (int c = 0; c < kClasses; ++c) {
+    const int64_t want = class_q[c] / (4 * (int64_t)p->grid_batch[c]);
+    int64_t t = 16;
+    while (t * 2 <= want && t * 2 <= p->tile_q) t *= 2;
+    hdr->tile[c] = (int32_t)std::max<int64_t>(16, std::min<int64_t>(t, p->tile_q));
+  }
+  int32_t ne = 0;
   for (int c = 0; c < kClasses; ++c) {
     for (int x = 0; x < kQueues; ++x) {
-      hdr->qbound[c][x] = (int32_t)nt;
+      hdr->qbound[c][x] = ne;
+      int64_t nt = 0;
       for (int32_t r : queue_reqs[(size_t)c * kQueues + x]) {
-        for (int64_t b = 0; b < reqs[r].nq; b += p->tile_q) {
-          if (nt >= p->max_tiles)
-            return set_error(MKNN_EINVAL, "mknn_batch_plan_run: tile table overflow");
-          tiles[nt].req = r;
-          tiles[nt].pad = 0;
-          tiles[nt].begin = b;
-          tiles[nt].end = std::min<int64_t>(reqs[r].nq, b + p->tile_q);
-          ++nt;
-        }
+        ents[ne].req = r;
+        ents[ne].first = (int32_t)nt;
+        ++ne;
+        nt += (reqs[r].nq + hdr->tile[c] - 1) / hdr->tile[c];
       }
+      hdr->qtiles[c][x] = (int32_t)nt;
     }
-    hdr->qbound[c][kQueues] = (int32_t)nt;
+    hdr->qbound[c][kQueues] = ne;
   }
   hdr->nreq = nreq;
   hdr->sorted = p->sort ? 1 : 0;

@@ -100,7 +100,9 @@ struct mknn_server {
   std::vector<Slot> slots;
   hipStream_t del_stream = nullptr;
   std::mutex mu;
-  std::condition_variable cv_sched, cv_done;
+  std::condition_variable cv_sched, cv_done, cv_work;
+  std::atomic<bool> dirty{false};   // new operations or finished host work since the last pass
+  std::deque<int> plain_order;      // plain mode: busy slots in launch order (one stream)
   std::list<OpPtr> pending;         // arrival order
   int64_t pending_deletes = 0;
   std::unordered_map<uint64_t, OpPtr> ops;
@@ -118,6 +120,11 @@ struct mknn_server {
 };
 
 namespace mknn {
+
+static void wake_scheduler(mknn_server *s) {
+  s->dirty.store(true, std::memory_order_release);
+  s->cv_sched.notify_one();
+}
 
 static hipEvent_t take_event(mknn_server *s) {
   if (!s->free_events.empty()) {
@@ -180,6 +187,7 @@ static void launch_wave(mknn_server *s, int x, std::vector<OpPtr> &wave) {
   }
   (void)hipEventRecord(sl.ev, sl.stream);
   sl.busy = true;
+  if (s->plain) s->plain_order.push_back(x);
   for (const OpPtr &op : wave) sl.queries += op->req.nq;
   s->inflight_queries += sl.queries;
   ++s->waves;
@@ -190,7 +198,7 @@ static void worker_loop(mknn_server *s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
-    s->cv_sched.wait(lk, [&] { return s->stop || !s->del_queue.empty(); });
+    s->cv_work.wait(lk, [&] { return s->stop || !s->del_queue.empty(); });
     if (s->del_queue.empty()) {
       if (s->stop) return;
       continue;
@@ -203,44 +211,79 @@ static void worker_loop(mknn_server *s) {
     if (op->status != MKNN_OK) op->err = mknn_last_error();
     lk.lock();
     s->del_done.push_back(op);
-    s->cv_sched.notify_all();
+    wake_scheduler(s);
   }
 }
 
+static bool server_idle(const mknn_server *s) {
+  bool idle = s->pending.empty() && s->blocked.empty() && s->applying.empty();
+  for (const Slot &sl : s->slots) idle &= !sl.busy;
+  return idle;
+}
+
+// The scheduler thread owns the slots and the list of deltas being applied; it polls their
+// completion events without the lock, so submitters and waiters are not starved, and takes
+// the lock only when something finished or new work arrived.
 static void scheduler_loop(mknn_server *s) {
   (void)hipSetDevice(s->device);
-  std::unique_lock<std::mutex> lk(s->mu);
+  std::vector<int> done_slots;
+  std::vector<size_t> done_apps;
   for (;;) {
-    bool progress = false;
-    // ---- completions of waves
-    for (Slot &sl : s->slots) {
-      if (sl.busy && hipEventQuery(sl.ev) == hipSuccess) {
-        for (const OpPtr &op : sl.ops) finish_op(s, op, MKNN_OK, "");
-        sl.ops.clear();
-        sl.clouds.clear();
-        s->inflight_queries -= sl.queries;
-        sl.queries = 0;
-        sl.busy = false;
-        progress = true;
+    done_slots.clear();
+    done_apps.clear();
+    bool inflight = !s->applying.empty();
+    if (s->plain) {
+      // one stream: requests complete in launch order
+      for (int x : s->plain_order) {
+        if (hipEventQuery(s->slots[x].ev) != hipSuccess) break;
+        done_slots.push_back(x);
+      }
+      inflight |= !s->plain_order.empty();
+    } else {
+      for (int x = 0; x < (int)s->slots.size(); ++x) {
+        if (!s->slots[x].busy) continue;
+        inflight = true;
+        if (hipEventQuery(s->slots[x].ev) == hipSuccess) done_slots.push_back(x);
       }
     }
-    // ---- completions of applied deletions
-    for (size_t t = 0; t < s->applying.size();) {
-      if (hipEventQuery(s->applying[t].ev) == hipSuccess) {
-        finish_op(s, s->applying[t].op, MKNN_OK, "");
-        s->free_events.push_back(s->applying[t].ev);
-        s->applying.erase(s->applying.begin() + t);
-        progress = true;
-      } else {
-        ++t;
+    for (size_t t = 0; t < s->applying.size(); ++t)
+      if (hipEventQuery(s->applying[t].ev) == hipSuccess) done_apps.push_back(t);
+    const bool fresh = s->dirty.exchange(false, std::memory_order_acq_rel);
+    if (done_slots.empty() && done_apps.empty() && !fresh) {
+      if (inflight) {
+        std::this_thread::yield();
+        continue;
       }
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (s->stop && server_idle(s)) break;
+      s->cv_sched.wait_for(lk, std::chrono::milliseconds(2),
+                           [&] { return s->stop || s->dirty.load(std::memory_order_acquire); });
+      continue;
+    }
+    std::unique_lock<std::mutex> lk(s->mu);
+    // ---- completions of waves
+    for (int x : done_slots) {
+      Slot &sl = s->slots[x];
+      for (const OpPtr &op : sl.ops) finish_op(s, op, MKNN_OK, "");
+      sl.ops.clear();
+      sl.clouds.clear();
+      s->inflight_queries -= sl.queries;
+      sl.queries = 0;
+      sl.busy = false;
+      if (s->plain) s->plain_order.pop_front();
+    }
+    // ---- completions of applied deletions (indices ascending: erase from the back)
+    for (size_t t = done_apps.size(); t-- > 0;) {
+      Applying &ap = s->applying[done_apps[t]];
+      finish_op(s, ap.op, MKNN_OK, "");
+      s->free_events.push_back(ap.ev);
+      s->applying.erase(s->applying.begin() + (std::ptrdiff_t)done_apps[t]);
     }
     // ---- deletions whose host part finished: order the device delta after the waves that
     //      still read the cloud, then release the cloud
     while (!s->del_done.empty()) {
       OpPtr op = s->del_done.front();
       s->del_done.pop_front();
-      progress = true;
       mknn_cloud *c = op->cloud;
       if (op->status == MKNN_OK && op->delta.on_device) {
         const int64_t need = (int64_t)(op->delta.rec.size() / 4);
@@ -293,7 +336,6 @@ static void scheduler_loop(mknn_server *s) {
       }
       if (wave.empty()) break;   // the other free slots would find the same
       launch_wave(s, x, wave);
-      progress = true;
     }
     // ---- start deletions: one at a time per cloud, in arrival order; in strict order only
     //      once no earlier request on the cloud is still waiting
@@ -311,30 +353,15 @@ static void scheduler_loop(mknn_server *s) {
           s->blocked.insert(c);
           s->del_queue.push_back(op);
           --s->pending_deletes;
-          s->cv_sched.notify_all();
+          s->cv_work.notify_one();
           it = s->pending.erase(it);
-          progress = true;
         } else {
           del_held.insert(c);
           ++it;
         }
       }
     }
-    bool idle = s->pending.empty() && s->del_queue.empty() && s->del_done.empty() &&
-                s->applying.empty();
-    for (const Slot &sl : s->slots) idle &= !sl.busy;
-    if (s->stop && idle) break;
-    if (progress) continue;
-    bool inflight = !s->applying.empty() || !s->del_done.empty();
-    for (const Slot &sl : s->slots) inflight |= sl.busy;
-    if (inflight) {
-      // poll the completion events; submitters and workers get the lock meanwhile
-      lk.unlock();
-      std::this_thread::yield();
-      lk.lock();
-    } else {
-      s->cv_sched.wait_for(lk, std::chrono::milliseconds(5));
-    }
+    if (s->stop && server_idle(s)) break;
   }
 }
 
@@ -421,7 +448,7 @@ mknn_status mknn_server_submit(mknn_server *s, const mknn_request *req, int32_t 
     return MKNN_OK;
   }
   s->pending.push_back(op);
-  s->cv_sched.notify_all();
+  wake_scheduler(s);
   return MKNN_OK;
 }
 
@@ -442,7 +469,7 @@ mknn_status mknn_server_delete(mknn_server *s, mknn_cloud *c, const int32_t *ran
   s->ops[op->ticket] = op;
   s->pending.push_back(op);
   ++s->pending_deletes;
-  s->cv_sched.notify_all();
+  wake_scheduler(s);
   return MKNN_OK;
 }
 
@@ -487,12 +514,12 @@ void mknn_server_destroy(mknn_server *s) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
-    s->cv_sched.notify_all();
+    wake_scheduler(s);
   }
   if (s->sched.joinable()) s->sched.join();
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    s->cv_sched.notify_all();
+    s->cv_work.notify_all();
   }
   for (std::thread &t : s->workers)
     if (t.joinable()) t.join();

@@ -296,17 +296,24 @@ class ServingWorkload:
         lo, hi = bbox_expanded(c.points, 1.0)
         return Request(ci, uniform_in_box(rng, nq, lo, hi), k, m)
 
-    def deletion_plan(self, frac: float = 0.01, batch: int = 1000):
-        """Per cloud, `frac` of its ranks without replacement, split into batches <= batch."""
+    def deletion_plan(self, frac: float = 0.01, batch: int = 1000, parts: int = 1):
+        """Per cloud, `frac` of its ranks without replacement, split into batches <= batch,
+        in a seeded random order.  With parts > 1, returns that many such plans over
+        disjoint rank sets (one per run that deletes from the same clouds)."""
         rng = np.random.default_rng(np.random.SeedSequence(7).spawn(1)[0])
-        plan = []
+        plans = [[] for _ in range(parts)]
         for ci, c in enumerate(self.clouds):
             cnt = int(round(frac * c.n))
-            ranks = rng.choice(c.n, cnt, replace=False).astype(np.int32)
-            for s in range(0, cnt, batch):
-                plan.append((ci, ranks[s:s + batch]))
-        order = rng.permutation(len(plan))
-        return [plan[i] for i in order]
+            ranks = rng.choice(c.n, cnt * parts, replace=False).astype(np.int32)
+            for p in range(parts):
+                mine = ranks[p * cnt:(p + 1) * cnt]
+                for s in range(0, cnt, batch):
+                    plans[p].append((ci, mine[s:s + batch]))
+        out = []
+        for plan in plans:
+            order = rng.permutation(len(plan))
+            out.append([plan[i] for i in order])
+        return out[0] if parts == 1 else out
 
 
 def serving_clouds(num: int = 64, n_lo: int = 10_000, n_hi: int = 2_000_000,
