@@ -205,31 +205,36 @@ class _ServeRun:
         n = hi - lo
         lat = np.zeros(n)
         t_done = np.zeros(n)
+        t_wait = np.zeros(n)      # submitted -> launched
+        t_lag = np.zeros(n)       # scheduled arrival -> submitted
         state = {"collected": lo, "err": None}
         cv = threading.Condition()
 
         def collect():
-            a, b, v = ct.c_double(), ct.c_double(), ct.c_int64()
+            tt = (ct.c_double * 3)()
+            v = ct.c_int64()
             while True:
                 item = q.get()
                 if item is None:
                     return
                 i, tk, t_sched = item
-                st = L.mknn_server_wait(h, ct.c_uint64(tk), ct.byref(a), ct.byref(b), ct.byref(v))
+                st = L.mknn_server_wait(h, ct.c_uint64(tk), tt, ct.byref(v))
                 if st != 0 and state["err"] is None:
                     state["err"] = (i, st, L.mknn_last_error().decode())
-                if i >= 0:
-                    lat[i - lo] = b.value - t_sched
-                    t_done[i - lo] = b.value
-                    with cv:
-                        state["collected"] = i + 1
-                        cv.notify_all()
-                    if (i - lo + 1) % 5000 == 0:
-                        log(f"  {label}: {i - lo + 1}/{n} requests done")
+                lat[i - lo] = tt[2] - t_sched
+                t_done[i - lo] = tt[2]
+                t_lag[i - lo] = tt[0] - t_sched
+                t_wait[i - lo] = tt[1] - tt[0]
+                with cv:
+                    state["collected"] = i + 1
+                    cv.notify_all()
+                if (i - lo + 1) % 5000 == 0:
+                    log(f"  {label}: {i - lo + 1}/{n} requests done")
 
         th = threading.Thread(target=collect, daemon=True)
         th.start()
         dels = sorted(deletions, key=lambda d: d[0])
+        del_tickets = []   # waited for after the requests, so they never hold back the ring
         di = 0
         tk = ct.c_uint64()
         t0 = L.mknn_server_now() + 0.005
@@ -242,7 +247,7 @@ class _ServeRun:
                                           r.shape[0], ct.byref(tk))
                 if st != 0:
                     raise RuntimeError(L.mknn_last_error().decode())
-                q.put((-1, tk.value, 0.0))
+                del_tickets.append(tk.value)
                 srv._keep[tk.value] = (r,)
                 di += 1
             if state["collected"] < self.need[i]:
@@ -267,8 +272,14 @@ class _ServeRun:
             q.put((i, tk.value, t_sched))
         q.put(None)
         th.join()
+        tt = (ct.c_double * 3)()
+        for tk_ in del_tickets:
+            st = L.mknn_server_wait(h, ct.c_uint64(tk_), tt, None)
+            if st != 0 and state["err"] is None:
+                state["err"] = ("deletion", st, L.mknn_last_error().decode())
         if state["err"] is not None:
             raise RuntimeError(f"request {state['err']}")
+        self.parts = (t_lag, t_wait)
         return lat, t_done, t_first
 
 
@@ -281,6 +292,7 @@ def bench_serving(args) -> int:
     import torch
     from paper_2605_02224_amd import workloads as W
     from paper_2605_02224_amd import api as A
+    sys.setswitchinterval(2e-4)   # the submitter and the collector hand the GIL over quickly
     t0 = time.perf_counter()
     w = W.serving_clouds(num=args.clouds, n_hi=args.serving_n_hi)
     npts = sum(c.n for c in w.clouds)
@@ -291,7 +303,9 @@ def bench_serving(args) -> int:
     log(f"built and uploaded in {build_s:.1f} s")
     nwarm, nmeas, nsat = args.warm_requests, args.requests, args.sat_requests
     total = nsat + nwarm + nmeas
+    t0 = time.perf_counter()
     reqs = [w.request() for _ in range(total)]
+    log(f"{total} requests generated in {time.perf_counter() - t0:.1f} s")
     qoff = np.zeros(total + 1, np.int64)
     qoff[1:] = np.cumsum([r.queries.shape[0] for r in reqs])
     qd = torch.from_numpy(np.concatenate([r.queries for r in reqs])).cuda()
@@ -302,6 +316,8 @@ def bench_serving(args) -> int:
             torch.empty(cap, dtype=torch.float32).pin_memory())
     torch.cuda.synchronize()
     run = _ServeRun(reqs, qoff, qd, ring, clouds)
+    log(f"{int(qoff[-1])} queries resident, output ring of {cap} entries; host cpus "
+        f"{len(os.sched_getaffinity(0))}")
     nq_of = np.diff(qoff)
     pool = 1 << 22
     kw = dict(pool_queries=pool, nstreams=args.slots, max_wave_requests=256,
@@ -328,9 +344,12 @@ def bench_serving(args) -> int:
     rate = args.load * sat["plain"] / mean_nq
     rng = np.random.default_rng(11)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, hi - lo))
-    parts = w.deletion_plan(frac=0.01, batch=1000, parts=2)
+    parts = w.deletion_plan(frac=args.delete_frac, batch=1000, parts=2)
     res = {}
     for p, name in enumerate(("plain", "batched")):
+        for cl in clouds:          # both runs start from freshly packed lists
+            cl.compact()
+        torch.cuda.synchronize()
         pos = np.sort(rng.integers(lo + nwarm, hi, len(parts[p])))
         dels = [(int(pos[t]), ci, r) for t, (ci, r) in enumerate(parts[p])]
         srv = server(name == "plain")
@@ -340,17 +359,23 @@ def bench_serving(args) -> int:
         w_, r_ = srv.stats()
         srv.close()
         m = lat[nwarm:]
+        lag, wt = run.parts[0][nwarm:], run.parts[1][nwarm:]
         t_meas = t_first + arrivals[nwarm] - arrivals[0]
         served = float(nq_of[lo + nwarm:hi].sum() / (t_done[nwarm:].max() - t_meas))
         res[name] = {"p50_ms": round(float(np.percentile(m, 50)) * 1e3, 3),
                      "p99_ms": round(float(np.percentile(m, 99)) * 1e3, 3),
                      "mean_ms": round(float(m.mean()) * 1e3, 3),
+                     "mean_submit_lag_ms": round(float(lag.mean()) * 1e3, 3),
+                     "mean_queue_wait_ms": round(float(wt.mean()) * 1e3, 3),
+                     "p99_queue_wait_ms": round(float(np.percentile(wt, 99)) * 1e3, 3),
                      "served_qps": round(served, 1),
                      "requests_per_wave": round(r_ / max(w_, 1), 2),
                      "deletion_batches": len(dels),
                      "wall_s": round(time.perf_counter() - t0, 2)}
         log(f"{name} open loop: p50 {res[name]['p50_ms']} ms, p99 {res[name]['p99_ms']} ms, "
-            f"{served / 1e6:.1f} M queries/s served")
+            f"{served / 1e6:.1f} M queries/s served; mean submit lag "
+            f"{res[name]['mean_submit_lag_ms']} ms, mean queue wait "
+            f"{res[name]['mean_queue_wait_ms']} ms")
     line = {
         "metric": "k-NN queries/sec (k=16, 1M-pt surface) + p50/p99 latency, batched vs plain",
         "value": round(sat["batched"], 1), "unit": "queries/s", "n_gpus": 1,
@@ -383,6 +408,8 @@ def main() -> int:
     ap.add_argument("--load", type=float, default=0.7, help="serving: x plain saturation")
     ap.add_argument("--slots", type=int, default=2, help="serving: stream slots")
     ap.add_argument("--serving-n-hi", type=int, default=2_000_000)
+    ap.add_argument("--delete-frac", type=float, default=0.01,
+                    help="serving: fraction of each cloud deleted during a run")
     ap.add_argument("--clouds", type=int, default=256)
     ap.add_argument("--tile", type=int, default=1024)
     ap.add_argument("--gpus", type=int, default=1)

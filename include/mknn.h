@@ -90,6 +90,12 @@ mknn_status mknn_points_by_rank(const mknn_cloud *c, const float **xyz);
  */
 mknn_status mknn_upload(mknn_cloud *c, void *stream);
 
+/* mknn_compact: packs the device lists of an uploaded cloud again, in the upload layout,
+ * which gives back the arena slack that deletion deltas have used.  Synchronises `stream`;
+ * no query on the cloud may be in flight on another stream.  Errors: EINVAL (not uploaded),
+ * EHIP, ENOMEM. */
+mknn_status mknn_compact(mknn_cloud *c, void *stream);
+
 /* Bytes of device memory the uploaded cloud occupies. */
 int64_t mknn_device_bytes(const mknn_cloud *c);
 
@@ -265,12 +271,13 @@ mknn_status mknn_server_delete(mknn_server *s, mknn_cloud *c, const int32_t *ran
                                uint64_t *ticket);
 /* *done = 1 once the operation has completed. */
 mknn_status mknn_server_poll(mknn_server *s, uint64_t ticket, int32_t *done);
-/* Block until the operation completes, then forget the ticket.  t_submit / t_done (may be
- * NULL) receive the submission time and the time completion was observed, in seconds of
- * mknn_server_now().  deletions_seen (may be NULL) receives, for a request, the number of
- * deletion batches of this server applied to its cloud when it was launched.  Returns the
- * operation's own status. */
-mknn_status mknn_server_wait(mknn_server *s, uint64_t ticket, double *t_submit, double *t_done,
+/* Block until the operation completes, then forget the ticket.  times (may be NULL)
+ * receives, in seconds of mknn_server_now(): [0] submission, [1] launch (a request's wave
+ * was launched; a deletion's device delta was enqueued), [2] completion observed (after the
+ * copies to host memory).  deletions_seen (may be NULL) receives, for a request, the number
+ * of deletion batches of this server applied to its cloud when it was launched.  Returns
+ * the operation's own status. */
+mknn_status mknn_server_wait(mknn_server *s, uint64_t ticket, double *times,
                              int64_t *deletions_seen);
 /* Waves launched so far and the requests they held. */
 mknn_status mknn_server_stats(mknn_server *s, int64_t *waves, int64_t *wave_requests);

@@ -25,6 +25,7 @@ SIGNATURES = {
     "mknn_successors": (ctypes.c_int, [_P, _PP, _PP, ctypes.POINTER(_I64)]),
     "mknn_points_by_rank": (ctypes.c_int, [_P, _PP]),
     "mknn_upload": (ctypes.c_int, [_P, _P]),
+    "mknn_compact": (ctypes.c_int, [_P, _P]),
     "mknn_device_bytes": (_I64, [_P]),
     "mknn_knn": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P]),
     "mknn_knn_var": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P]),
@@ -60,7 +61,7 @@ SIGNATURES.update({
     "mknn_server_delete": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(ctypes.c_uint64)]),
     "mknn_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_I32)]),
     "mknn_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
-                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+                                        ctypes.POINTER(_I64)]),
     "mknn_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "mknn_server_now": (ctypes.c_double, []),
     "mknn_server_destroy": (None, [_P]),

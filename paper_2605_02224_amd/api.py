@@ -105,6 +105,11 @@ class Cloud:
         check(_lib.lib().mknn_upload(self._h, _stream(stream)))
         return self
 
+    def compact(self, stream=None) -> "Cloud":
+        """Pack the device lists again, giving back the slack used by deletion deltas."""
+        check(_lib.lib().mknn_compact(self._h, _stream(stream)))
+        return self
+
     @property
     def device_bytes(self) -> int:
         return int(_lib.lib().mknn_device_bytes(self._h))
@@ -261,14 +266,14 @@ class Server:
 
     def wait(self, ticket, with_seen: bool = False):
         """Block until done; returns (submit_time, done_time, buffers[, deletions_seen])."""
-        a, b, v = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-        st = _lib.lib().mknn_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(a),
-                                         ctypes.byref(b), ctypes.byref(v))
+        t = (ctypes.c_double * 3)()
+        v = ctypes.c_int64()
+        st = _lib.lib().mknn_server_wait(self._h, ctypes.c_uint64(ticket), t, ctypes.byref(v))
         bufs = self._keep.pop(ticket, None)
         check(st)
         if with_seen:
-            return a.value, b.value, bufs, v.value
-        return a.value, b.value, bufs
+            return t[0], t[2], bufs, v.value
+        return t[0], t[2], bufs
 
     def stats(self):
         w, r = ctypes.c_int64(), ctypes.c_int64()

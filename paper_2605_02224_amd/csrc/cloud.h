@@ -27,12 +27,26 @@ struct DynLists {
   void clear(int64_t r) { len[r] = 0; }
 };
 // List segments rewritten by a deletion batch, ready to be appended to the device arena.
+// The whole device image of the lists: records {x, y, z, rank bits} of every list, lists in
+// the Morton order of their owners, then padding; one {start, length} descriptor per rank.
+struct HostPack {
+  std::vector<float> ent;          // 4 floats per record
+  std::vector<uint64_t> lst;
+  int64_t nnz = 0;                 // records in use
+  int64_t cap = 0;                 // records to allocate (slack for later deltas + padding)
+};
+// List segments rewritten by a deletion batch, ready to be appended to the device arena, or,
+// when the arena's slack would run out, a complete new image of the lists.
 struct DeviceDelta {
   bool on_device = false;
   std::vector<int32_t> ranks;      // lists that changed
   std::vector<uint32_t> lens;      // their new lengths
   std::vector<float> rec;          // their new records {x, y, z, rank bits}, concatenated
   std::vector<uint64_t> desc;      // new descriptors (filled when applied)
+  bool repack = false;             // apply `pack` as a new arena instead
+  HostPack pack;
+  void *old_ent = nullptr;         // arena replaced by a re-pack: free once its readers are done
+  uint64_t *old_lst = nullptr;
 };
 }  // namespace mknn
 

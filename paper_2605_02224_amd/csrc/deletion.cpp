@@ -116,8 +116,8 @@ struct NewEntry {
 };
 
 // Redistribution for one deleted rank; fills `adds` with the new (owner, rank) entries.
-mknn_status redistribute(mknn_cloud *c, int32_t i, const std::vector<double> &P,
-                         std::vector<NewEntry> *adds) {
+mknn_status redistribute(mknn_cloud *c, int32_t i, std::vector<NewEntry> *adds) {
+  const float *P = c->xyz.data();
   std::vector<int32_t> loc;   // local set by ascending rank: pred[i] then L_i
   const int32_t np = c->dpred.size(i), ns = c->dsucc.size(i);
   loc.insert(loc.end(), c->dpred.begin(i), c->dpred.begin(i) + np);
@@ -126,8 +126,10 @@ mknn_status redistribute(mknn_cloud *c, int32_t i, const std::vector<double> &P,
   if (ns == 0) return MKNN_OK;
   std::vector<double> lp(3 * L);
   for (int64_t t = 0; t < L; ++t)
-    for (int d = 0; d < 3; ++d) lp[3 * t + d] = P[3 * (int64_t)loc[t] + d];
-  const double *pi = &P[3 * (int64_t)i];
+    for (int d = 0; d < 3; ++d) lp[3 * t + d] = (double)P[3 * (int64_t)loc[t] + d];
+  double pi_xyz[3];
+  for (int d = 0; d < 3; ++d) pi_xyz[d] = (double)P[3 * (int64_t)i + d];
+  const double *pi = pi_xyz;
   DelaunayBuilder dt(lp.data(), L);
   int64_t inserted = 0;   // local ids inserted into dt
   for (int64_t t = np; t < L; ++t) {
@@ -188,12 +190,11 @@ mknn_status delete_ranks_host(mknn_cloud *c, const int32_t *ranks, int64_t count
       c->dpred.from_csr(c->pred, c->n);
       c->editable = true;
     }
-    std::vector<double> P(c->xyz.begin(), c->xyz.end());
     std::vector<char> mark(c->n, 0);
     std::vector<NewEntry> adds;
     for (int32_t i : del) {
       adds.clear();
-      mknn_status st = redistribute(c, i, P, &adds);
+      mknn_status st = redistribute(c, i, &adds);
       if (st != MKNN_OK) {
         if (i != del.front()) {
           // earlier ranks of the batch are already applied: the host lists have moved on,

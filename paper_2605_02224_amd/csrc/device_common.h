@@ -97,11 +97,16 @@ inline void fill_cloud_args(const mknn_cloud *c, QueryArgs *a) {
 }
 
 // Deletion split in two: delete_prepare edits the host lists and gathers the rewritten
-// list segments; delete_apply enqueues their copy and the descriptor switch on a stream
-// (asynchronously, except that running out of arena slack re-packs synchronously).  The
-// delta must stay alive until the stream has executed the copies.
+// list segments (or, when the arena's slack would run out, a complete new image of the
+// lists); delete_apply enqueues their copy and the descriptor switch (or the switch to a new
+// arena) on a stream, asynchronously.  The delta must stay alive until the stream has
+// executed the copies.
 mknn_status delete_prepare(mknn_cloud *c, const int32_t *ranks, int64_t count, DeviceDelta *d);
 mknn_status delete_apply(mknn_cloud *c, DeviceDelta *d, hipStream_t s);
+// After a re-pack, the replaced arena is freed by the caller once no work reads it.
+void release_old_arena(DeviceDelta *d);
+mknn_status pack_lists(mknn_cloud *c, HostPack *p);
+mknn_status install_pack(mknn_cloud *c, const HostPack *p, hipStream_t s);
 extern "C" mknn_status mknn_upload(mknn_cloud *c, void *stream);
 
 // Optional HIP-event timing of the main query kernels (defined in mknn_device.hip).

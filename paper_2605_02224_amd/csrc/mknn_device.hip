@@ -276,6 +276,90 @@ __global__ __launch_bounds__(256) void apply_descriptors_kernel(uint64_t *lst, c
   if (t < cnt) lst[r[t]] = desc[t];
 }
 
+void release_old_arena(DeviceDelta *d) {
+  if (d->old_ent) (void)hipFree(d->old_ent);
+  if (d->old_lst) (void)hipFree(d->old_lst);
+  d->old_ent = nullptr;
+  d->old_lst = nullptr;
+}
+
+// ---- the device image of the lists
+mknn_status pack_lists(mknn_cloud *c, HostPack *p) {
+  try {
+    const int64_t n = c->n;
+    // list placement: owners in Morton order
+    BoxArgs b = box_of(c);
+    std::vector<uint64_t> key(n);
+    for (int64_t r = 0; r < n; ++r) {
+      const uint64_t code = morton30(c->xyz[3 * r], c->xyz[3 * r + 1], c->xyz[3 * r + 2], b);
+      key[r] = (code << 32) | (uint64_t)r;
+    }
+    std::sort(key.begin(), key.end());
+    refresh_csr(c);
+    const int64_t nnz = (int64_t)c->succ.ent.size();
+    // slack for list rewrites after deletions (copy-on-write segments): half the records.
+    // A deleted point rewrites about 25 lists of about 7.5 entries, so this covers deleting
+    // about 2% of the points before a re-pack.
+    const int64_t cap = nnz + std::max<int64_t>(nnz / 2, 1 << 16) + kEntPad;
+    if (cap > (int64_t)0xffffffffll)
+      return set_error(MKNN_EUNSUPPORTED, "mknn_upload: more than 2^32 list entries");
+    p->ent.assign((size_t)(nnz + kEntPad) * 4, 0.f);
+    p->lst.resize((size_t)n);
+    uint64_t cur = 0;
+    for (int64_t t = 0; t < n; ++t) {
+      int64_t r = (int64_t)(key[t] & 0xffffffffu);
+      int64_t b0 = c->succ.off[r], b1 = c->succ.off[r + 1];
+      p->lst[r] = cur | ((uint64_t)(b1 - b0) << 32);
+      for (int64_t e = b0; e < b1; ++e) {
+        int32_t j = c->succ.ent[e];
+        float *v = &p->ent[cur * 4];
+        v[0] = c->xyz[3 * (int64_t)j];
+        v[1] = c->xyz[3 * (int64_t)j + 1];
+        v[2] = c->xyz[3 * (int64_t)j + 2];
+        std::memcpy(&v[3], &j, 4);
+        ++cur;
+      }
+    }
+    for (int q = 0; q < kEntPad; ++q) {
+      const int32_t big = kEmpty;
+      std::memcpy(&p->ent[(cur + q) * 4 + 3], &big, 4);
+    }
+    p->nnz = nnz;
+    p->cap = cap;
+  } catch (const std::bad_alloc &) {
+    return set_error(MKNN_ENOMEM, "mknn_upload: out of host memory");
+  }
+  return MKNN_OK;
+}
+
+// Allocate a new arena for `p` on the current device and enqueue its copy on `s`.  The
+// host image must stay alive until `s` has passed the copies.  The previous arena is not
+// touched; c->d_ent / c->d_lst are replaced.
+mknn_status install_pack(mknn_cloud *c, const HostPack *p, hipStream_t s) {
+  void *ent = nullptr;
+  uint64_t *lst = nullptr;
+  hipError_t e = hipMalloc(&ent, sizeof(float4) * (size_t)p->cap);
+  if (e == hipSuccess) e = hipMalloc((void **)&lst, sizeof(uint64_t) * p->lst.size());
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ent, p->ent.data(), sizeof(float) * p->ent.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(lst, p->lst.data(), sizeof(uint64_t) * p->lst.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    if (ent) (void)hipFree(ent);
+    if (lst) (void)hipFree(lst);
+    return set_error(e == hipErrorOutOfMemory ? MKNN_ENOMEM : MKNN_EHIP,
+                     std::string("mknn_upload: ") + hipGetErrorName(e));
+  }
+  c->d_ent = ent;
+  c->d_lst = lst;
+  c->dev_bytes = (int64_t)(sizeof(float4) * (size_t)p->cap + sizeof(uint64_t) * p->lst.size());
+  c->ent_used = p->nnz;
+  c->ent_cap = p->cap - kEntPad;
+  c->dev_head = c->head;
+  c->dev_version = c->version.load();
+  return MKNN_OK;
+}
+
 // ---- deletion: host preparation and device application of the list deltas
 mknn_status delete_prepare(mknn_cloud *c, const int32_t *ranks, int64_t count, DeviceDelta *d) {
   d->on_device = c->d_ent && c->dev_version == c->version;
@@ -287,11 +371,18 @@ mknn_status delete_prepare(mknn_cloud *c, const int32_t *ranks, int64_t count, D
     return MKNN_OK;
   }
   // on the device the version moves when the delta is applied
+  int64_t need = 0;
+  for (int32_t r : changed) need += c->dsucc.size(r);
+  if (c->ent_used + need > c->ent_cap) {
+    // out of slack: build a complete new image here, off the caller's launch path
+    d->repack = true;
+    st = pack_lists(c, &d->pack);
+    if (st != MKNN_OK) ++c->version;   // the host lists have moved on without the device
+    return st;
+  }
   try {
     // copy-on-write: every changed list gets a fresh segment at the end of the arena, so
     // work that already read the old descriptor keeps reading the old, untouched records
-    int64_t need = 0;
-    for (int32_t r : changed) need += c->dsucc.size(r);
     d->ranks = changed;
     d->lens.resize(changed.size());
     d->rec.resize((size_t)need * 4);
@@ -312,6 +403,7 @@ mknn_status delete_prepare(mknn_cloud *c, const int32_t *ranks, int64_t count, D
       cur += len;
     }
   } catch (const std::bad_alloc &) {
+    ++c->version;
     return set_error(MKNN_ENOMEM, "mknn_delete: out of host memory");
   }
   return MKNN_OK;
@@ -321,11 +413,15 @@ mknn_status delete_apply(mknn_cloud *c, DeviceDelta *d, hipStream_t s) {
   if (!d->on_device) return MKNN_OK;
   ++c->version;   // the device copy is stale until the delta below is complete
   const int64_t need = (int64_t)(d->rec.size() / 4);
-  if (c->ent_used + need > c->ent_cap) {
-    // out of slack: pack everything again once the stream's earlier work is done
-    HIP_TRY(hipStreamSynchronize(s), "mknn_delete: synchronize before re-pack");
-    d->rec.clear();
-    return mknn_upload(c, s);
+  if (d->repack) {
+    // a new arena; the old one is kept for the work that still reads it (d->old_*)
+    void *old_ent = c->d_ent;
+    uint64_t *old_lst = c->d_lst;
+    mknn_status st = install_pack(c, &d->pack, s);
+    if (st != MKNN_OK) return st;
+    d->old_ent = old_ent;
+    d->old_lst = old_lst;
+    return MKNN_OK;
   }
   d->desc.resize(d->ranks.size());
   int64_t cur = 0;
@@ -533,64 +629,33 @@ mknn_status mknn_upload(mknn_cloud *c, void *stream) {
   HIP_TRY(hipGetDevice(&dev), "mknn_upload: hipGetDevice");
   if (c->d_ent && c->dev_version == c->version && c->device == dev) return MKNN_OK;
   hipStream_t s = (hipStream_t)stream;
-  try {
-    const int64_t n = c->n;
-    // list placement: owners in Morton order
-    BoxArgs b = box_of(c);
-    std::vector<uint64_t> key(n);
-    for (int64_t r = 0; r < n; ++r) {
-      const uint64_t code = morton30(c->xyz[3 * r], c->xyz[3 * r + 1], c->xyz[3 * r + 2], b);
-      key[r] = (code << 32) | (uint64_t)r;
-    }
-    std::sort(key.begin(), key.end());
-    refresh_csr(c);
-    const int64_t nnz = (int64_t)c->succ.ent.size();
-    // slack for list rewrites after deletions (copy-on-write segments)
-    const int64_t cap = nnz + std::max<int64_t>(nnz / 8, 1 << 16) + kEntPad;
-    if (cap > (int64_t)0xffffffffll)
-      return set_error(MKNN_EUNSUPPORTED, "mknn_upload: more than 2^32 list entries");
-    std::vector<float4> ent((size_t)(nnz + kEntPad));
-    std::vector<uint64_t> lst((size_t)n);
-    uint64_t cur = 0;
-    for (int64_t t = 0; t < n; ++t) {
-      int64_t r = (int64_t)(key[t] & 0xffffffffu);
-      int64_t b0 = c->succ.off[r], b1 = c->succ.off[r + 1];
-      lst[r] = cur | ((uint64_t)(b1 - b0) << 32);
-      for (int64_t e = b0; e < b1; ++e) {
-        int32_t j = c->succ.ent[e];
-        float4 v;
-        v.x = c->xyz[3 * (int64_t)j];
-        v.y = c->xyz[3 * (int64_t)j + 1];
-        v.z = c->xyz[3 * (int64_t)j + 2];
-        std::memcpy(&v.w, &j, 4);
-        ent[cur++] = v;
-      }
-    }
-    for (int p = 0; p < kEntPad; ++p) {
-      int32_t big = kEmpty;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      std::memcpy(&v.w, &big, 4);
-      ent[cur + p] = v;
-    }
+  HostPack pack;
+  mknn_status st = pack_lists(c, &pack);
+  if (st != MKNN_OK) return st;
+  free_device(c);
+  c->device = dev;
+  st = install_pack(c, &pack, s);
+  if (st != MKNN_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s), "mknn_upload: synchronize");
+  return MKNN_OK;
+}
 
-    free_device(c);
-    c->device = dev;
-    HIP_TRY(hipMalloc(&c->d_ent, sizeof(float4) * (size_t)cap), "mknn_upload: hipMalloc entries");
-    HIP_TRY(hipMalloc((void **)&c->d_lst, sizeof(uint64_t) * lst.size()), "mknn_upload: hipMalloc lists");
-
-    HIP_TRY(hipMemcpyAsync(c->d_ent, ent.data(), sizeof(float4) * ent.size(), hipMemcpyHostToDevice, s),
-            "mknn_upload: copy entries");
-    HIP_TRY(hipMemcpyAsync(c->d_lst, lst.data(), sizeof(uint64_t) * lst.size(), hipMemcpyHostToDevice, s),
-            "mknn_upload: copy lists");
-    HIP_TRY(hipStreamSynchronize(s), "mknn_upload: synchronize");
-    c->dev_bytes = (int64_t)(sizeof(float4) * (size_t)cap + sizeof(uint64_t) * lst.size());
-    c->ent_used = nnz;
-    c->ent_cap = cap - kEntPad;
-    c->dev_head = c->head;
-    c->dev_version = c->version.load();
-  } catch (const std::bad_alloc &) {
-    return set_error(MKNN_ENOMEM, "mknn_upload: out of host memory");
-  }
+mknn_status mknn_compact(mknn_cloud *c, void *stream) {
+  clear_error();
+  if (!c) return set_error(MKNN_EINVAL, "mknn_compact: cloud is NULL");
+  mknn_status st = check_uploaded(c, "mknn_compact");
+  if (st != MKNN_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  HostPack pack;
+  st = pack_lists(c, &pack);
+  if (st != MKNN_OK) return st;
+  DeviceDelta old;
+  old.old_ent = c->d_ent;
+  old.old_lst = c->d_lst;
+  st = install_pack(c, &pack, s);
+  if (st != MKNN_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s), "mknn_compact: synchronize");
+  release_old_arena(&old);
   return MKNN_OK;
 }
 
@@ -678,6 +743,7 @@ mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void
   st = delete_apply(c, &d, s);
   if (st != MKNN_OK) return st;
   HIP_TRY(hipStreamSynchronize(s), "mknn_delete: synchronize");
+  release_old_arena(&d);
   return MKNN_OK;
 }
 

@@ -30,6 +30,8 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <condition_variable>
 #include <deque>
 #include <list>
@@ -59,7 +61,7 @@ struct ServerOp {
   mknn_cloud *cloud = nullptr;
   std::vector<int32_t> ranks;
   DeviceDelta delta;
-  double t_submit = 0, t_done = 0;
+  double t_submit = 0, t_launch = 0, t_done = 0;
   int64_t seen = 0;                 // deletion batches applied to the cloud at launch
   mknn_status status = MKNN_OK;
   std::string err;
@@ -117,6 +119,10 @@ struct mknn_server {
   bool stop = false;
   uint64_t next_ticket = 1;
   int64_t waves = 0, wave_requests = 0;
+  // seconds the scheduler spent launching waves, applying deltas and freeing old arenas,
+  // and host seconds of the workers' deletion work (printed at destroy if MKNN_SERVER_TRACE)
+  double t_launch = 0, t_apply = 0, t_release = 0, t_prepare = 0;
+  int64_t repacks = 0;
 };
 
 namespace mknn {
@@ -150,7 +156,9 @@ static void launch_wave(mknn_server *s, int x, std::vector<OpPtr> &wave) {
   Slot &sl = s->slots[x];
   sl.ops = wave;
   sl.clouds.clear();
+  const double t_launch = now_s();
   for (const OpPtr &op : wave) {
+    op->t_launch = t_launch;
     sl.clouds.insert(op->cloud);
     auto it = s->applied.find(op->cloud);
     op->seen = it == s->applied.end() ? 0 : it->second;
@@ -206,10 +214,13 @@ static void worker_loop(mknn_server *s) {
     OpPtr op = s->del_queue.front();
     s->del_queue.pop_front();
     lk.unlock();
-    // host part of Alg. 3: the cloud is held back from new waves meanwhile
+    // host part of Alg. 3
+    const double t0 = now_s();
     op->status = delete_prepare(op->cloud, op->ranks.data(), (int64_t)op->ranks.size(), &op->delta);
     if (op->status != MKNN_OK) op->err = mknn_last_error();
+    const double dt = now_s() - t0;
     lk.lock();
+    s->t_prepare += dt;
     s->del_done.push_back(op);
     wake_scheduler(s);
   }
@@ -275,6 +286,11 @@ static void scheduler_loop(mknn_server *s) {
     // ---- completions of applied deletions (indices ascending: erase from the back)
     for (size_t t = done_apps.size(); t-- > 0;) {
       Applying &ap = s->applying[done_apps[t]];
+      if (ap.op->delta.old_ent) {
+        const double t0 = now_s();
+        release_old_arena(&ap.op->delta);
+        s->t_release += now_s() - t0;
+      }
       finish_op(s, ap.op, MKNN_OK, "");
       s->free_events.push_back(ap.ev);
       s->applying.erase(s->applying.begin() + (std::ptrdiff_t)done_apps[t]);
@@ -286,14 +302,15 @@ static void scheduler_loop(mknn_server *s) {
       s->del_done.pop_front();
       mknn_cloud *c = op->cloud;
       if (op->status == MKNN_OK && op->delta.on_device) {
-        const int64_t need = (int64_t)(op->delta.rec.size() / 4);
-        const bool repack = c->ent_used + need > c->ent_cap;
-        for (Slot &sl : s->slots) {
-          if (!sl.busy || !sl.clouds.count(c)) continue;
-          if (repack) (void)hipEventSynchronize(sl.ev);   // the arena is replaced
-          else (void)hipStreamWaitEvent(s->del_stream, sl.ev, 0);
-        }
+        // the in-flight waves on this cloud finish before the switch (and before a replaced
+        // arena is freed, when the applied event completes)
+        for (Slot &sl : s->slots)
+          if (sl.busy && sl.clouds.count(c)) (void)hipStreamWaitEvent(s->del_stream, sl.ev, 0);
+        const double t0 = now_s();
+        op->t_launch = t0;
+        s->repacks += op->delta.repack ? 1 : 0;
         mknn_status st = delete_apply(c, &op->delta, s->del_stream);
+        s->t_apply += now_s() - t0;
         if (st != MKNN_OK) {
           op->status = st;
           op->err = mknn_last_error();
@@ -335,7 +352,9 @@ static void scheduler_loop(mknn_server *s) {
         it = s->pending.erase(it);
       }
       if (wave.empty()) break;   // the other free slots would find the same
+      const double t0 = now_s();
       launch_wave(s, x, wave);
+      s->t_launch += now_s() - t0;
     }
     // ---- start deletions: one at a time per cloud, in arrival order; in strict order only
     //      once no earlier request on the cloud is still waiting
@@ -483,7 +502,7 @@ mknn_status mknn_server_poll(mknn_server *s, uint64_t ticket, int32_t *done) {
   return MKNN_OK;
 }
 
-mknn_status mknn_server_wait(mknn_server *s, uint64_t ticket, double *t_submit, double *t_done,
+mknn_status mknn_server_wait(mknn_server *s, uint64_t ticket, double *times,
                              int64_t *deletions_seen) {
   clear_error();
   if (!s) return set_error(MKNN_EINVAL, "mknn_server_wait: server is NULL");
@@ -493,8 +512,11 @@ mknn_status mknn_server_wait(mknn_server *s, uint64_t ticket, double *t_submit, 
   OpPtr op = it->second;
   s->cv_done.wait(lk, [&] { return op->done; });
   s->ops.erase(ticket);
-  if (t_submit) *t_submit = op->t_submit;
-  if (t_done) *t_done = op->t_done;
+  if (times) {
+    times[0] = op->t_submit;
+    times[1] = op->t_launch;
+    times[2] = op->t_done;
+  }
   if (deletions_seen) *deletions_seen = op->seen;
   if (op->status != MKNN_OK) return set_error(op->status, op->err);
   return MKNN_OK;
@@ -517,6 +539,12 @@ void mknn_server_destroy(mknn_server *s) {
     wake_scheduler(s);
   }
   if (s->sched.joinable()) s->sched.join();
+  if (std::getenv("MKNN_SERVER_TRACE"))
+    std::fprintf(stderr,
+                 "[mknn server] waves %lld (requests %lld): launch %.3f s, apply %.3f s "
+                 "(%lld re-packs), arena release %.3f s, deletion host work %.3f s\n",
+                 (long long)s->waves, (long long)s->wave_requests, s->t_launch, s->t_apply,
+                 (long long)s->repacks, s->t_release, s->t_prepare);
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->cv_work.notify_all();

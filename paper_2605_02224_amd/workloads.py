@@ -293,7 +293,9 @@ class ServingWorkload:
         nq = max(1, min(self.max_nq, nq))
         k = int(rng.choice(np.asarray(self.k_choices)))
         m = int(rng.integers(int(math.ceil(c.n / 10)), c.n + 1))
-        lo, hi = bbox_expanded(c.points, 1.0)
+        if not hasattr(self, "_boxes"):
+            self._boxes = [bbox_expanded(cc.points, 1.0) for cc in self.clouds]
+        lo, hi = self._boxes[ci]
         return Request(ci, uniform_in_box(rng, nq, lo, hi), k, m)
 
     def deletion_plan(self, frac: float = 0.01, batch: int = 1000, parts: int = 1):

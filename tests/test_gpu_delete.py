@@ -85,3 +85,29 @@ def test_repack_when_slack_runs_out(env):
         cl.delete(dead[b:b + 250])
         live[dead[b:b + 250]] = 0
         assert _check(env, cl, P, live, Q, 12) <= 2
+
+
+def test_compact_after_deletions_keeps_results(env):
+    """Re-packing the device lists after deletions gives back the slack and changes no
+    result bit."""
+    torch, oracle, A, W = env
+    c = W.random_cloud(20000, seed=24, shape="ellipsoid")
+    P = c.by_rank
+    cl = A.Cloud.build(P).upload()
+    rng = np.random.default_rng(8)
+    dead = rng.choice(20000, 600, replace=False)
+    for b in range(0, 600, 200):
+        cl.delete(dead[b:b + 200])
+    Q = W.uniform_in_box(rng, 20000, *W.bbox_expanded(P, 1.1))
+    qd = torch.from_numpy(Q).cuda()
+    before = cl.knn(qd, 20)
+    torch.cuda.synchronize()
+    cl.compact()
+    after = cl.knn(qd, 20)
+    torch.cuda.synchronize()
+    assert torch.equal(before[0], after[0]) and torch.equal(before[1], after[1])
+    live = np.ones(20000, np.uint8)
+    live[dead] = 0
+    ri, _, rD = oracle.knn_bruteforce(P, Q[:1500], 21, live=live)
+    compare_rows(after[0].cpu().numpy()[:1500], after[1].cpu().numpy()[:1500], ri[:, :20],
+                 rD[:, :20], rD[:, 20])
