@@ -109,6 +109,9 @@ mknn_status pack_lists(mknn_cloud *c, HostPack *p);
 mknn_status install_pack(mknn_cloud *c, const HostPack *p, hipStream_t s);
 extern "C" mknn_status mknn_upload(mknn_cloud *c, void *stream);
 
+// Candidates per chunk from which the k <= 16 path merges with a network (MKNN_MERGE_MIN).
+int32_t merge_min();
+
 // Optional HIP-event timing of the main query kernels (defined in mknn_device.hip).
 hipError_t timing_mark(hipStream_t s, bool start);
 bool timing_enabled();

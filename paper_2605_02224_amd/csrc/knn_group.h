@@ -18,6 +18,8 @@
 //
 // Every branch a cross-lane operation depends on is uniform across the 16 lanes of a row.
 #pragma once
+#include <utility>
+
 #include "knn_kernels.h"
 
 namespace mknn {
@@ -48,6 +50,63 @@ __device__ __forceinline__ double dpp_f64(double old, double x) {
   const int32_t lo = dpp_i32<CTRL>((int32_t)o, (int32_t)v);
   const int32_t hi = dpp_i32<CTRL>((int32_t)(o >> 32), (int32_t)(v >> 32));
   return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+// Lane l ^ J within a row of 16, for the compare-exchange stages of a bitonic network.
+template <int J>
+__device__ __forceinline__ int32_t xor_lane(int32_t x) {
+  if constexpr (J == 1) return __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xf, 0xf, false);  // quad_perm 1,0,3,2
+  if constexpr (J == 2) return __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xf, 0xf, false);  // quad_perm 2,3,0,1
+  if constexpr (J == 4) return __builtin_amdgcn_ds_swizzle(x, 0x101F);   // bitmask mode, xor 4
+  if constexpr (J == 8) return __builtin_amdgcn_update_dpp(x, x, 0x128, 0xf, 0xf, false);  // row_ror:8
+  return x;
+}
+
+template <int J>
+__device__ __forceinline__ double xor_lane_f64(double x) {
+  const int64_t v = __double_as_longlong(x);
+  const int32_t lo = xor_lane<J>((int32_t)v), hi = xor_lane<J>((int32_t)(v >> 32));
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+// One compare-exchange stage between lanes l and l ^ J: the lane keeps the smaller key if
+// keep_min, else the larger.  Equal keys only occur between identical padding entries.
+template <int J>
+__device__ __forceinline__ void cas_stage(double &d, int32_t &r, bool keep_min) {
+  const double pd = xor_lane_f64<J>(d);
+  const int32_t pr = xor_lane<J>(r);
+  const bool take = key_less(pd, pr, d, r) == keep_min;
+  d = take ? pd : d;
+  r = take ? pr : r;
+}
+
+// Bitonic sort of one key per lane across the row; DESC sorts descending.
+template <bool DESC>
+__device__ __forceinline__ void row_sort16(double &d, int32_t &r, int l) {
+#define MKNN_CAS(K, J) cas_stage<J>(d, r, ((l & (J)) == 0) == ((((l & (K)) == 0)) != DESC))
+  MKNN_CAS(2, 1);
+  MKNN_CAS(4, 2);
+  MKNN_CAS(4, 1);
+  MKNN_CAS(8, 4);
+  MKNN_CAS(8, 2);
+  MKNN_CAS(8, 1);
+  MKNN_CAS(16, 8);
+  MKNN_CAS(16, 4);
+  MKNN_CAS(16, 2);
+  MKNN_CAS(16, 1);
+#undef MKNN_CAS
+}
+
+// Whether v equals any lane's x in the row: row_ror:t for t = 1..15 passes every value of
+// the row by every lane once.
+template <int T>
+__device__ __forceinline__ int32_t row_ror(int32_t x) {
+  if constexpr (T == 0) return x;
+  else return __builtin_amdgcn_update_dpp(x, x, 0x120 + T, 0xf, 0xf, false);
+}
+template <int... T>
+__device__ __forceinline__ bool in_row(int32_t v, int32_t x, std::integer_sequence<int, T...>) {
+  return ((v == row_ror<T>(x)) | ...);
 }
 
 template <int S, bool EXACTK>
@@ -121,6 +180,35 @@ struct RowTopK {
     return 1;
   }
 
+  // k <= 16 (one slot per lane): merge every lane's candidate with `better` set at once.
+  // Candidates already in N are dropped, the rest are sorted descending by a bitonic
+  // network, the elementwise minimum with the ascending N is bitonic and holds the 16
+  // smallest keys of both, and a bitonic merge sorts it.  Fixed cost, no per-candidate
+  // control flow, so the four rows of a wavefront run it together.
+  __device__ __forceinline__ int merge16(bool better, double dd, int32_t rr, int l, int k) {
+    static_assert(S == 1, "merge16 serves one slot per lane");
+    // evaluated by every lane: the row moves must see all 16 ranks of N
+    const bool dup = in_row(rr, r[0], std::make_integer_sequence<int, 16>{});
+    better = better & !dup;
+    double cd = better ? dd : INFINITY;
+    int32_t cr = better ? rr : kEmpty;
+    row_sort16<true>(cd, cr, l);
+    const bool cm = key_less(cd, cr, d[0], r[0]);
+    d[0] = cm ? cd : d[0];
+    r[0] = cm ? cr : r[0];
+    cas_stage<8>(d[0], r[0], (l & 8) == 0);
+    cas_stage<4>(d[0], r[0], (l & 4) == 0);
+    cas_stage<2>(d[0], r[0], (l & 2) == 0);
+    cas_stage<1>(d[0], r[0], (l & 1) == 0);
+    if (EXACTK) {
+      thr_d = dpp_f64<kDppRowBcast15>(d[0], d[0]);
+      thr_r = dpp_i32<kDppRowBcast15>(r[0], r[0]);
+    } else {
+      slot(k - 1, thr_d, thr_r);
+    }
+    return better ? 1 : 0;
+  }
+
   // Offer every lane's (dd, rr) with `better` set; updates the threshold as it goes.
   __device__ __forceinline__ int insert_all(bool better, double dd, int32_t rr, int l, int g,
                                             int k) {
@@ -178,7 +266,22 @@ __device__ __forceinline__ bool scan_list(const QueryArgs &a, RowTopK<S, EXACTK>
       }
     }
     if (COUNT) cs.nent += __popc(vmask);
-    const int ins = N.insert_all(valid && key_less(dd, r, N.thr_d, N.thr_r), dd, r, l, g, k);
+    const bool better = valid && key_less(dd, r, N.thr_d, N.thr_r);
+    int ins = 0;
+    if constexpr (S == 1) {
+      // the most candidates any row of the wavefront has in this chunk (wave-uniform)
+      const uint64_t wb = __ballot(better);
+      const int most = max(max(__popc((uint32_t)wb & 0xffffu), __popc((uint32_t)(wb >> 16) & 0xffffu)),
+                           max(__popc((uint32_t)(wb >> 32) & 0xffffu), __popc((uint32_t)(wb >> 48))));
+      if (most > 0 && most >= a.merge_min) {
+        const int got = N.merge16(better, dd, r, l, k);
+        if (COUNT) ins = __popc(row_bits(__ballot(got), g));
+      } else if (most > 0) {
+        ins = N.insert_all(better, dd, r, l, g, k);
+      }
+    } else {
+      ins = N.insert_all(better, dd, r, l, g, k);
+    }
     if (COUNT) cs.nins += ins;
     if (vmask != 0xffffu) break;   // end of the list or of the prefix
   }
@@ -268,8 +371,10 @@ __device__ __forceinline__ void group_query(const QueryArgs &a, int64_t s, int l
 }
 
 // Plain launch: one row per query, queries in (sorted) order, XCD-contiguous tiles.
+// Eight wavefronts per SIMD (the hardware maximum) hide most of the walk's memory latency;
+// the merge network's lane masks would otherwise take enough scalar registers to cost one.
 template <int S, bool EXACTK, bool COUNT>
-__global__ __launch_bounds__(256) void knn_group_kernel(QueryArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void knn_group_kernel(QueryArgs a) {
   const int lane = threadIdx.x & 63;
   const int l = lane & 15, g = lane >> 4;
   const int64_t wave =

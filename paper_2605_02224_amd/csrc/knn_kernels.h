@@ -34,6 +34,8 @@ struct QueryArgs {
   float *out_dist;
   int32_t *cnt_entries, *cnt_lists;   // diagnostics (COUNT variant only)
   int32_t *cnt_inserts;               // optional diagnostic: candidates inserted into N
+  int32_t merge_min;                  // k <= 16: candidates per chunk from which a merge
+                                      // network replaces one-by-one insertion (0 = default)
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range

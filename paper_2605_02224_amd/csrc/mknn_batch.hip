@@ -430,6 +430,7 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   for (int32_t r = 0; r < nreq; ++r) {
     const mknn_request &q = reqs[r];
     fill_cloud_args(q.cloud, &args[r]);
+    args[r].merge_min = merge_min();
     args[r].q = q.d_q;
     args[r].qs = p->sort ? p->d_qs + qoff[r] : nullptr;
     args[r].nq = q.nq;

@@ -485,6 +485,18 @@ static hipError_t launch_lane(const QueryArgs &a, hipStream_t s) {
 
 
 // Optional dynamic LDS per workgroup, used only to cap occupancy in tuning experiments.
+// Candidates per chunk (most over the rows of a wavefront) from which k <= 16 uses the
+// merge network instead of inserting one by one.
+int32_t merge_min() {
+  static long v = -1;
+  if (v < 0) {
+    const char *e = getenv("MKNN_MERGE_MIN");
+    v = e ? atol(e) : 6;   // measured optimum on the 1M torus at k = 16 (sweep 1..17)
+    if (v < 1) v = 1;
+  }
+  return (int32_t)v;
+}
+
 static size_t lds_pad() {
   static long v = -1;
   if (v < 0) {
@@ -495,8 +507,10 @@ static size_t lds_pad() {
 }
 
 template <int S, bool EXACTK, bool COUNT>
-static hipError_t launch_group(const QueryArgs &a, hipStream_t s) {
+static hipError_t launch_group(const QueryArgs &a0, hipStream_t s) {
   const int threads = 256;   // 4 waves x 4 queries
+  QueryArgs a = a0;
+  a.merge_min = merge_min();
   const uint32_t blocks = (uint32_t)((a.nq + 15) / 16);
   hipLaunchKernelGGL((knn_group_kernel<S, EXACTK, COUNT>), dim3(blocks), dim3(threads), lds_pad(),
                      s, a);
