@@ -39,9 +39,11 @@ __device__ __forceinline__ bool key_less(double da, int32_t ra, double db, int32
 constexpr int kDppRowShr1 = 0x111;
 constexpr int kDppRowBcast15 = 0x15F;
 
+// Every use below either has a valid source lane for every lane or ignores the lanes that
+// do not (row_shr:1 at lane 0), so the DPP move needs no "old" operand (bound_ctrl).
 template <int CTRL>
-__device__ __forceinline__ int32_t dpp_i32(int32_t old, int32_t x) {
-  return __builtin_amdgcn_update_dpp(old, x, CTRL, 0xf, 0xf, false);
+__device__ __forceinline__ int32_t dpp_i32(int32_t /*unused*/, int32_t x) {
+  return __builtin_amdgcn_mov_dpp(x, CTRL, 0xf, 0xf, true);
 }
 
 template <int CTRL>
@@ -52,49 +54,52 @@ __device__ __forceinline__ double dpp_f64(double old, double x) {
   return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
 
-// Lane l ^ J within a row of 16, for the compare-exchange stages of a bitonic network.
-template <int J>
+// Partner lanes of the compare-exchange stages (lane l ^ X within a row of 16).
+template <int X>
 __device__ __forceinline__ int32_t xor_lane(int32_t x) {
-  if constexpr (J == 1) return __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xf, 0xf, false);  // quad_perm 1,0,3,2
-  if constexpr (J == 2) return __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xf, 0xf, false);  // quad_perm 2,3,0,1
-  if constexpr (J == 4) return __builtin_amdgcn_ds_swizzle(x, 0x101F);   // bitmask mode, xor 4
-  if constexpr (J == 8) return __builtin_amdgcn_update_dpp(x, x, 0x128, 0xf, 0xf, false);  // row_ror:8
+  if constexpr (X == 1) return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xf, 0xf, true);    // quad_perm 1,0,3,2
+  if constexpr (X == 2) return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xf, 0xf, true);    // quad_perm 2,3,0,1
+  if constexpr (X == 3) return __builtin_amdgcn_mov_dpp(x, 0x1B, 0xf, 0xf, true);    // quad_perm 3,2,1,0
+  if constexpr (X == 4) return __builtin_amdgcn_ds_swizzle(x, 0x101F);               // bitmask mode, xor 4
+  if constexpr (X == 7) return __builtin_amdgcn_mov_dpp(x, 0x141, 0xf, 0xf, true);   // row_half_mirror
+  if constexpr (X == 8) return __builtin_amdgcn_mov_dpp(x, 0x128, 0xf, 0xf, true);   // row_ror:8
+  if constexpr (X == 15) return __builtin_amdgcn_mov_dpp(x, 0x140, 0xf, 0xf, true);  // row_mirror
   return x;
 }
 
-template <int J>
+template <int X>
 __device__ __forceinline__ double xor_lane_f64(double x) {
   const int64_t v = __double_as_longlong(x);
-  const int32_t lo = xor_lane<J>((int32_t)v), hi = xor_lane<J>((int32_t)(v >> 32));
+  const int32_t lo = xor_lane<X>((int32_t)v), hi = xor_lane<X>((int32_t)(v >> 32));
   return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
 
-// One compare-exchange stage between lanes l and l ^ J: the lane keeps the smaller key if
-// keep_min, else the larger.  Equal keys only occur between identical padding entries.
-template <int J>
-__device__ __forceinline__ void cas_stage(double &d, int32_t &r, bool keep_min) {
-  const double pd = xor_lane_f64<J>(d);
-  const int32_t pr = xor_lane<J>(r);
-  const bool take = key_less(pd, pr, d, r) == keep_min;
+// One compare-exchange stage between lanes l and l ^ X: of each pair, the lane whose bit
+// BIT is clear keeps the smaller key, the other the larger.  Equal keys only occur between
+// identical padding entries.
+template <int X, int BIT>
+__device__ __forceinline__ void cas_stage(double &d, int32_t &r, int l) {
+  const double pd = xor_lane_f64<X>(d);
+  const int32_t pr = xor_lane<X>(r);
+  const bool take = key_less(pd, pr, d, r) == ((l & BIT) == 0);
   d = take ? pd : d;
   r = take ? pr : r;
 }
 
-// Bitonic sort of one key per lane across the row; DESC sorts descending.
-template <bool DESC>
+// Ascending bitonic sort of one key per lane across the row.  Each merge level starts by
+// comparing mirrored lanes (l ^ 3, l ^ 7, l ^ 15), so that every stage keeps the minimum in
+// the lower lane of a pair and only four lane masks are needed.
 __device__ __forceinline__ void row_sort16(double &d, int32_t &r, int l) {
-#define MKNN_CAS(K, J) cas_stage<J>(d, r, ((l & (J)) == 0) == ((((l & (K)) == 0)) != DESC))
-  MKNN_CAS(2, 1);
-  MKNN_CAS(4, 2);
-  MKNN_CAS(4, 1);
-  MKNN_CAS(8, 4);
-  MKNN_CAS(8, 2);
-  MKNN_CAS(8, 1);
-  MKNN_CAS(16, 8);
-  MKNN_CAS(16, 4);
-  MKNN_CAS(16, 2);
-  MKNN_CAS(16, 1);
-#undef MKNN_CAS
+  cas_stage<1, 1>(d, r, l);
+  cas_stage<3, 2>(d, r, l);
+  cas_stage<1, 1>(d, r, l);
+  cas_stage<7, 4>(d, r, l);
+  cas_stage<2, 2>(d, r, l);
+  cas_stage<1, 1>(d, r, l);
+  cas_stage<15, 8>(d, r, l);
+  cas_stage<4, 4>(d, r, l);
+  cas_stage<2, 2>(d, r, l);
+  cas_stage<1, 1>(d, r, l);
 }
 
 // Whether v equals any lane's x in the row: row_ror:t for t = 1..15 passes every value of
@@ -102,7 +107,7 @@ __device__ __forceinline__ void row_sort16(double &d, int32_t &r, int l) {
 template <int T>
 __device__ __forceinline__ int32_t row_ror(int32_t x) {
   if constexpr (T == 0) return x;
-  else return __builtin_amdgcn_update_dpp(x, x, 0x120 + T, 0xf, 0xf, false);
+  else return __builtin_amdgcn_mov_dpp(x, 0x120 + T, 0xf, 0xf, true);
 }
 template <int... T>
 __device__ __forceinline__ bool in_row(int32_t v, int32_t x, std::integer_sequence<int, T...>) {
@@ -181,10 +186,10 @@ struct RowTopK {
   }
 
   // k <= 16 (one slot per lane): merge every lane's candidate with `better` set at once.
-  // Candidates already in N are dropped, the rest are sorted descending by a bitonic
-  // network, the elementwise minimum with the ascending N is bitonic and holds the 16
-  // smallest keys of both, and a bitonic merge sorts it.  Fixed cost, no per-candidate
-  // control flow, so the four rows of a wavefront run it together.
+  // Candidates already in N are dropped, the rest are sorted by a bitonic network; the
+  // elementwise minimum of the ascending N and the mirrored (descending) candidates is
+  // bitonic and holds the 16 smallest keys of both, and a bitonic merge sorts it.  Fixed
+  // cost, no per-candidate control flow, so the four rows of a wavefront run it together.
   __device__ __forceinline__ int merge16(bool better, double dd, int32_t rr, int l, int k) {
     static_assert(S == 1, "merge16 serves one slot per lane");
     // evaluated by every lane: the row moves must see all 16 ranks of N
@@ -192,14 +197,16 @@ struct RowTopK {
     better = better & !dup;
     double cd = better ? dd : INFINITY;
     int32_t cr = better ? rr : kEmpty;
-    row_sort16<true>(cd, cr, l);
+    row_sort16(cd, cr, l);
+    cd = xor_lane_f64<15>(cd);
+    cr = xor_lane<15>(cr);
     const bool cm = key_less(cd, cr, d[0], r[0]);
     d[0] = cm ? cd : d[0];
     r[0] = cm ? cr : r[0];
-    cas_stage<8>(d[0], r[0], (l & 8) == 0);
-    cas_stage<4>(d[0], r[0], (l & 4) == 0);
-    cas_stage<2>(d[0], r[0], (l & 2) == 0);
-    cas_stage<1>(d[0], r[0], (l & 1) == 0);
+    cas_stage<8, 8>(d[0], r[0], l);
+    cas_stage<4, 4>(d[0], r[0], l);
+    cas_stage<2, 2>(d[0], r[0], l);
+    cas_stage<1, 1>(d[0], r[0], l);
     if (EXACTK) {
       thr_d = dpp_f64<kDppRowBcast15>(d[0], d[0]);
       thr_r = dpp_i32<kDppRowBcast15>(r[0], r[0]);
@@ -371,10 +378,12 @@ __device__ __forceinline__ void group_query(const QueryArgs &a, int64_t s, int l
 }
 
 // Plain launch: one row per query, queries in (sorted) order, XCD-contiguous tiles.
-// Eight wavefronts per SIMD (the hardware maximum) hide most of the walk's memory latency;
-// the merge network's lane masks would otherwise take enough scalar registers to cost one.
+// Eight wavefronts per SIMD (the hardware maximum) hide most of the walk's memory latency.
+// For one slot per lane the merge network's lane masks would otherwise take enough scalar
+// registers to cost one; wider candidate lists are left to the compiler (forcing eight
+// would spill vector registers).
 template <int S, bool EXACTK, bool COUNT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void knn_group_kernel(QueryArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8))) void knn_group_kernel(QueryArgs a) {
   const int lane = threadIdx.x & 63;
   const int l = lane & 15, g = lane >> 4;
   const int64_t wave =

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(const BatchHeader *h,
 }
 
 template <int S>
-__global__ __launch_bounds__(256) void knn_batch_kernel(const BatchHeader *h,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8))) void knn_batch_kernel(const BatchHeader *h,
                                                         const QueryArgs *reqs,
                                                         const BatchEntry *ents,
                                                         uint32_t *counters, int cls) {
@@ -173,8 +173,9 @@ __global__ __launch_bounds__(256) void knn_batch_kernel(const BatchHeader *h,
       s_tile[1] = t;
     }
     __syncthreads();
-    const int32_t req = s_tile[0];
-    const int64_t begin = (int64_t)s_tile[1] * tq;
+    // workgroup-uniform: keep the request and its arguments in scalar registers
+    const int32_t req = __builtin_amdgcn_readfirstlane(s_tile[0]);
+    const int64_t begin = (int64_t)__builtin_amdgcn_readfirstlane(s_tile[1]) * tq;
     __syncthreads();
     if (req < 0) return;
     const QueryArgs &a = reqs[req];
