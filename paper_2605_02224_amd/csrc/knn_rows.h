@@ -1,0 +1,182 @@
+// Row-scheduled variant of the group kernel: the same 16-lane rows and candidate list as
+// knn_group.h, but every row advances through its own sequence of queries independently.
+//
+// Why: in the group kernel the four rows of a wavefront run one query each from start to
+// end, so a row whose descent (Alg. 1) or list is shorter waits, masked off, for the
+// longest one; about half of all lane-cycles were spent masked.  Here each loop iteration
+// processes one 16-entry chunk for every row -- a descent chunk, an expansion chunk
+// (Alg. 2) or the next chunk of a long list -- and a row that finishes its query writes
+// the result and starts its next query in the same iteration.  Candidate insertion is
+// shared: the chunk's candidates of all four rows go through one merge network (or the
+// one-by-one insertion) together.  A wavefront owns `per_wave` consecutive sorted queries;
+// row g takes positions g, g + 4, g + 8, ... of them, so the rows stay on Morton
+// neighbours.
+//
+// Per chunk the row state decides what the chunk means:
+//   descent   : the first entry closer than the current site is the transition site; it
+//               is offered to N and the walk jumps to its list.  A list without one is the
+//               final list of the descent, offered whole (it doubles as Alg. 2's first
+//               iteration, exactly as in the group kernel).
+//   expansion : every entry of the list of N's slot `it` is offered (it = 1 .. k-2).
+#pragma once
+#include "knn_group.h"
+
+namespace mknn {
+
+// Offer every lane's flagged candidate to N, the four rows at once.
+template <int S, bool EXACTK>
+__device__ __forceinline__ void offer_all(RowTopK<S, EXACTK> &N, bool cand, double dd,
+                                          int32_t rr, int l, int g, int k, int merge_min) {
+  const uint64_t wb = __ballot(cand);
+  if (wb == 0) return;
+  if constexpr (S == 1) {
+    const int most = max(max(__popc((uint32_t)wb & 0xffffu), __popc((uint32_t)(wb >> 16) & 0xffffu)),
+                         max(__popc((uint32_t)(wb >> 32) & 0xffffu), __popc((uint32_t)(wb >> 48))));
+    if (most >= merge_min) {
+      N.merge16(cand, dd, rr, l, k);
+      return;
+    }
+  }
+  N.insert_all(cand, dd, rr, l, g, k);
+}
+
+template <int S, bool EXACTK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
+void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
+  const int lane = threadIdx.x & 63;
+  const int l = lane & 15, g = lane >> 4;
+  const int64_t wave =
+      ((int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t begin = wave * per_wave;
+  const int64_t end = begin + per_wave < a.nq ? begin + per_wave : a.nq;
+
+  RowTopK<S, EXACTK> N;
+  N.init();
+  double qx = 0, qy = 0, qz = 0, dcur = 0;
+  int64_t qi = 0, next = begin + g;
+  int32_t k = 0, m = 0, cur = 0, it = 0;
+  int32_t phase = 2;                      // 0 descent, 1 expansion, 2 no query left
+  uint64_t dsc = 0;
+  uint32_t base = 0;
+
+  // Start the next query of this row (row-uniform control).  Queries whose prefix holds no
+  // live site are answered at once with empty rows.
+  auto start = [&]() {
+    phase = 2;
+    while (next < end) {
+      const int64_t s = next;
+      next += 4;
+      if (a.qs) {
+        const float4 v = a.qs[s];
+        qx = v.x;
+        qy = v.y;
+        qz = v.z;
+        qi = __float_as_int(v.w);
+      } else {
+        qi = s;
+        qx = a.q[3 * s];
+        qy = a.q[3 * s + 1];
+        qz = a.q[3 * s + 2];
+      }
+      k = a.kq ? a.kq[qi] : a.k;
+      int64_t mm = a.mq ? (int64_t)a.mq[qi] : (int64_t)a.m;
+      if (mm > a.n) mm = a.n;
+      m = (int32_t)mm;
+      if (k < 1 || k > 16 * S || m < 1) continue;
+      N.init();
+      if (a.head >= m) {
+        const int64_t row = a.row_off ? a.row_off[qi] : qi * (int64_t)a.k;
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+          const int j = 16 * t + l;
+          if (j < k) {
+            a.out_idx[row + j] = -1;
+            a.out_dist[row + j] = INFINITY;
+          }
+        }
+        continue;
+      }
+      cur = a.head;
+      {
+        const double dx = qx - (double)a.hx, dy = qy - (double)a.hy, dz = qz - (double)a.hz;
+        dcur = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+      }
+      if (l == 0) {
+        N.d[0] = dcur;
+        N.r[0] = cur;
+      }
+      if (k == 1) {
+        N.thr_d = dcur;
+        N.thr_r = cur;
+      }
+      dsc = a.lst[cur];
+      base = 0;
+      it = 0;
+      phase = 0;
+      return;
+    }
+  };
+
+  start();
+  for (;;) {
+    const bool active = phase != 2;
+    if (__ballot(active) == 0) break;
+    // ---- one chunk of every active row's current list
+    const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
+    const uint32_t e = base + (uint32_t)l;
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (active && e < len) c = a.ent[st + e];
+    const int32_t r = __float_as_int(c.w);
+    const bool valid = active && e < len && r < m;
+    double dd = INFINITY;
+    if (valid) {
+      const double dx = qx - (double)c.x, dy = qy - (double)c.y, dz = qz - (double)c.z;
+      dd = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    }
+    const uint32_t vmask = row_bits(__ballot(valid), g);
+    const uint32_t jm = row_bits(__ballot(valid && phase == 0 && dd < dcur), g);
+    const int j = jm ? __ffs(jm) - 1 : 0;
+    // candidates: a jumping row offers its transition site only (Alg. 1), the other rows
+    // every entry of the chunk
+    const bool cand = (jm ? l == j : valid) && key_less(dd, r, N.thr_d, N.thr_r);
+    offer_all(N, cand, dd, r, l, g, k, a.merge_min);
+    // ---- advance each row (row-uniform)
+    if (jm) {
+      dcur = __shfl(dd, j, 16);
+      cur = __shfl(r, j, 16);
+      dsc = a.lst[cur];
+      base = 0;
+    } else if (active) {
+      if (vmask == 0xffffu && base + 16 < len) {
+        base += 16;   // the next chunk of a long list
+      } else {
+        // the list is finished: the next confirmed neighbour's list, or the query is done
+        it = phase == 0 ? 1 : it + 1;
+        phase = 1;
+        int32_t pr = kEmpty;
+        if (it < k - 1) {
+          double pd;
+          N.slot(it, pd, pr);
+        }
+        if (pr != kEmpty) {
+          dsc = a.lst[pr];
+          base = 0;
+        } else {
+          const int64_t row = a.row_off ? a.row_off[qi] : qi * (int64_t)a.k;
+#pragma unroll
+          for (int t = 0; t < S; ++t) {
+            const int jj = 16 * t + l;
+            if (jj < k) {
+              const bool empty = N.r[t] == kEmpty;
+              a.out_idx[row + jj] = empty ? -1 : N.r[t];
+              a.out_dist[row + jj] = empty ? INFINITY : (float)sqrt(N.d[t]);
+            }
+          }
+          start();
+        }
+      }
+    }
+  }
+}
+
+}  // namespace mknn

@@ -26,6 +26,7 @@
 
 #include "device_common.h"
 #include "knn_group.h"
+#include "knn_rows.h"
 
 namespace mknn {
 
@@ -532,7 +533,40 @@ static hipError_t dispatch_group(const QueryArgs &a, int kmax, bool exact, hipSt
 }
 
 
-// kernel family: 0 = automatic, 1 = one query per lane, 2 = 16 lanes per query
+// Queries per wavefront of the row-scheduled kernel (MKNN_PER_WAVE).
+static int32_t rows_per_wave() {
+  static long v = -1;
+  if (v < 0) {
+    const char *e = getenv("MKNN_PER_WAVE");
+    v = e ? atol(e) : 4;   // one query per row measured fastest (sweep 4..64, 1M torus)
+    if (v < 4) v = 4;
+  }
+  return (int32_t)v;
+}
+
+template <int S, bool EXACTK>
+static hipError_t launch_rows(const QueryArgs &a0, hipStream_t s) {
+  QueryArgs a = a0;
+  a.merge_min = merge_min();
+  const int32_t pw = rows_per_wave();
+  const int64_t waves = (a.nq + pw - 1) / pw;
+  const uint32_t blocks = (uint32_t)((waves + 3) / 4);
+  hipLaunchKernelGGL((knn_rows_kernel<S, EXACTK>), dim3(blocks), dim3(256), 0, s, a, pw);
+  return hipGetLastError();
+}
+
+static hipError_t dispatch_rows(const QueryArgs &a, int kmax, bool exact, hipStream_t s) {
+#define MKNN_RCASE(SS)                                                                        if (kmax <= 16 * SS)                                                                         return (exact && kmax == 16 * SS) ? launch_rows<SS, true>(a, s)                                                             : launch_rows<SS, false>(a, s);
+  MKNN_RCASE(1)
+  MKNN_RCASE(2)
+  MKNN_RCASE(3)
+  MKNN_RCASE(4)
+#undef MKNN_RCASE
+  return hipErrorInvalidValue;
+}
+
+// kernel family: 0 = automatic, 1 = one query per lane, 2 = 16 lanes per query,
+// 3 = 16 lanes per query with rows scheduled independently
 static int g_family = 0;
 
 static int family_for(int kmax) {
@@ -540,11 +574,11 @@ static int family_for(int kmax) {
   static int env = -1;
   if (env < 0) {
     const char *v = getenv("MKNN_KERNEL");
-    env = (v && v[0] == 'l') ? 1 : (v && v[0] == 'g') ? 2 : 0;
+    env = (v && v[0] == 'l') ? 1 : (v && v[0] == 'g') ? 2 : (v && v[0] == 'r') ? 3 : 0;
   }
   if (env) return env;
   (void)kmax;
-  return 2;
+  return 3;
 }
 
 template <bool COUNT>
@@ -620,6 +654,8 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
   if (e == hipSuccess) {
     if (fam == 1)
       e = d_ce ? dispatch_lane<true>(a, kmax, exact, s) : dispatch_lane<false>(a, kmax, exact, s);
+    else if (fam == 3 && !d_ce)
+      e = dispatch_rows(a, kmax, exact, s);
     else
       e = d_ce ? dispatch_group<true>(a, kmax, exact, s) : dispatch_group<false>(a, kmax, exact, s);
   }
