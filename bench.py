@@ -411,7 +411,7 @@ def main() -> int:
     ap.add_argument("--delete-frac", type=float, default=0.01,
                     help="serving: fraction of each cloud deleted during a run")
     ap.add_argument("--clouds", type=int, default=256)
-    ap.add_argument("--tile", type=int, default=1024)
+    ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)

@@ -133,12 +133,13 @@ mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, cons
  * launch per register class (k <= 16, 32, 48, 64).  Same per-query semantics as mknn_knn
  * (Alg. 1 + Alg. 2, Sec. 4.2).
  *
- * Each request is cut into tiles of at most `tile_queries` queries (shorter tiles when the
- * batch is small, so that it still fills the chip).  Requests are assigned to 8 per-XCD
- * queues (largest estimated cost first, all tiles of a request on one queue).
- * Persistent workgroups claim tiles from their own queue with an atomic counter and steal
- * from the other queues when it runs dry.  The queries of all requests are bucketed
- * together by (request, Morton code) unless MKNN_BATCH_NO_SORT is set.
+ * Each request is cut into tiles of at most `tile_queries` queries (4 .. 2^20; 16 is a good
+ * default: small tiles keep concurrent work on nearby queries).  Requests are assigned to 8
+ * per-XCD queues (largest estimated cost first, all tiles of a request on one queue).
+ * Persistent wavefronts claim tiles from their own queue with an atomic counter and steal
+ * from the other queues when it runs dry; their 16-lane rows take queries one at a time.
+ * The queries of all requests are bucketed together by (request, Morton code) unless
+ * MKNN_BATCH_NO_SORT is set.
  */
 typedef struct {
   const mknn_cloud *cloud;   /* an uploaded cloud */

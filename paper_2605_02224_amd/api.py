@@ -190,7 +190,7 @@ def alloc_outputs(items):
 class BatchPlan:
     """Device buffers + captured hipGraph for batches of many clouds (mknn_batch_plan_*)."""
 
-    def __init__(self, max_requests: int, max_queries: int, tile_queries: int = 1024,
+    def __init__(self, max_requests: int, max_queries: int, tile_queries: int = 16,
                  sort: bool = True, graph: bool = True):
         flags = (0 if sort else _lib.BATCH_NO_SORT) | (0 if graph else _lib.BATCH_NO_GRAPH)
         h = ctypes.c_void_p()

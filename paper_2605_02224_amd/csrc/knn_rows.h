@@ -1,16 +1,14 @@
 // Row-scheduled variant of the group kernel: the same 16-lane rows and candidate list as
-// knn_group.h, but every row advances through its own sequence of queries independently.
+// knn_group.h, but every row advances through its own queries independently.
 //
 // Why: in the group kernel the four rows of a wavefront run one query each from start to
 // end, so a row whose descent (Alg. 1) or list is shorter waits, masked off, for the
-// longest one; about half of all lane-cycles were spent masked.  Here each loop iteration
-// processes one 16-entry chunk for every row -- a descent chunk, an expansion chunk
-// (Alg. 2) or the next chunk of a long list -- and a row that finishes its query writes
-// the result and starts its next query in the same iteration.  Candidate insertion is
-// shared: the chunk's candidates of all four rows go through one merge network (or the
-// one-by-one insertion) together.  A wavefront owns `per_wave` consecutive sorted queries;
-// row g takes positions g, g + 4, g + 8, ... of them, so the rows stay on Morton
-// neighbours.
+// longest one; about half of all lane-cycles were spent masked.  Here each step processes
+// one 16-entry chunk for every row -- a descent chunk, an expansion chunk (Alg. 2) or the
+// next chunk of a long list -- so a row in its descent and a row in its expansion run the
+// same instructions, and a row that finishes writes its result and takes another query
+// while the others go on.  Candidate insertion is shared: the chunk's candidates of all
+// four rows go through one merge network (or the one-by-one insertion) together.
 //
 // Per chunk the row state decides what the chunk means:
 //   descent   : the first entry closer than the current site is the transition site; it
@@ -40,6 +38,129 @@ __device__ __forceinline__ void offer_all(RowTopK<S, EXACTK> &N, bool cand, doub
   N.insert_all(cand, dd, rr, l, g, k);
 }
 
+constexpr int32_t kRowDescent = 0, kRowExpand = 1, kRowIdle = 2;
+
+// The state of one row's current query.  Row-uniform values, held by every lane of the row.
+template <int S, bool EXACTK>
+struct RowWalker {
+  RowTopK<S, EXACTK> N;
+  double qx = 0, qy = 0, qz = 0, dcur = 0;
+  int64_t qi = 0;
+  int32_t k = 0, m = 0, cur = 0, it = 0;
+  int32_t phase = kRowIdle;
+  uint64_t dsc = 0;
+  uint32_t base = 0;
+
+  // Start the query at sorted position s of request a.  A query whose prefix holds no live
+  // site is answered at once (empty row) and leaves the row idle.
+  __device__ __forceinline__ void begin(const QueryArgs &a, int64_t s, int l) {
+    phase = kRowIdle;
+    if (a.qs) {
+      const float4 v = a.qs[s];
+      qx = v.x;
+      qy = v.y;
+      qz = v.z;
+      qi = __float_as_int(v.w);
+    } else {
+      qi = s;
+      qx = a.q[3 * s];
+      qy = a.q[3 * s + 1];
+      qz = a.q[3 * s + 2];
+    }
+    k = a.kq ? a.kq[qi] : a.k;
+    int64_t mm = a.mq ? (int64_t)a.mq[qi] : (int64_t)a.m;
+    if (mm > a.n) mm = a.n;
+    m = (int32_t)mm;
+    if (k < 1 || k > 16 * S || m < 1) return;
+    N.init();
+    if (a.head >= m) {
+      finish(a, l);
+      return;
+    }
+    cur = a.head;
+    const double dx = qx - (double)a.hx, dy = qy - (double)a.hy, dz = qz - (double)a.hz;
+    dcur = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    if (l == 0) {
+      N.d[0] = dcur;
+      N.r[0] = cur;
+    }
+    if (k == 1) {
+      N.thr_d = dcur;
+      N.thr_r = cur;
+    }
+    dsc = a.lst[cur];
+    base = 0;
+    it = 0;
+    phase = kRowDescent;
+  }
+
+  __device__ __forceinline__ void finish(const QueryArgs &a, int l) {
+    const int64_t row = a.row_off ? a.row_off[qi] : qi * (int64_t)a.k;
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int j = 16 * t + l;
+      if (j < k) {
+        const bool empty = N.r[t] == kEmpty;
+        a.out_idx[row + j] = empty ? -1 : N.r[t];
+        a.out_dist[row + j] = empty ? INFINITY : (float)sqrt(N.d[t]);
+      }
+    }
+    phase = kRowIdle;
+  }
+
+  // One chunk for every row of the wavefront (call from uniform control flow).  A row that
+  // completes its query writes the result (through `a`) and becomes idle.  The list arrays
+  // come in separately so that callers can keep them in scalar registers.
+  __device__ __forceinline__ void step(const QueryArgs &a, const float4 *ent,
+                                       const uint64_t *lst, int merge_min, int l, int g) {
+    const bool active = phase != kRowIdle;
+    const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
+    const uint32_t e = base + (uint32_t)l;
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (active && e < len) c = ent[st + e];
+    const int32_t r = __float_as_int(c.w);
+    const bool valid = active && e < len && r < m;
+    double dd = INFINITY;
+    if (valid) {
+      const double dx = qx - (double)c.x, dy = qy - (double)c.y, dz = qz - (double)c.z;
+      dd = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    }
+    const uint32_t vmask = row_bits(__ballot(valid), g);
+    const uint32_t jm = row_bits(__ballot(valid && phase == kRowDescent && dd < dcur), g);
+    const int j = jm ? __ffs(jm) - 1 : 0;
+    // a jumping row offers its transition site only (Alg. 1), the other rows every entry
+    const bool cand = (jm ? l == j : valid) && key_less(dd, r, N.thr_d, N.thr_r);
+    offer_all(N, cand, dd, r, l, g, k, merge_min);
+    if (jm) {
+      dcur = __shfl(dd, j, 16);
+      cur = __shfl(r, j, 16);
+      dsc = lst[cur];
+      base = 0;
+    } else if (active) {
+      if (vmask == 0xffffu && base + 16 < len) {
+        base += 16;   // the next chunk of a long list
+      } else {
+        // the list is finished: the next confirmed neighbour's list, or the query is done
+        it = phase == kRowDescent ? 1 : it + 1;
+        phase = kRowExpand;
+        int32_t pr = kEmpty;
+        if (it < k - 1) {
+          double pd;
+          N.slot(it, pd, pr);
+        }
+        if (pr != kEmpty) {
+          dsc = lst[pr];
+          base = 0;
+        } else {
+          finish(a, l);
+        }
+      }
+    }
+  }
+};
+
+// Plain launch: a wavefront owns `per_wave` consecutive sorted queries; row g takes
+// positions g, g + 4, g + 8, ... of them, so the rows stay on Morton neighbours.
 template <int S, bool EXACTK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
 void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
@@ -49,133 +170,16 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
       ((int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t begin = wave * per_wave;
   const int64_t end = begin + per_wave < a.nq ? begin + per_wave : a.nq;
-
-  RowTopK<S, EXACTK> N;
-  N.init();
-  double qx = 0, qy = 0, qz = 0, dcur = 0;
-  int64_t qi = 0, next = begin + g;
-  int32_t k = 0, m = 0, cur = 0, it = 0;
-  int32_t phase = 2;                      // 0 descent, 1 expansion, 2 no query left
-  uint64_t dsc = 0;
-  uint32_t base = 0;
-
-  // Start the next query of this row (row-uniform control).  Queries whose prefix holds no
-  // live site are answered at once with empty rows.
-  auto start = [&]() {
-    phase = 2;
-    while (next < end) {
-      const int64_t s = next;
-      next += 4;
-      if (a.qs) {
-        const float4 v = a.qs[s];
-        qx = v.x;
-        qy = v.y;
-        qz = v.z;
-        qi = __float_as_int(v.w);
-      } else {
-        qi = s;
-        qx = a.q[3 * s];
-        qy = a.q[3 * s + 1];
-        qz = a.q[3 * s + 2];
-      }
-      k = a.kq ? a.kq[qi] : a.k;
-      int64_t mm = a.mq ? (int64_t)a.mq[qi] : (int64_t)a.m;
-      if (mm > a.n) mm = a.n;
-      m = (int32_t)mm;
-      if (k < 1 || k > 16 * S || m < 1) continue;
-      N.init();
-      if (a.head >= m) {
-        const int64_t row = a.row_off ? a.row_off[qi] : qi * (int64_t)a.k;
-#pragma unroll
-        for (int t = 0; t < S; ++t) {
-          const int j = 16 * t + l;
-          if (j < k) {
-            a.out_idx[row + j] = -1;
-            a.out_dist[row + j] = INFINITY;
-          }
-        }
-        continue;
-      }
-      cur = a.head;
-      {
-        const double dx = qx - (double)a.hx, dy = qy - (double)a.hy, dz = qz - (double)a.hz;
-        dcur = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-      }
-      if (l == 0) {
-        N.d[0] = dcur;
-        N.r[0] = cur;
-      }
-      if (k == 1) {
-        N.thr_d = dcur;
-        N.thr_r = cur;
-      }
-      dsc = a.lst[cur];
-      base = 0;
-      it = 0;
-      phase = 0;
-      return;
-    }
-  };
-
-  start();
+  RowWalker<S, EXACTK> w;
+  w.N.init();
+  int64_t next = begin + g;
   for (;;) {
-    const bool active = phase != 2;
-    if (__ballot(active) == 0) break;
-    // ---- one chunk of every active row's current list
-    const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
-    const uint32_t e = base + (uint32_t)l;
-    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (active && e < len) c = a.ent[st + e];
-    const int32_t r = __float_as_int(c.w);
-    const bool valid = active && e < len && r < m;
-    double dd = INFINITY;
-    if (valid) {
-      const double dx = qx - (double)c.x, dy = qy - (double)c.y, dz = qz - (double)c.z;
-      dd = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    while (w.phase == kRowIdle && next < end) {
+      w.begin(a, next, l);
+      next += 4;
     }
-    const uint32_t vmask = row_bits(__ballot(valid), g);
-    const uint32_t jm = row_bits(__ballot(valid && phase == 0 && dd < dcur), g);
-    const int j = jm ? __ffs(jm) - 1 : 0;
-    // candidates: a jumping row offers its transition site only (Alg. 1), the other rows
-    // every entry of the chunk
-    const bool cand = (jm ? l == j : valid) && key_less(dd, r, N.thr_d, N.thr_r);
-    offer_all(N, cand, dd, r, l, g, k, a.merge_min);
-    // ---- advance each row (row-uniform)
-    if (jm) {
-      dcur = __shfl(dd, j, 16);
-      cur = __shfl(r, j, 16);
-      dsc = a.lst[cur];
-      base = 0;
-    } else if (active) {
-      if (vmask == 0xffffu && base + 16 < len) {
-        base += 16;   // the next chunk of a long list
-      } else {
-        // the list is finished: the next confirmed neighbour's list, or the query is done
-        it = phase == 0 ? 1 : it + 1;
-        phase = 1;
-        int32_t pr = kEmpty;
-        if (it < k - 1) {
-          double pd;
-          N.slot(it, pd, pr);
-        }
-        if (pr != kEmpty) {
-          dsc = a.lst[pr];
-          base = 0;
-        } else {
-          const int64_t row = a.row_off ? a.row_off[qi] : qi * (int64_t)a.k;
-#pragma unroll
-          for (int t = 0; t < S; ++t) {
-            const int jj = 16 * t + l;
-            if (jj < k) {
-              const bool empty = N.r[t] == kEmpty;
-              a.out_idx[row + jj] = empty ? -1 : N.r[t];
-              a.out_dist[row + jj] = empty ? INFINITY : (float)sqrt(N.d[t]);
-            }
-          }
-          start();
-        }
-      }
-    }
+    if (__ballot(w.phase != kRowIdle) == 0) break;
+    w.step(a, a.ent, a.lst, a.merge_min, l, g);
   }
 }
 

@@ -2,17 +2,19 @@
 // persistent launch per register-capacity class.
 //
 // Work decomposition.  Every request (cloud, queries, k, m) is cut into tiles of T queries,
-// T chosen per class and batch as a power of two in [16, tile_queries] that gives about four
-// tiles per resident workgroup, so a small batch still fills the chip.  Requests are placed
-// on 8 queues -- one per XCD, workgroups are dispatched round-robin over the XCDs so
-// blockIdx % 8 names the XCD -- by a largest-processing-time-first rule on an estimated cost
-// (queries x (k + 8) x log2 n), all tiles of a request on one queue so its lists stay in
-// that XCD's L2.  A queue is a list of (request, first tile) entries.  A persistent
-// workgroup claims tiles from its own queue with one atomic per tile, finds the owning
+// T chosen per class and batch as a power of two in [4, tile_queries] (16 by default) that
+// gives at most one tile per resident wavefront for a small batch.  Small tiles keep the
+// wavefronts of an XCD on a narrow, Morton-contiguous window of queries, so the lists they
+// read stay in that XCD's L2; measured on 256 clouds, 16-query tiles beat 1024-query tiles
+// by a fifth.  Requests are placed on 8 queues -- one per XCD, workgroups are dispatched
+// round-robin over the XCDs so blockIdx % 8 names the XCD -- by a largest-processing-time-
+// first rule on an estimated cost (queries x (k + 8) x log2 n), all tiles of a request on
+// one queue.  A queue is a list of (request, first tile) entries.  Every persistent
+// wavefront claims tiles from its own queue with one atomic per tile, finds the owning
 // request by binary search over the entries, and steals from the other queues when its own
-// is empty; every workgroup leaves once all 8 queues are exhausted.  Inside a tile the 16
-// rows of the workgroup run the group-per-query walk (Alg. 1 + Alg. 2, knn_group.h) on the
-// tile's queries.
+// is empty; it leaves once all 8 queues are exhausted.  Its four 16-lane rows take the
+// tile's queries one at a time as they become idle (knn_rows.h), so no row waits for
+// another at a tile boundary.
 //
 // Query preparation.  The queries of all requests are bucketed together by (request,
 // 12-bit Morton code in the request's cloud box) with one counting sort -- histogram, one
@@ -37,6 +39,7 @@
 
 #include "device_common.h"
 #include "knn_group.h"
+#include "knn_rows.h"
 
 namespace mknn {
 
@@ -137,53 +140,102 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(const BatchHeader *h,
   }
 }
 
+// Claim the next tile for this wavefront: its own XCD queue first, then the others.
+// Wavefront-uniform result: (request, tile index within the queue entry) or request -1.
+__device__ __forceinline__ void claim_tile(const BatchHeader *h, const BatchEntry *ents,
+                                           uint32_t *counters, int cls, int home, int &tried,
+                                           int32_t &req, int32_t &tile) {
+  const int lane = threadIdx.x & 63;
+  req = -1;
+  tile = 0;
+  while (tried < kQueues) {
+    const int x = (home + tried) % kQueues;
+    const int32_t nt = h->qtiles[cls][x];
+    if (nt > 0) {
+      uint32_t v = 0;
+      if (lane == 0) v = atomicAdd(&counters[cls * kQueues + x], 1u);
+      v = __builtin_amdgcn_readfirstlane(v);
+      if ((int64_t)v < (int64_t)nt) {
+        // the entry owning tile v: last one with first <= v
+        int32_t lo = h->qbound[cls][x], hi = h->qbound[cls][x + 1];
+        while (hi - lo > 1) {
+          const int32_t mid = (lo + hi) >> 1;
+          if (ents[mid].first <= (int32_t)v) lo = mid; else hi = mid;
+        }
+        req = ents[lo].req;
+        tile = (int32_t)v - ents[lo].first;
+        return;
+      }
+    }
+    ++tried;
+  }
+}
+
+// Row-scheduled batched kernel.  Every wavefront claims tiles on its own and its four rows
+// (knn_rows.h) take the tile's queries one at a time as they become idle, so rows never
+// wait for each other at tile boundaries.  A wavefront serves one request at a time: a
+// claimed tile of another request is held until every row has finished the current one.
 template <int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8))) void knn_batch_kernel(const BatchHeader *h,
-                                                        const QueryArgs *reqs,
-                                                        const BatchEntry *ents,
-                                                        uint32_t *counters, int cls) {
-  __shared__ int32_t s_tile[2];
-  const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
+void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const BatchEntry *ents,
+                           uint32_t *counters, int cls) {
+  const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4;
   const int home = blockIdx.x % kQueues;
   const int64_t tq = h->tile[cls];
-  int tried = 0;   // used by thread 0: queues found empty so far
+  int tried = 0;
+  int32_t req = -1, preq = -1;     // current request; claimed tile of another request
+  int64_t tnext = 0, tend = 0, pbegin = 0;
+  bool exhausted = false;
+  const float4 *ent = nullptr;     // the current request's lists, in scalar registers
+  const uint64_t *lst = nullptr;
+  int merge_min = 1;
+  RowWalker<S, false> w;
+  w.N.init();
   for (;;) {
-    if (threadIdx.x == 0) {
-      int32_t req = -1, t = 0;
-      while (tried < kQueues) {
-        const int x = (home + tried) % kQueues;
-        const int32_t nt = h->qtiles[cls][x];
-        if (nt > 0) {
-          const uint32_t v = atomicAdd(&counters[cls * kQueues + x], 1u);
-          if ((int64_t)v < (int64_t)nt) {
-            // the entry owning tile v: last one with first <= v
-            int32_t lo = h->qbound[cls][x], hi = h->qbound[cls][x + 1];
-            while (hi - lo > 1) {
-              const int32_t mid = (lo + hi) >> 1;
-              if (ents[mid].first <= (int32_t)v) lo = mid; else hi = mid;
-            }
-            req = ents[lo].req;
-            t = (int32_t)v - ents[lo].first;
-            break;
-          }
-        }
-        ++tried;
+    // ---- give idle rows queries of the current tile, claiming tiles as needed
+    for (;;) {
+      const uint64_t idle = __ballot(w.phase == kRowIdle && l == 0);
+      if (idle == 0) break;
+      if (tnext < tend) {
+        const int rank = __popcll(idle & ((1ull << (16 * g)) - 1));
+        const int64_t s = tnext + rank;
+        if (w.phase == kRowIdle && s < tend) w.begin(reqs[req], s, l);
+        const int64_t cnt = __popcll(idle);
+        tnext = tnext + cnt < tend ? tnext + cnt : tend;
+        continue;   // a query answered at once leaves its row idle again
       }
-      s_tile[0] = req;
-      s_tile[1] = t;
+      if (preq >= 0) {
+        if (__ballot(w.phase != kRowIdle) != 0) break;   // rows still on the current request
+        req = preq;
+        preq = -1;
+        tnext = pbegin;
+        tend = pbegin + tq < reqs[req].nq ? pbegin + tq : reqs[req].nq;
+        ent = reqs[req].ent;
+        lst = reqs[req].lst;
+        merge_min = reqs[req].merge_min;
+        continue;
+      }
+      if (exhausted) break;
+      int32_t creq, ct;
+      claim_tile(h, ents, counters, cls, home, tried, creq, ct);
+      if (creq < 0) {
+        exhausted = true;
+        continue;
+      }
+      const int64_t b = (int64_t)ct * tq;
+      if (creq == req) {
+        tnext = b;
+        tend = b + tq < reqs[req].nq ? b + tq : reqs[req].nq;
+      } else {
+        preq = creq;
+        pbegin = b;
+      }
     }
-    __syncthreads();
-    // workgroup-uniform: keep the request and its arguments in scalar registers
-    const int32_t req = __builtin_amdgcn_readfirstlane(s_tile[0]);
-    const int64_t begin = (int64_t)__builtin_amdgcn_readfirstlane(s_tile[1]) * tq;
-    __syncthreads();
-    if (req < 0) return;
-    const QueryArgs &a = reqs[req];
-    const int64_t end = begin + tq < a.nq ? begin + tq : a.nq;
-    for (int64_t s0 = begin + 4 * w; s0 < end; s0 += 16) {
-      const int64_t s = s0 + g;
-      if (s < end) group_query<S, false, false>(a, s, l, g);
+    if (__ballot(w.phase != kRowIdle) == 0) {
+      if (exhausted && preq < 0) return;
+      continue;
     }
+    w.step(reqs[req], ent, lst, merge_min, l, g);
   }
 }
 
@@ -192,7 +244,7 @@ static int resident_batch_blocks() {
   static int nb = 0;
   if (!nb) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, reinterpret_cast<const void *>(&knn_batch_kernel<S>), 256, 0) != hipSuccess ||
+            &nb, reinterpret_cast<const void *>(&knn_batch_rows_kernel<S>), 256, 0) != hipSuccess ||
         nb < 1)
       nb = 1;
   }
@@ -209,7 +261,7 @@ using namespace mknn;
 struct mknn_batch_plan {
   int device = -1;
   int64_t max_req = 0, max_q = 0;
-  int32_t tile_q = 1024;
+  int32_t tile_q = 16;
   bool sort = true, use_graph = true;
   // device: staging mirror | counters | bins | sorted queries
   char *d_base = nullptr;
@@ -267,13 +319,13 @@ static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = timing_mark(s, true);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(knn_batch_kernel<1>, dim3(p->grid_batch[0]), dim3(256), 0, s, hdr, reqs,
+  hipLaunchKernelGGL(knn_batch_rows_kernel<1>, dim3(p->grid_batch[0]), dim3(256), 0, s, hdr, reqs,
                      ents, p->d_counters, 0);
-  hipLaunchKernelGGL(knn_batch_kernel<2>, dim3(p->grid_batch[1]), dim3(256), 0, s, hdr, reqs,
+  hipLaunchKernelGGL(knn_batch_rows_kernel<2>, dim3(p->grid_batch[1]), dim3(256), 0, s, hdr, reqs,
                      ents, p->d_counters, 1);
-  hipLaunchKernelGGL(knn_batch_kernel<3>, dim3(p->grid_batch[2]), dim3(256), 0, s, hdr, reqs,
+  hipLaunchKernelGGL(knn_batch_rows_kernel<3>, dim3(p->grid_batch[2]), dim3(256), 0, s, hdr, reqs,
                      ents, p->d_counters, 2);
-  hipLaunchKernelGGL(knn_batch_kernel<4>, dim3(p->grid_batch[3]), dim3(256), 0, s, hdr, reqs,
+  hipLaunchKernelGGL(knn_batch_rows_kernel<4>, dim3(p->grid_batch[3]), dim3(256), 0, s, hdr, reqs,
                      ents, p->d_counters, 3);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -290,8 +342,8 @@ mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, in
   if (max_requests < 1 || max_requests > (1 << 20) || max_queries < 1 ||
       max_queries > (int64_t)0x7fffffff)
     return set_error(MKNN_EINVAL, "mknn_batch_plan_create: capacity out of range");
-  if (tile_queries < 16 || tile_queries > (1 << 20))
-    return set_error(MKNN_EINVAL, "mknn_batch_plan_create: tile_queries out of range [16, 2^20]");
+  if (tile_queries < 4 || tile_queries > (1 << 20))
+    return set_error(MKNN_EINVAL, "mknn_batch_plan_create: tile_queries out of range [4, 2^20]");
   mknn_batch_plan *p = new (std::nothrow) mknn_batch_plan();
   if (!p) return set_error(MKNN_ENOMEM, "mknn_batch_plan_create: out of host memory");
   p->max_req = max_requests;
@@ -406,9 +458,9 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   for (int32_t r = 0; r < nreq; ++r) class_q[cls[r]] += reqs[r].nq;
   for (int c = 0; c < kClasses; ++c) {
     const int64_t want = class_q[c] / (4 * (int64_t)p->grid_batch[c]);
-    int64_t t = 16;
+    int64_t t = 4;
     while (t * 2 <= want && t * 2 <= p->tile_q) t *= 2;
-    hdr->tile[c] = (int32_t)std::max<int64_t>(16, std::min<int64_t>(t, p->tile_q));
+    hdr->tile[c] = (int32_t)std::max<int64_t>(4, std::min<int64_t>(t, p->tile_q));
   }
   int32_t ne = 0;
   for (int c = 0; c < kClasses; ++c) {
@@ -485,7 +537,7 @@ mknn_status mknn_batch_knn(const mknn_request *reqs, int32_t nreq, void *stream)
   }
   if (!g_plan) {
     mknn_status st = mknn_batch_plan_create(std::max<int64_t>(nreq, 64),
-                                            std::max<int64_t>(tq, (int64_t)1 << 20), 1024, 0,
+                                            std::max<int64_t>(tq, (int64_t)1 << 20), 16, 0,
                                             &g_plan);
     if (st != MKNN_OK) return st;
   }

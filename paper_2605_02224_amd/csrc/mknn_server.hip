@@ -417,7 +417,7 @@ mknn_status mknn_server_create(int64_t pool_queries, int32_t nstreams, int32_t m
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
     if (e == hipSuccess && !plain) {
-      if (mknn_batch_plan_create(s->max_wave, s->slot_queries, 1024, 0, &sl.plan) != MKNN_OK) {
+      if (mknn_batch_plan_create(s->max_wave, s->slot_queries, 16, 0, &sl.plan) != MKNN_OK) {
         const std::string msg = mknn_last_error();
         mknn_server_destroy(s);
         return set_error(MKNN_ENOMEM, "mknn_server_create: " + msg);
