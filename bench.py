@@ -110,6 +110,10 @@ def bench_batched(args) -> int:
     nq = sum(q.shape[0] for q in qs)
     items = A.alloc_outputs([(c, q, w.k, None) for c, q in zip(clouds, qs)])
     plan = A.BatchPlan(len(items), nq, tile_queries=args.tile, sort=True, graph=True)
+    tile = args.tile
+    if not args.no_autotune:
+        tile = plan.tune(items)   # untimed: picks the tile length for this batch
+        log(f"autotuner: tile length {tile}")
     torch.cuda.synchronize()
 
     def run_batched():
@@ -140,7 +144,7 @@ def bench_batched(args) -> int:
         "config": {"workload": f"batched_{len(items)}_clouds_k{w.k}", "clouds": len(items),
                    "points": int(sum(c.n for c in w.clouds)), "queries": int(nq), "k": w.k,
                    "form": "one persistent launch (hipGraph replay) per batch",
-                   "tile_queries": args.tile},
+                   "tile_queries": tile},
         "extra": {"plain_qps": round(res["plain"][0], 1),
                   "plain_ms": round(res["plain"][1] * 1e3, 3),
                   "speedup_vs_plain": round(res["batched"][0] / res["plain"][0], 3),
@@ -421,6 +425,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the context measurements")
+    ap.add_argument("--no-autotune", action="store_true", help="use the built-in configuration")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -470,6 +475,14 @@ def main() -> int:
     log(f"per query: {E:.1f} entries, {L:.2f} lists, {INS:.1f} inserts -> "
         f"{bytes_per_q:.0f} algorithmic bytes")
 
+    # autotuner (untimed): picks the kernel configuration for this size and k class
+    tuned = None
+    if not args.no_autotune:
+        from paper_2605_02224_amd import api as A
+        t0 = time.perf_counter()
+        best, tried = A.autotune(cl, q, k)
+        tuned = dict(best, seconds=round(time.perf_counter() - t0, 3))
+        log(f"autotuner: {best} of {len(tried)} candidates")
     for _ in range(args.warmup):
         cl.knn(q, k, out=(idx, dist))
     torch.cuda.synchronize()
@@ -497,7 +510,7 @@ def main() -> int:
     extras = {"build_s": round(build_s, 2), "device_bytes": cl.device_bytes,
               "entries_per_query": round(E, 2), "lists_per_query": round(L, 3),
               "inserts_per_query": round(INS, 2),
-              "kernel_ms": round(kern_ms, 4)}
+              "kernel_ms": round(kern_ms, 4), "autotuned": tuned}
     extra_runs = () if args.no_extras else (("volume_k1", q, 1), ("surface_k16", qb, 16),
                                             ("surface_k1", qb, 1))
     for name, qq, kk in extra_runs:

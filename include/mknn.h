@@ -173,12 +173,53 @@ mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries,
 mknn_status mknn_batch_plan_run(mknn_batch_plan *plan, const mknn_request *reqs, int32_t nreq,
                                 void *stream);
 
+/* Autotuner of the batched form: runs the batch with tile lengths 8, 16, 32, 64 and 256
+ * (three timed runs each, HIP events on `stream`), keeps the fastest as the plan's tile
+ * length and reports it.  The outputs hold the batch's results afterwards. */
+mknn_status mknn_batch_plan_tune(mknn_batch_plan *plan, const mknn_request *reqs, int32_t nreq,
+                                 void *stream, int32_t *best_tile);
+
 /* Release a plan (waits for its last run). */
 void mknn_batch_plan_destroy(mknn_batch_plan *plan);
 
 /* Convenience form: runs the batch on a plan the library keeps per process and grows on
  * demand.  Not thread-safe. */
 mknn_status mknn_batch_knn(const mknn_request *reqs, int32_t nreq, void *stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Autotuner.
+ *
+ * The query kernels come in three families -- one query per lane (register list of k
+ * entries), 16 lanes per query in lockstep, and 16 lanes per query with every row scheduled
+ * independently -- and, for k <= 16, switch from one-by-one candidate insertion to a
+ * merge network above a number of candidates per chunk.  mknn_autotune times every
+ * candidate configuration on the given queries (device float32 [nq][3], k, prefix m; m = 0
+ * means n) with HIP events on `stream`, keeps the fastest for clouds of this size class
+ * (log2 n) and this k class on the current device, and reports the timings.  Later
+ * mknn_knn / mknn_knn_var launches and batch plans use the table; untuned classes use the
+ * built-in defaults.  The table lives in the process and can be saved and loaded as text.
+ *   tried      optional host array of max_tried entries, receives every candidate
+ *   ntried     number of candidates timed
+ *   best       the chosen configuration
+ * Errors: EINVAL, EUNSUPPORTED (k), EHIP.  Not thread-safe with concurrent launches on the
+ * same stream.
+ */
+typedef struct {
+  int32_t family;      /* 1 lane per query, 2 lockstep rows, 3 scheduled rows */
+  int32_t merge_min;   /* k <= 16: candidates per chunk from which the merge network is used */
+  int32_t per_wave;    /* scheduled rows: queries per wavefront */
+  float ms;            /* best of three timed runs (milliseconds) */
+} mknn_tune_entry;
+
+mknn_status mknn_autotune(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k, int32_t m,
+                          void *stream, mknn_tune_entry *tried, int32_t max_tried,
+                          int32_t *ntried, mknn_tune_entry *best);
+/* Text form of the table: a "mknn-tune 1" line, then one line per entry
+ * "device S exact log2n family merge_min per_wave".  Load merges into the current table.
+ * Errors: EINVAL (path, malformed file), ENOTFOUND (load: no such file). */
+mknn_status mknn_tune_save(const char *path);
+mknn_status mknn_tune_load(const char *path);
+void mknn_tune_reset(void);
 
 /* ---------------------------------------------------------------------------------------
  * Work counters (diagnostics for the memory roofline).

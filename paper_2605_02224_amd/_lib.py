@@ -25,7 +25,6 @@ SIGNATURES = {
     "mknn_successors": (ctypes.c_int, [_P, _PP, _PP, ctypes.POINTER(_I64)]),
     "mknn_points_by_rank": (ctypes.c_int, [_P, _PP]),
     "mknn_upload": (ctypes.c_int, [_P, _P]),
-    "mknn_compact": (ctypes.c_int, [_P, _P]),
     "mknn_device_bytes": (_I64, [_P]),
     "mknn_knn": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P]),
     "mknn_knn_var": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P]),
@@ -36,6 +35,12 @@ SIGNATURES = {
     "mknn_last_error": (ctypes.c_char_p, []),
     "mknn_version": (ctypes.c_char_p, []),
 }
+
+class TuneEntry(ctypes.Structure):
+    """mknn_tune_entry of mknn.h"""
+    _fields_ = [("family", ctypes.c_int32), ("merge_min", ctypes.c_int32),
+                ("per_wave", ctypes.c_int32), ("ms", ctypes.c_float)]
+
 
 class Request(ctypes.Structure):
     """mknn_request of mknn.h"""
@@ -66,6 +71,14 @@ SIGNATURES.update({
     "mknn_server_now": (ctypes.c_double, []),
     "mknn_server_destroy": (None, [_P]),
     "mknn_live_count": (_I64, [_P]),
+    "mknn_compact": (ctypes.c_int, [_P, _P]),
+    "mknn_autotune": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, ctypes.POINTER(TuneEntry), _I32,
+                                     ctypes.POINTER(_I32), ctypes.POINTER(TuneEntry)]),
+    "mknn_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "mknn_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "mknn_tune_reset": (None, []),
+    "mknn_batch_plan_tune": (ctypes.c_int, [_P, ctypes.POINTER(Request), _I32, _P,
+                                            ctypes.POINTER(_I32)]),
     "mknn_head": (_I32, [_P]),
 })
 

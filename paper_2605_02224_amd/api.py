@@ -162,6 +162,38 @@ class Cloud:
         return (ce, cl, ci) if inserts else (ce, cl)
 
 
+FAMILIES = {1: "lane", 2: "group", 3: "rows"}
+
+
+def autotune(cloud, q, k: int, m: Optional[int] = None, stream=None):
+    """Time every kernel configuration on these queries and keep the fastest for clouds of
+    this size class and this k class.  Returns (best, tried) as dicts."""
+    tried = (_lib.TuneEntry * 16)()
+    best = _lib.TuneEntry()
+    n = ctypes.c_int32()
+    q = q.contiguous()
+    check(_lib.lib().mknn_autotune(cloud.handle, _ptr(q), q.shape[0], int(k),
+                                   0 if m is None else int(m), _stream(stream), tried, 16,
+                                   ctypes.byref(n), ctypes.byref(best)))
+
+    def d(e):
+        return {"family": FAMILIES[e.family], "merge_min": e.merge_min,
+                "per_wave": e.per_wave, "ms": float(e.ms)}
+    return d(best), [d(tried[i]) for i in range(min(n.value, 16))]
+
+
+def tune_save(path: str) -> None:
+    check(_lib.lib().mknn_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> None:
+    check(_lib.lib().mknn_tune_load(path.encode()))
+
+
+def tune_reset() -> None:
+    _lib.lib().mknn_tune_reset()
+
+
 def _requests(items):
     """items: sequence of (cloud, q, k, m, idx, dist) -> ctypes array of mknn_request."""
     arr = (_lib.Request * max(1, len(items)))()
@@ -202,6 +234,14 @@ class BatchPlan:
         """items: sequence of (cloud, q, k, m, idx, dist); enqueues the batch."""
         self._keep = _requests(items)
         check(_lib.lib().mknn_batch_plan_run(self._h, self._keep, len(items), _stream(stream)))
+
+    def tune(self, items, stream=None) -> int:
+        """Pick the fastest tile length for batches like this one; returns it."""
+        self._keep = _requests(items)
+        t = ctypes.c_int32()
+        check(_lib.lib().mknn_batch_plan_tune(self._h, self._keep, len(items), _stream(stream),
+                                              ctypes.byref(t)))
+        return t.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

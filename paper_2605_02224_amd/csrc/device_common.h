@@ -109,8 +109,13 @@ mknn_status pack_lists(mknn_cloud *c, HostPack *p);
 mknn_status install_pack(mknn_cloud *c, const HostPack *p, hipStream_t s);
 extern "C" mknn_status mknn_upload(mknn_cloud *c, void *stream);
 
-// Candidates per chunk from which the k <= 16 path merges with a network (MKNN_MERGE_MIN).
-int32_t merge_min();
+// A launch configuration of the query kernels (see mknn_device.hip).
+struct TuneConfig {
+  int32_t family;      // 1 lane per query, 2 lockstep rows, 3 scheduled rows
+  int32_t merge_min;   // k <= 16: candidates per chunk from which the merge network is used
+  int32_t per_wave;    // row kernel: queries per wavefront
+};
+TuneConfig config_for(int kmax, bool exact, int64_t n);
 
 // Optional HIP-event timing of the main query kernels (defined in mknn_device.hip).
 hipError_t timing_mark(hipStream_t s, bool start);

@@ -483,7 +483,7 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   for (int32_t r = 0; r < nreq; ++r) {
     const mknn_request &q = reqs[r];
     fill_cloud_args(q.cloud, &args[r]);
-    args[r].merge_min = merge_min();
+    args[r].merge_min = config_for(q.k, false, q.cloud->n).merge_min;
     args[r].q = q.d_q;
     args[r].qs = p->sort ? p->d_qs + qoff[r] : nullptr;
     args[r].nq = q.nq;
@@ -518,6 +518,46 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   }
   HIP_TRY(hipEventRecord(p->done, s), "mknn_batch_plan_run: record");
   p->pending = true;
+  return MKNN_OK;
+}
+
+mknn_status mknn_batch_plan_tune(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
+                                 void *stream, int32_t *best_tile) {
+  clear_error();
+  if (!p) return set_error(MKNN_EINVAL, "mknn_batch_plan_tune: plan is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0), "mknn_batch_plan_tune: event");
+  hipError_t e = hipEventCreate(&e1);
+  const int32_t keep = p->tile_q;
+  int32_t best = keep;
+  float best_ms = INFINITY;
+  mknn_status st = MKNN_OK;
+  for (int32_t t : {8, 16, 32, 64, 256}) {
+    p->tile_q = t;
+    float tm = INFINITY;
+    for (int rep = 0; rep < 4 && e == hipSuccess && st == MKNN_OK; ++rep) {
+      e = hipEventRecord(e0, s);
+      if (e == hipSuccess) st = mknn_batch_plan_run(p, reqs, nreq, stream);
+      if (st != MKNN_OK || e != hipSuccess) break;
+      e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float v = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&v, e0, e1);
+      if (e == hipSuccess && rep > 0) tm = std::min(tm, v);
+    }
+    if (st != MKNN_OK || e != hipSuccess) break;
+    if (tm < best_ms) {
+      best_ms = tm;
+      best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  p->tile_q = (st == MKNN_OK && e == hipSuccess) ? best : keep;
+  if (st != MKNN_OK) return st;
+  if (e != hipSuccess) return set_error(MKNN_EHIP, std::string("mknn_batch_plan_tune: ") + hipGetErrorName(e));
+  if (best_tile) *best_tile = best;
   return MKNN_OK;
 }
 

@@ -22,7 +22,10 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <map>
+#include <mutex>
 #include <vector>
+#include <map>
 
 #include "device_common.h"
 #include "knn_group.h"
@@ -476,6 +479,61 @@ hipError_t timing_mark(hipStream_t s, bool start) {
   return hipEventRecord(g_events[g_events_used++].second, s);
 }
 
+
+// ---------------------------------------------------------------------------------------
+// Launch configuration and the autotuner's table
+//
+// A configuration picks the kernel family (1: one query per lane, 2: 16 lanes per query in
+// lockstep, 3: 16 lanes per query with independently scheduled rows), the number of
+// candidates per chunk from which k <= 16 merges with the network instead of inserting one
+// by one, and the queries per wavefront of the row kernel.  mknn_autotune fills a table
+// keyed by (device, slots per lane S, k == 16 S, log2 n); launches look their key up and
+// fall back to the measured defaults.  Environment variables override both (experiments).
+// ---------------------------------------------------------------------------------------
+static long env_long(const char *name, long dflt) {
+  const char *e = getenv(name);
+  return e ? atol(e) : dflt;
+}
+
+static const TuneConfig kDefaultConfig = {3, 6, 4};   // measured on the 1M torus, k = 16
+
+static std::mutex g_tune_mu;
+static std::map<uint64_t, TuneConfig> g_tune;
+
+static uint64_t tune_key(int dev, int S, bool exact, int64_t n) {
+  int b = 0;
+  while (b < 40 && ((int64_t)1 << (b + 1)) <= n) ++b;
+  return ((uint64_t)(uint32_t)dev << 32) | ((uint64_t)S << 16) | ((uint64_t)(exact ? 1 : 0) << 8) |
+         (uint64_t)b;
+}
+
+static TuneConfig env_overrides(TuneConfig c) {
+  static long fam = -2, mm = -2, pw = -2;
+  if (fam == -2) {
+    const char *v = getenv("MKNN_KERNEL");
+    fam = (v && v[0] == 'l') ? 1 : (v && v[0] == 'g') ? 2 : (v && v[0] == 'r') ? 3 : 0;
+    mm = env_long("MKNN_MERGE_MIN", 0);
+    pw = env_long("MKNN_PER_WAVE", 0);
+  }
+  if (fam > 0) c.family = (int32_t)fam;
+  if (mm > 0) c.merge_min = (int32_t)mm;
+  if (pw >= 4) c.per_wave = (int32_t)pw;
+  return c;
+}
+
+TuneConfig config_for(int kmax, bool exact, int64_t n) {
+  const int S = (kmax + 15) / 16;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  TuneConfig c = kDefaultConfig;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(dev, S, exact && kmax == 16 * S, n));
+    if (it != g_tune.end()) c = it->second;
+  }
+  return env_overrides(c);
+}
+
 template <int K, bool EXACTK, bool COUNT>
 static hipError_t launch_lane(const QueryArgs &a, hipStream_t s) {
   const int threads = 256;
@@ -484,34 +542,34 @@ static hipError_t launch_lane(const QueryArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-
-// Optional dynamic LDS per workgroup, used only to cap occupancy in tuning experiments.
-// Candidates per chunk (most over the rows of a wavefront) from which k <= 16 uses the
-// merge network instead of inserting one by one.
-int32_t merge_min() {
-  static long v = -1;
-  if (v < 0) {
-    const char *e = getenv("MKNN_MERGE_MIN");
-    v = e ? atol(e) : 6;   // measured optimum on the 1M torus at k = 16 (sweep 1..17)
-    if (v < 1) v = 1;
-  }
-  return (int32_t)v;
+template <bool COUNT>
+static hipError_t dispatch_lane(const QueryArgs &a, int kmax, bool exact, hipStream_t s) {
+#define MKNN_CASE(KK)                                                                       \
+  if (kmax <= KK)                                                                          \
+    return (exact && kmax == KK) ? launch_lane<KK, true, COUNT>(a, s)                     \
+                                 : launch_lane<KK, false, COUNT>(a, s);
+  MKNN_CASE(1)
+  MKNN_CASE(2)
+  MKNN_CASE(4)
+  MKNN_CASE(8)
+  MKNN_CASE(16)
+  MKNN_CASE(32)
+  MKNN_CASE(64)
+#undef MKNN_CASE
+  return hipErrorInvalidValue;
 }
 
+// Optional dynamic LDS per workgroup of the group kernel, used only to cap occupancy in
+// experiments (MKNN_LDS_PAD bytes).
 static size_t lds_pad() {
   static long v = -1;
-  if (v < 0) {
-    const char *e = getenv("MKNN_LDS_PAD");
-    v = e ? atol(e) : 0;
-  }
+  if (v < 0) v = env_long("MKNN_LDS_PAD", 0);
   return (size_t)v;
 }
 
 template <int S, bool EXACTK, bool COUNT>
-static hipError_t launch_group(const QueryArgs &a0, hipStream_t s) {
+static hipError_t launch_group(const QueryArgs &a, hipStream_t s) {
   const int threads = 256;   // 4 waves x 4 queries
-  QueryArgs a = a0;
-  a.merge_min = merge_min();
   const uint32_t blocks = (uint32_t)((a.nq + 15) / 16);
   hipLaunchKernelGGL((knn_group_kernel<S, EXACTK, COUNT>), dim3(blocks), dim3(threads), lds_pad(),
                      s, a);
@@ -532,31 +590,20 @@ static hipError_t dispatch_group(const QueryArgs &a, int kmax, bool exact, hipSt
   return hipErrorInvalidValue;
 }
 
-
-// Queries per wavefront of the row-scheduled kernel (MKNN_PER_WAVE).
-static int32_t rows_per_wave() {
-  static long v = -1;
-  if (v < 0) {
-    const char *e = getenv("MKNN_PER_WAVE");
-    v = e ? atol(e) : 4;   // one query per row measured fastest (sweep 4..64, 1M torus)
-    if (v < 4) v = 4;
-  }
-  return (int32_t)v;
-}
-
 template <int S, bool EXACTK>
-static hipError_t launch_rows(const QueryArgs &a0, hipStream_t s) {
-  QueryArgs a = a0;
-  a.merge_min = merge_min();
-  const int32_t pw = rows_per_wave();
-  const int64_t waves = (a.nq + pw - 1) / pw;
+static hipError_t launch_rows(const QueryArgs &a, int32_t per_wave, hipStream_t s) {
+  const int64_t waves = (a.nq + per_wave - 1) / per_wave;
   const uint32_t blocks = (uint32_t)((waves + 3) / 4);
-  hipLaunchKernelGGL((knn_rows_kernel<S, EXACTK>), dim3(blocks), dim3(256), 0, s, a, pw);
+  hipLaunchKernelGGL((knn_rows_kernel<S, EXACTK>), dim3(blocks), dim3(256), 0, s, a, per_wave);
   return hipGetLastError();
 }
 
-static hipError_t dispatch_rows(const QueryArgs &a, int kmax, bool exact, hipStream_t s) {
-#define MKNN_RCASE(SS)                                                                        if (kmax <= 16 * SS)                                                                         return (exact && kmax == 16 * SS) ? launch_rows<SS, true>(a, s)                                                             : launch_rows<SS, false>(a, s);
+static hipError_t dispatch_rows(const QueryArgs &a, int kmax, bool exact, int32_t per_wave,
+                                hipStream_t s) {
+#define MKNN_RCASE(SS)                                                                      \
+  if (kmax <= 16 * SS)                                                                     \
+    return (exact && kmax == 16 * SS) ? launch_rows<SS, true>(a, per_wave, s)             \
+                                      : launch_rows<SS, false>(a, per_wave, s);
   MKNN_RCASE(1)
   MKNN_RCASE(2)
   MKNN_RCASE(3)
@@ -564,41 +611,6 @@ static hipError_t dispatch_rows(const QueryArgs &a, int kmax, bool exact, hipStr
 #undef MKNN_RCASE
   return hipErrorInvalidValue;
 }
-
-// kernel family: 0 = automatic, 1 = one query per lane, 2 = 16 lanes per query,
-// 3 = 16 lanes per query with rows scheduled independently
-static int g_family = 0;
-
-static int family_for(int kmax) {
-  if (g_family) return g_family;
-  static int env = -1;
-  if (env < 0) {
-    const char *v = getenv("MKNN_KERNEL");
-    env = (v && v[0] == 'l') ? 1 : (v && v[0] == 'g') ? 2 : (v && v[0] == 'r') ? 3 : 0;
-  }
-  if (env) return env;
-  (void)kmax;
-  return 3;
-}
-
-template <bool COUNT>
-static hipError_t dispatch_lane(const QueryArgs &a, int kmax, bool exact, hipStream_t s) {
-#define MKNN_CASE(KK)                                                                       \
-  if (kmax <= KK)                                                                          \
-    return (exact && kmax == KK) ? launch_lane<KK, true, COUNT>(a, s)                     \
-                                 : launch_lane<KK, false, COUNT>(a, s);
-  MKNN_CASE(1)
-  MKNN_CASE(2)
-  MKNN_CASE(4)
-  MKNN_CASE(8)
-  MKNN_CASE(16)
-  MKNN_CASE(32)
-  MKNN_CASE(64)
-#undef MKNN_CASE
-  return hipErrorInvalidValue;
-}
-
-
 
 // Morton bucketing of the queries into stream-ordered scratch, for batches large enough
 // to pay for it.
@@ -628,7 +640,7 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
                              int32_t m, const int32_t *d_k, const int32_t *d_m,
                              const int64_t *d_row_off, int32_t kmax, int32_t *d_idx,
                              float *d_dist, int32_t *d_ce, int32_t *d_cl, int32_t *d_ci,
-                             hipStream_t s, const char *who) {
+                             hipStream_t s, const char *who, const TuneConfig *force = nullptr) {
   QueryArgs a;
   fill_cloud_args(c, &a);
   a.q = d_q;
@@ -649,13 +661,14 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
   if (st != MKNN_OK) return st;
   a.qs = qs;
   const bool exact = (d_k == nullptr);
-  const int fam = family_for(kmax);
+  const TuneConfig cfg = force ? *force : config_for(kmax, exact, c->n);
+  a.merge_min = cfg.merge_min;
   hipError_t e = timing_mark(s, true);
   if (e == hipSuccess) {
-    if (fam == 1)
+    if (cfg.family == 1)
       e = d_ce ? dispatch_lane<true>(a, kmax, exact, s) : dispatch_lane<false>(a, kmax, exact, s);
-    else if (fam == 3 && !d_ce)
-      e = dispatch_rows(a, kmax, exact, s);
+    else if (cfg.family == 3 && !d_ce)
+      e = dispatch_rows(a, kmax, exact, cfg.per_wave, s);
     else
       e = d_ce ? dispatch_group<true>(a, kmax, exact, s) : dispatch_group<false>(a, kmax, exact, s);
   }
@@ -756,6 +769,125 @@ mknn_status mknn_knn_counts(const mknn_cloud *c, const float *d_q, int64_t nq, i
   if (!d_q || !d_entries || !d_lists) return set_error(MKNN_EINVAL, "mknn_knn_counts: NULL buffer");
   return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, nullptr, nullptr, d_entries,
                    d_lists, d_inserts, (hipStream_t)stream, "mknn_knn_counts");
+}
+
+mknn_status mknn_autotune(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k, int32_t m,
+                          void *stream, mknn_tune_entry *tried, int32_t max_tried,
+                          int32_t *ntried, mknn_tune_entry *best) {
+  clear_error();
+  if (k > MKNN_KMAX) return set_error(MKNN_EUNSUPPORTED, "mknn_autotune: k above MKNN_KMAX");
+  if (k < 1) return set_error(MKNN_EINVAL, "mknn_autotune: k must be >= 1");
+  if (nq < 1 || nq > 0x7fffffffll) return set_error(MKNN_EINVAL, "mknn_autotune: nq out of range");
+  if (!d_q || (max_tried > 0 && !tried)) return set_error(MKNN_EINVAL, "mknn_autotune: NULL buffer");
+  mknn_status st = check_uploaded(c, "mknn_autotune");
+  if (st != MKNN_OK) return st;
+  if (m == 0) m = (int32_t)c->n;
+  if (m < 1 || m > c->n) return set_error(MKNN_EINVAL, "mknn_autotune: m must be in [0, n]");
+  const int S = (k + 15) / 16;
+  std::vector<TuneConfig> cand;
+  for (int pw : {4, 8}) {
+    if (S == 1)
+      for (int mm : {4, 6, 8}) cand.push_back({3, mm, pw});
+    else
+      cand.push_back({3, 6, pw});
+  }
+  cand.push_back({2, 6, 4});
+  cand.push_back({1, 6, 4});
+  hipStream_t s = (hipStream_t)stream;
+  void *out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const size_t cnt = (size_t)nq * (size_t)k;
+  HIP_TRY(hipMallocAsync(&out, cnt * (sizeof(int32_t) + sizeof(float)), s), "mknn_autotune: scratch");
+  int32_t *d_idx = (int32_t *)out;
+  float *d_dist = (float *)(d_idx + cnt);
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  std::vector<float> ms(cand.size(), INFINITY);
+  for (size_t t = 0; t < cand.size() && e == hipSuccess && st == MKNN_OK; ++t) {
+    for (int rep = 0; rep < 4 && e == hipSuccess && st == MKNN_OK; ++rep) {
+      e = hipEventRecord(e0, s);
+      if (e != hipSuccess) break;
+      st = run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, d_idx, d_dist, nullptr,
+                     nullptr, nullptr, s, "mknn_autotune", &cand[t]);
+      if (st != MKNN_OK) break;
+      e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float v = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&v, e0, e1);
+      if (e == hipSuccess && rep > 0) ms[t] = std::min(ms[t], v);   // first run warms up
+    }
+  }
+  (void)hipFreeAsync(out, s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st != MKNN_OK) return st;
+  if (e != hipSuccess) return set_error(MKNN_EHIP, std::string("mknn_autotune: ") + hipGetErrorName(e));
+  size_t bi = 0;
+  for (size_t t = 1; t < cand.size(); ++t)
+    if (ms[t] < ms[bi]) bi = t;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(dev, S, k == 16 * S, c->n)] = cand[bi];
+  }
+  const int32_t n_out = (int32_t)std::min<size_t>(cand.size(), max_tried > 0 ? (size_t)max_tried : 0);
+  for (int32_t t = 0; t < n_out; ++t)
+    tried[t] = {cand[t].family, cand[t].merge_min, cand[t].per_wave, ms[t]};
+  if (ntried) *ntried = (int32_t)cand.size();
+  if (best) *best = {cand[bi].family, cand[bi].merge_min, cand[bi].per_wave, ms[bi]};
+  return MKNN_OK;
+}
+
+void mknn_tune_reset(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+mknn_status mknn_tune_save(const char *path) {
+  clear_error();
+  if (!path) return set_error(MKNN_EINVAL, "mknn_tune_save: path is NULL");
+  std::FILE *f = std::fopen(path, "w");
+  if (!f) return set_error(MKNN_EINVAL, std::string("mknn_tune_save: cannot write ") + path);
+  std::fprintf(f, "mknn-tune 1\n");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto &kv : g_tune) {
+    const uint64_t key = kv.first;
+    std::fprintf(f, "%u %u %u %u %d %d %d\n", (unsigned)(key >> 32), (unsigned)((key >> 16) & 0xffff),
+                 (unsigned)((key >> 8) & 0xff), (unsigned)(key & 0xff), kv.second.family,
+                 kv.second.merge_min, kv.second.per_wave);
+  }
+  const bool ok = std::fclose(f) == 0;
+  return ok ? MKNN_OK : set_error(MKNN_EINVAL, std::string("mknn_tune_save: write failed: ") + path);
+}
+
+mknn_status mknn_tune_load(const char *path) {
+  clear_error();
+  if (!path) return set_error(MKNN_EINVAL, "mknn_tune_load: path is NULL");
+  std::FILE *f = std::fopen(path, "r");
+  if (!f) return set_error(MKNN_ENOTFOUND, std::string("mknn_tune_load: cannot read ") + path);
+  char magic[16] = {0};
+  int ver = 0;
+  std::map<uint64_t, TuneConfig> table;
+  bool ok = std::fscanf(f, "%15s %d", magic, &ver) == 2 && std::string(magic) == "mknn-tune" && ver == 1;
+  unsigned dev, S, exact, bucket;
+  int fam, mm, pw;
+  while (ok) {
+    const int got = std::fscanf(f, "%u %u %u %u %d %d %d", &dev, &S, &exact, &bucket, &fam, &mm, &pw);
+    if (got == EOF) break;
+    if (got != 7 || S < 1 || S > 4 || exact > 1 || bucket > 40 || fam < 1 || fam > 3 || mm < 1 ||
+        mm > 17 || pw < 4 || pw > 4096) {
+      ok = false;
+      break;
+    }
+    const uint64_t key = ((uint64_t)dev << 32) | ((uint64_t)S << 16) | ((uint64_t)exact << 8) | bucket;
+    table[key] = {fam, mm, pw};
+  }
+  std::fclose(f);
+  if (!ok) return set_error(MKNN_EINVAL, std::string("mknn_tune_load: malformed file ") + path);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto &kv : table) g_tune[kv.first] = kv.second;
+  return MKNN_OK;
 }
 
 mknn_status mknn_timing_enable(int enable) {

@@ -1,0 +1,68 @@
+"""GPU tests of the autotuner: every candidate configuration is timed, the chosen one is
+used afterwards, and results do not depend on the configuration (bitwise) and match the
+oracle."""
+import numpy as np
+import pytest
+
+from tests._compare import compare_rows
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    oracle.build(force=False)
+    from paper_2605_02224_amd import api as A
+    from paper_2605_02224_amd import workloads as W
+    return torch, oracle, A, W
+
+
+@pytest.mark.parametrize("k", [5, 16, 40])
+def test_autotune_keeps_results(env, k, tmp_path):
+    torch, oracle, A, W = env
+    P = W.random_cloud(40000, seed=31 + k, shape="torus").by_rank
+    cl = A.Cloud.build(P).upload()
+    Q = W.uniform_in_box(np.random.default_rng(k), 20000, *W.bbox_expanded(P, 1.1))
+    q = torch.from_numpy(Q).cuda()
+    A.tune_reset()
+    before = cl.knn(q, k)
+    best, tried = A.autotune(cl, q, k)
+    assert len(tried) >= 4 and best in tried
+    assert all(t["ms"] > 0 for t in tried)
+    assert best["ms"] == min(t["ms"] for t in tried)
+    after = cl.knn(q, k)
+    torch.cuda.synchronize()
+    assert torch.equal(before[0], after[0]) and torch.equal(before[1], after[1])
+    ri, _, rD = oracle.knn_bruteforce(P, Q[:2000], k + 1)
+    compare_rows(after[0].cpu().numpy()[:2000], after[1].cpu().numpy()[:2000], ri[:, :k],
+                 rD[:, :k], rD[:, k])
+    path = tmp_path / "tune.txt"
+    A.tune_save(str(path))
+    assert len(path.read_text().splitlines()) == 2
+    A.tune_reset()
+
+
+def test_batch_plan_tune(env):
+    torch, oracle, A, W = env
+    rng = np.random.default_rng(9)
+    items = []
+    for i in range(12):
+        P = W.random_cloud(int(rng.integers(2000, 30000)), seed=60 + i, shape=W.SHAPES[i % 3]).by_rank
+        cl = A.Cloud.build(P).upload()
+        Q = W.uniform_in_box(rng, int(rng.integers(100, 20000)), *W.bbox_expanded(P, 1.1))
+        items.append((cl, torch.from_numpy(Q).cuda(), int(rng.choice([3, 10, 16, 33])), None))
+    items = A.alloc_outputs(items)
+    plan = A.BatchPlan(len(items), sum(it[1].shape[0] for it in items))
+    tile = plan.tune(items)
+    assert tile in (8, 16, 32, 64, 256)
+    plan.run(items)
+    torch.cuda.synchronize()
+    for cl, q, k, m, idx, dist in items:
+        ri, rd = cl.knn(q, k)
+        torch.cuda.synchronize()
+        assert torch.equal(ri, idx) and torch.equal(rd, dist)
+    plan.close()
