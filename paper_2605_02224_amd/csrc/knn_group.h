@@ -28,9 +28,12 @@ __device__ __forceinline__ uint32_t row_bits(uint64_t ballot, int g) {
   return (uint32_t)(ballot >> (16 * g)) & 0xffffu;
 }
 
-// (da, ra) < (db, rb) lexicographically; bitwise operators keep it free of branches
+// (da, ra) < (db, rb) lexicographically; bitwise operators keep it free of branches.
+// Squared distances are never negative (nor -0.0, nor NaN), so their IEEE bit patterns
+// order like unsigned integers; +inf marks empty slots and compares above every distance.
 __device__ __forceinline__ bool key_less(double da, int32_t ra, double db, int32_t rb) {
-  return (da < db) | ((da == db) & (ra < rb));
+  const uint64_t ua = (uint64_t)__double_as_longlong(da), ub = (uint64_t)__double_as_longlong(db);
+  return (ua < ub) | ((ua == ub) & (ra < rb));
 }
 
 // DPP row moves (within each row of 16 lanes):
@@ -38,6 +41,7 @@ __device__ __forceinline__ bool key_less(double da, int32_t ra, double db, int32
 //   row_newbcast:15  every lane reads lane 15 of its row
 constexpr int kDppRowShr1 = 0x111;
 constexpr int kDppRowBcast15 = 0x15F;
+constexpr int kDppRowBcast0 = 0x150;    // row_newbcast:0, every lane reads lane 0 of its row
 
 // Every use below either has a valid source lane for every lane or ignores the lanes that
 // do not (row_shr:1 at lane 0), so the DPP move needs no "old" operand (bound_ctrl).
@@ -156,25 +160,28 @@ struct RowTopK {
 #pragma unroll
     for (int s = 0; s < S; ++s)
       pos += __popc(row_bits(__ballot(key_less(d[s], r[s], cd, cr)), g));
-    // slot 16 s + l takes slot 16 s + l - 1 when it lies after the insertion point
-    double pd[S];
-    int32_t pr[S];
+    // slot 16 s + l takes slot 16 s + l - 1 when it lies after the insertion point; lane 0
+    // of slot s takes lane 15 of slot s - 1.  Slots that lie wholly before every row's
+    // insertion point stay as they are.
+    double wd = 0.0;
+    int32_t wr = 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      pd[s] = dpp_f64<kDppRowShr1>(d[s], d[s]);
-      pr[s] = dpp_i32<kDppRowShr1>(r[s], r[s]);
-      if (s > 0) {
-        const double wd = dpp_f64<kDppRowBcast15>(d[s - 1], d[s - 1]);
-        const int32_t wr = dpp_i32<kDppRowBcast15>(r[s - 1], r[s - 1]);
-        pd[s] = (l == 0) ? wd : pd[s];
-        pr[s] = (l == 0) ? wr : pr[s];
+      const double last_d = S > 1 ? dpp_f64<kDppRowBcast15>(d[s], d[s]) : 0.0;
+      const int32_t last_r = S > 1 ? dpp_i32<kDppRowBcast15>(r[s], r[s]) : 0;
+      if (S == 1 || __ballot(pos <= 16 * s + 15) != 0) {
+        double pd = dpp_f64<kDppRowShr1>(d[s], d[s]);
+        int32_t pr = dpp_i32<kDppRowShr1>(r[s], r[s]);
+        if (s > 0) {
+          pd = (l == 0) ? wd : pd;
+          pr = (l == 0) ? wr : pr;
+        }
+        const int j = 16 * s + l;
+        d[s] = j > pos ? pd : (j == pos ? cd : d[s]);
+        r[s] = j > pos ? pr : (j == pos ? cr : r[s]);
       }
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int j = 16 * s + l;
-      d[s] = j > pos ? pd[s] : (j == pos ? cd : d[s]);
-      r[s] = j > pos ? pr[s] : (j == pos ? cr : r[s]);
+      wd = last_d;
+      wr = last_r;
     }
     if (EXACTK) {
       thr_d = dpp_f64<kDppRowBcast15>(d[S - 1], d[S - 1]);
@@ -210,6 +217,74 @@ struct RowTopK {
     if (EXACTK) {
       thr_d = dpp_f64<kDppRowBcast15>(d[0], d[0]);
       thr_r = dpp_i32<kDppRowBcast15>(r[0], r[0]);
+    } else {
+      slot(k - 1, thr_d, thr_r);
+    }
+    return better ? 1 : 0;
+  }
+
+  // k > 16 (S slots per lane; slot s of lane l holds position 16 s + l): merge every lane's
+  // candidate with `better` set at once.  The candidates are sorted across the row and
+  // carried through the slots in order: at slot s the elementwise minimum of the slot and
+  // the mirrored carry (bitonic) becomes the new slot, the maximum (bitonic) the new carry,
+  // each sorted by a 4-stage bitonic merge; what is carried out of the last slot drops out.
+  // A slot whose largest key lies below every row's smallest carried key is left alone.
+  // Candidates already in N can only equal a key of a slot that is merged; they are dropped
+  // there (and the carry compacted) before the merge.
+  __device__ __forceinline__ int mergeS(bool better, double dd, int32_t rr, int l, int g,
+                                        int k) {
+    static_assert(S > 1, "mergeS serves more than one slot per lane");
+    double cd = better ? dd : INFINITY;
+    int32_t cr = better ? rr : kEmpty;
+    row_sort16(cd, cr, l);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double c0d = dpp_f64<kDppRowBcast0>(cd, cd);
+      const int32_t c0r = dpp_i32<kDppRowBcast0>(cr, cr);
+      const double n15d = dpp_f64<kDppRowBcast15>(d[s], d[s]);
+      const int32_t n15r = dpp_i32<kDppRowBcast15>(r[s], r[s]);
+      if (__ballot(!key_less(n15d, n15r, c0d, c0r)) == 0) continue;   // nothing lands here
+      // evaluated by every lane: the row moves must see all 16 ranks of the slot
+      const bool seen = in_row(cr, r[s], std::make_integer_sequence<int, 16>{});
+      const bool dup = seen & (cr != kEmpty);
+      if (__ballot(dup) != 0) {
+        cd = dup ? INFINITY : cd;
+        cr = dup ? kEmpty : cr;
+        // stable compaction of the row: kept candidates first, +inf after
+        const bool keep = cr != kEmpty;
+        const uint32_t bits = row_bits(__ballot(keep), g);
+        const int below = __popc(bits & ((1u << l) - 1u));
+        const int dst = keep ? below : __popc(bits) + (l - below);
+        const int addr = 4 * (16 * g + dst);
+        const int64_t v = __double_as_longlong(cd);
+        const int32_t lo = __builtin_amdgcn_ds_permute(addr, (int32_t)v);
+        const int32_t hi = __builtin_amdgcn_ds_permute(addr, (int32_t)(v >> 32));
+        cr = __builtin_amdgcn_ds_permute(addr, cr);
+        cd = __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+      }
+      const double md = xor_lane_f64<15>(cd);
+      const int32_t mr = xor_lane<15>(cr);
+      const bool lt = key_less(md, mr, d[s], r[s]);
+      double lod = lt ? md : d[s], hid = lt ? d[s] : md;
+      int32_t lor = lt ? mr : r[s], hir = lt ? r[s] : mr;
+      cas_stage<8, 8>(lod, lor, l);
+      cas_stage<4, 4>(lod, lor, l);
+      cas_stage<2, 2>(lod, lor, l);
+      cas_stage<1, 1>(lod, lor, l);
+      d[s] = lod;
+      r[s] = lor;
+      if (s + 1 < S) {
+        cas_stage<8, 8>(hid, hir, l);
+        cas_stage<4, 4>(hid, hir, l);
+        cas_stage<2, 2>(hid, hir, l);
+        cas_stage<1, 1>(hid, hir, l);
+        cd = hid;
+        cr = hir;
+      }
+    }
+    if (EXACTK) {
+      thr_d = dpp_f64<kDppRowBcast15>(d[S - 1], d[S - 1]);
+      thr_r = dpp_i32<kDppRowBcast15>(r[S - 1], r[S - 1]);
     } else {
       slot(k - 1, thr_d, thr_r);
     }

@@ -27,13 +27,14 @@ __device__ __forceinline__ void offer_all(RowTopK<S, EXACTK> &N, bool cand, doub
                                           int32_t rr, int l, int g, int k, int merge_min) {
   const uint64_t wb = __ballot(cand);
   if (wb == 0) return;
-  if constexpr (S == 1) {
-    const int most = max(max(__popc((uint32_t)wb & 0xffffu), __popc((uint32_t)(wb >> 16) & 0xffffu)),
-                         max(__popc((uint32_t)(wb >> 32) & 0xffffu), __popc((uint32_t)(wb >> 48))));
-    if (most >= merge_min) {
+  const int most = max(max(__popc((uint32_t)wb & 0xffffu), __popc((uint32_t)(wb >> 16) & 0xffffu)),
+                       max(__popc((uint32_t)(wb >> 32) & 0xffffu), __popc((uint32_t)(wb >> 48))));
+  if (most >= merge_min) {
+    if constexpr (S == 1)
       N.merge16(cand, dd, rr, l, k);
-      return;
-    }
+    else
+      N.mergeS(cand, dd, rr, l, g, k);
+    return;
   }
   N.insert_all(cand, dd, rr, l, g, k);
 }

@@ -495,7 +495,12 @@ static long env_long(const char *name, long dflt) {
   return e ? atol(e) : dflt;
 }
 
-static const TuneConfig kDefaultConfig = {3, 6, 4};   // measured on the 1M torus, k = 16
+// Defaults measured on the 1M torus: scheduled rows, one query per row, and the merge
+// network from 6 / 9 / 11 / 14 candidates per chunk for S = 1..4 slots per lane.
+static TuneConfig default_config(int S) {
+  static const int32_t mm[4] = {6, 9, 11, 14};
+  return {3, mm[(S < 1 ? 1 : S > 4 ? 4 : S) - 1], 4};
+}
 
 static std::mutex g_tune_mu;
 static std::map<uint64_t, TuneConfig> g_tune;
@@ -525,7 +530,7 @@ TuneConfig config_for(int kmax, bool exact, int64_t n) {
   const int S = (kmax + 15) / 16;
   int dev = 0;
   (void)hipGetDevice(&dev);
-  TuneConfig c = kDefaultConfig;
+  TuneConfig c = default_config(S);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(tune_key(dev, S, exact && kmax == 16 * S, n));
@@ -789,7 +794,7 @@ mknn_status mknn_autotune(const mknn_cloud *c, const float *d_q, int64_t nq, int
     if (S == 1)
       for (int mm : {4, 6, 8}) cand.push_back({3, mm, pw});
     else
-      cand.push_back({3, 6, pw});
+      for (int mm : {8, 11, 14, 17}) cand.push_back({3, mm, pw});   // 17: never the network
   }
   cand.push_back({2, 6, 4});
   cand.push_back({1, 6, 4});
