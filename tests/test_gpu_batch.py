@@ -119,3 +119,31 @@ def test_batch_errors(env):
     big = torch.zeros((101, 3), dtype=torch.float32, device="cuda")
     with pytest.raises(MknnError):
         plan.run(A.alloc_outputs([(cl, big, 4, 0)]))            # over query capacity
+
+
+def test_256_clouds_paper_scale_sampled(env):
+    """Batched form at full size: 256 clouds, sizes log-uniform in [1e3, 2e5] (about 10M
+    points), 4 n_c queries each, k=10, one batch in the launch configuration the benchmark
+    times (default 16-query tiles, sorted, graph), checked on a sample of every cloud's rows."""
+    torch, oracle, A, W, _ = env
+    import concurrent.futures as cf
+    w = W.many_clouds()
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
+        built = list(ex.map(lambda c: A.Cloud.build(c.by_rank), w.clouds))
+    for cl in built:
+        cl.upload()
+    items = A.alloc_outputs([(cl, torch.from_numpy(q).cuda(), w.k, None)
+                             for cl, q in zip(built, w.queries)])
+    plan = A.BatchPlan(len(items), sum(it[1].shape[0] for it in items))
+    plan.run(items)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    exc = 0
+    for c, (cl, q, k, m, idx, dist) in zip(w.clouds, items):
+        sel = rng.choice(q.shape[0], 24, replace=False)
+        Qs = q.cpu().numpy()[sel]
+        ri, _, rD = oracle.knn_bruteforce(c.by_rank, Qs, k + 1)
+        exc += compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k], rD[:, :k],
+                            rD[:, k])
+    assert exc <= 3
+    plan.close()

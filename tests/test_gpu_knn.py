@@ -178,3 +178,33 @@ def test_torus_1m_paper_scale_sampled(env):
             ex = compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k],
                               rD[:, :k], rD[:, k])
             assert ex <= 2
+
+
+def test_heightfield_2m_prefix_paper_scale_sampled(env):
+    """Dynamic prefix queries at full size: 2M height-field points, 2M volume queries, each with
+    its own prefix m (log-uniform in [n/1000, n]) and k in {1, 8, 32}, checked on a seeded
+    sample of rows against the oracle with the same per-query k and m."""
+    torch, oracle, A = env
+    from paper_2605_02224_amd import workloads as W
+    w = W.heightfield_prefix()
+    P = w.cloud.by_rank
+    cl = A.Cloud.build(P).upload()
+    q = torch.from_numpy(w.queries).cuda()
+    kq = torch.from_numpy(w.k_per_query).cuda()
+    mq = torch.from_numpy(w.m_per_query).cuda()
+    idx, dist, row_off = cl.knn_var(q, kq, mq)
+    torch.cuda.synchronize()
+    idx, dist, row_off = idx.cpu().numpy(), dist.cpu().numpy(), row_off.cpu().numpy()
+    sel = np.random.default_rng(1).choice(w.queries.shape[0], 2000, replace=False)
+    ri, _, rD, roff = oracle.knn_bruteforce(P, w.queries[sel],
+                                            k_per_query=w.k_per_query[sel] + 1,
+                                            m_per_query=w.m_per_query[sel])
+    ex = 0
+    for t, i in enumerate(sel):
+        k = int(w.k_per_query[i])
+        a, b = row_off[i], row_off[i + 1]
+        assert b - a == k
+        o = roff[t]
+        ex += compare_rows(idx[a:b][None], dist[a:b][None], ri[o:o + k][None], rD[o:o + k][None],
+                           rD[o + k:o + k + 1])
+    assert ex <= 3
