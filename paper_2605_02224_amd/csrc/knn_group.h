@@ -135,6 +135,16 @@ struct RowTopK {
     thr_r = kEmpty;
   }
 
+  // Recompute the threshold (key of slot k-1) after N was written directly.
+  __device__ __forceinline__ void refresh_threshold(int k) {
+    if (EXACTK) {
+      thr_d = dpp_f64<kDppRowBcast15>(d[S - 1], d[S - 1]);
+      thr_r = dpp_i32<kDppRowBcast15>(r[S - 1], r[S - 1]);
+    } else {
+      slot(k - 1, thr_d, thr_r);
+    }
+  }
+
   // slot j (row-uniform) broadcast to the row
   __device__ __forceinline__ void slot(int j, double &od, int32_t &orr) const {
     const int s = j >> 4, src = j & 15;

@@ -41,16 +41,29 @@ __device__ __forceinline__ void offer_all(RowTopK<S, EXACTK> &N, bool cand, doub
 
 constexpr int32_t kRowDescent = 0, kRowExpand = 1, kRowIdle = 2;
 
+// Per-row rings of transition sites (k <= 16), 16 entries for each of the 16 rows of a
+// 256-thread workgroup (every launch of these kernels uses 256 threads).  In LDS rather
+// than registers: 32 more VGPRs per lane would cost occupancy.
+__shared__ double g_ring_d[16 * 16];
+__shared__ int32_t g_ring_r[16 * 16];
+__device__ __forceinline__ double *ring_d(const QueryArgs &) { return g_ring_d + 16 * (threadIdx.x >> 4); }
+__device__ __forceinline__ int32_t *ring_r(const QueryArgs &) { return g_ring_r + 16 * (threadIdx.x >> 4); }
+
 // The state of one row's current query.  Row-uniform values, held by every lane of the row.
 template <int S, bool EXACTK>
 struct RowWalker {
   RowTopK<S, EXACTK> N;
-  double qx = 0, qy = 0, qz = 0, dcur = 0;
-  int64_t qi = 0;
+  float qx = 0, qy = 0, qz = 0;     // the query, widened where it is used (registers are tight)
+  double dcur = 0;
+  int32_t qi = 0;                  // caller index of the query (nq < 2^31)
   int32_t k = 0, m = 0, cur = 0, it = 0;
   int32_t phase = kRowIdle;
   uint64_t dsc = 0;
   uint32_t base = 0;
+  // k <= 16: the transition sites of the descent (Alg. 1) go to a ring of 16 in LDS (entry
+  // t % 16 for the t-th); each is strictly closer than the one before, so the last 16 are
+  // the only ones that can rank among the k nearest and the ring holds them sorted.
+  int32_t ntrans = 0;
 
   // Start the query at sorted position s of request a.  A query whose prefix holds no live
   // site is answered at once (empty row) and leaves the row idle.
@@ -63,7 +76,7 @@ struct RowWalker {
       qz = v.z;
       qi = __float_as_int(v.w);
     } else {
-      qi = s;
+      qi = (int32_t)s;
       qx = a.q[3 * s];
       qy = a.q[3 * s + 1];
       qz = a.q[3 * s + 2];
@@ -79,15 +92,24 @@ struct RowWalker {
       return;
     }
     cur = a.head;
-    const double dx = qx - (double)a.hx, dy = qy - (double)a.hy, dz = qz - (double)a.hz;
+    const double dx = (double)qx - (double)a.hx, dy = (double)qy - (double)a.hy,
+                 dz = (double)qz - (double)a.hz;
     dcur = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-    if (l == 0) {
-      N.d[0] = dcur;
-      N.r[0] = cur;
-    }
-    if (k == 1) {
-      N.thr_d = dcur;
-      N.thr_r = cur;
+    if constexpr (S == 1) {
+      if (l == 0) {
+        ring_d(a)[0] = dcur;
+        ring_r(a)[0] = cur;
+      }
+      ntrans = 1;
+    } else {
+      if (l == 0) {
+        N.d[0] = dcur;
+        N.r[0] = cur;
+      }
+      if (k == 1) {
+        N.thr_d = dcur;
+        N.thr_r = cur;
+      }
     }
     dsc = a.lst[cur];
     base = 0;
@@ -123,20 +145,50 @@ struct RowWalker {
     const bool valid = active && e < len && r < m;
     double dd = INFINITY;
     if (valid) {
-      const double dx = qx - (double)c.x, dy = qy - (double)c.y, dz = qz - (double)c.z;
+      const double dx = (double)qx - (double)c.x, dy = (double)qy - (double)c.y,
+                   dz = (double)qz - (double)c.z;
       dd = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
     }
     const uint32_t vmask = row_bits(__ballot(valid), g);
     const uint32_t jm = row_bits(__ballot(valid && phase == kRowDescent && dd < dcur), g);
     const int j = jm ? __ffs(jm) - 1 : 0;
-    // a jumping row offers its transition site only (Alg. 1), the other rows every entry
-    const bool cand = (jm ? l == j : valid) && key_less(dd, r, N.thr_d, N.thr_r);
+    // k <= 16: descent rows offer nothing (their transition sites go to the ring and the
+    // final list is scanned again as the first expansion).  Otherwise a jumping row offers
+    // its transition site only (Alg. 1) and the other rows every entry.
+    bool cand;
+    if constexpr (S == 1)
+      cand = valid && phase == kRowExpand && key_less(dd, r, N.thr_d, N.thr_r);
+    else
+      cand = (jm ? l == j : valid) && key_less(dd, r, N.thr_d, N.thr_r);
     offer_all(N, cand, dd, r, l, g, k, merge_min);
     if (jm) {
       dcur = __shfl(dd, j, 16);
       cur = __shfl(r, j, 16);
+      if constexpr (S == 1) {
+        if (l == (ntrans & 15)) {
+          ring_d(a)[l] = dcur;
+          ring_r(a)[l] = cur;
+        }
+        ++ntrans;
+      }
       dsc = lst[cur];
       base = 0;
+    } else if (S == 1 && active && phase == kRowDescent &&
+               !(vmask == 0xffffu && base + 16 < len)) {
+      // the descent ends at p_cur: N starts as the last transition sites, nearest first,
+      // and the final list is scanned again as the expansion of N[0]
+      const int have = ntrans < 16 ? ntrans : 16;
+      const int src = (ntrans - 1 - l) & 15;
+      N.d[0] = l < have ? ring_d(a)[src] : INFINITY;
+      N.r[0] = l < have ? ring_r(a)[src] : kEmpty;
+      N.refresh_threshold(k);
+      if (k == 1) {
+        finish(a, l);
+      } else {
+        phase = kRowExpand;
+        it = 0;
+        base = 0;
+      }
     } else if (active) {
       if (vmask == 0xffffu && base + 16 < len) {
         base += 16;   // the next chunk of a long list
