@@ -270,6 +270,27 @@ mknn_status mknn_timing_read(double *total_ms, int64_t *launches);
  */
 mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void *stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Insertion (the construction of Sec. 3, continued).
+ *
+ * mknn_insert: appends `count` points (host float32 [count][3]) to the birth order as ranks
+ * n, n+1, ...; their caller ids are their ranks.  Afterwards the successor lists equal those
+ * of the live points plus the new ones inserted in rank order: each new rank is appended to
+ * the lists of its Delaunay neighbours among the live points (and earlier new points), and
+ * its own list starts empty.  The triangulation of the live points is kept in the cloud for
+ * this (about 40 B per point); a deletion drops it and the next insertion builds it again.
+ * If the cloud is uploaded, the changed lists and the new descriptors are applied on
+ * `stream` as for deletions (copy on write; a re-pack when the slack runs out); the call
+ * synchronises `stream` before returning.
+ *   xyz    host float32 [count][3]; copied.
+ * Errors: ENONFINITE, EDUPLICATE (a point coincides with a live point or another new
+ * point; nothing is changed in either case), EUNSUPPORTED (fewer than four live points or
+ * more than 2^30 points: nothing is changed; or a failed insertion: the points before it
+ * stay inserted on the host, and the device copy must be uploaded again before the next
+ * query), EHIP, ENOMEM.  Not thread-safe per cloud, like mknn_delete.
+ */
+mknn_status mknn_insert(mknn_cloud *c, const float *xyz, int64_t count, void *stream);
+
 /* Number of live points, and the oldest live rank (where every descent starts). */
 int64_t mknn_live_count(const mknn_cloud *c);
 int32_t mknn_head(const mknn_cloud *c);

@@ -60,6 +60,7 @@ SIGNATURES.update({
     "mknn_batch_plan_destroy": (None, [_P]),
     "mknn_batch_knn": (ctypes.c_int, [ctypes.POINTER(Request), _I32, _P]),
     "mknn_delete": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "mknn_insert": (ctypes.c_int, [_P, _P, _I64, _P]),
     "mknn_server_create": (ctypes.c_int, [_I64, _I32, _I32, _I32, _PP]),
     "mknn_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(Request), _P, _P,
                                           ctypes.POINTER(ctypes.c_uint64)]),

@@ -92,6 +92,16 @@ class Cloud:
             st = _stream(stream)
         check(_lib.lib().mknn_delete(self._h, _ptr(r), r.shape[0], st))
 
+    def insert(self, points, stream=None) -> range:
+        """Append points (float32 [count, 3]) as the newest ranks; returns their ranks."""
+        pts = np.ascontiguousarray(np.asarray(points, dtype=np.float32).reshape(-1, 3))
+        n0 = self.n
+        st = None
+        if self.device_bytes:
+            st = _stream(stream)
+        check(_lib.lib().mknn_insert(self._h, _ptr(pts), pts.shape[0], st))
+        return range(n0, self.n)
+
     @property
     def live_count(self) -> int:
         return int(_lib.lib().mknn_live_count(self._h))

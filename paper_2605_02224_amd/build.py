@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libmknn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["mknn_host.cpp", "delaunay.cpp", "deletion.cpp"]
+HOST_SOURCES = ["mknn_host.cpp", "delaunay.cpp", "deletion.cpp", "insertion.cpp"]
 HIP_SOURCES = ["mknn_device.hip", "mknn_batch.hip", "mknn_server.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I" + INCLUDE, "-I" + CSRC]

@@ -2,6 +2,7 @@
 #pragma once
 #include <atomic>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,18 @@ struct DynLists {
   void insert_sorted(int64_t r, int32_t v);
   bool erase(int64_t r, int32_t v);
   void clear(int64_t r) { len[r] = 0; }
+  void grow(int64_t n) {   // new, empty lists up to n
+    start.resize(n, 0);
+    len.resize(n, 0);
+    cap.resize(n, 0);
+  }
+};
+
+// The triangulation of the live sites kept for appending points (insertion), built at the
+// first insertion; deletions remove their sites from it.
+struct InsertState {
+  std::vector<double> P;                       // all sites by rank, float64
+  std::unique_ptr<DelaunayBuilder> dt;         // live sites inserted in rank order
 };
 // List segments rewritten by a deletion batch, ready to be appended to the device arena.
 // The whole device image of the lists: records {x, y, z, rank bits} of every list, lists in
@@ -63,6 +76,7 @@ struct mknn_cloud {
   int32_t head = 0;                // smallest live rank
   int64_t nlive = 0;
   float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};   // bounding box of all points
+  std::unique_ptr<mknn::InsertState> ins;      // see InsertState
   // Bumped by every mutation of the host lists.  A deletion on an uploaded cloud bumps it
   // only when its device delta is applied, so the device copy stays usable (on the old
   // lists) while the host part of the deletion runs on another thread.
@@ -73,6 +87,7 @@ struct mknn_cloud {
   void *d_ent = nullptr;           // 16-byte records {x, y, z, rank}, padded
   uint64_t *d_lst = nullptr;       // per rank: start | (length << 32)
   int64_t ent_used = 0, ent_cap = 0;   // records in use / allocated (slack takes deltas)
+  int64_t lst_cap = 0;             // descriptors allocated (slack for appended points)
   int64_t dev_bytes = 0;
   std::atomic<uint64_t> dev_version{~0ull};
   int32_t dev_head = 0;            // the head of the lists on the device
@@ -85,5 +100,10 @@ void clear_error();
 // every rank whose successor list changed (for the device update).
 mknn_status delete_ranks_host(mknn_cloud *c, const int32_t *ranks, int64_t count,
                               std::vector<int32_t> *changed);
+// Appends xyz[0..count) (float32 [count][3]) as ranks n .. n+count-1 (Sec. 3 insertion):
+// every live Delaunay neighbour of a new site gets its rank appended.  On success *changed
+// receives every rank whose list changed or is new.
+mknn_status insert_points_host(mknn_cloud *c, const float *xyz, int64_t count,
+                               std::vector<int32_t> *changed);
 void refresh_csr(mknn_cloud *c);
 }  // namespace mknn

@@ -26,6 +26,7 @@ DelaunayBuilder::DelaunayBuilder(const double *pts, int64_t n) : P_(pts), n_(n) 
   llen_.assign(n, 0);
   lcap_.assign(n, 0);
   vmark_.assign(n, 0);
+  gone_.assign(n, 0);
   tv_.reserve((size_t)std::max<int64_t>(64, 7 * n) * 4);
   tn_.reserve((size_t)std::max<int64_t>(64, 7 * n) * 4);
   stamp_.reserve((size_t)std::max<int64_t>(64, 7 * n));
@@ -34,6 +35,13 @@ DelaunayBuilder::DelaunayBuilder(const double *pts, int64_t n) : P_(pts), n_(n) 
 
 int64_t DelaunayBuilder::num_tets() const {
   return (int64_t)stamp_.size() - (int64_t)free_.size();
+}
+
+bool DelaunayBuilder::tet(int64_t t, int32_t v[4]) const {
+  if (t < 0 || t >= (int64_t)stamp_.size()) return false;
+  if (std::find(free_.begin(), free_.end(), (int32_t)t) != free_.end()) return false;
+  for (int k = 0; k < 4; ++k) v[k] = tv_[4 * t + k];
+  return true;
 }
 
 int32_t DelaunayBuilder::alloc_tet() {
@@ -96,7 +104,7 @@ bool DelaunayBuilder::conflict(int32_t t, const double *p, bool strict) const {
 int32_t DelaunayBuilder::nearest_inserted(const double *p, double *dbest) const {
   // the lists hold, in insertion order, the later neighbours of each vertex, so the walk
   // starts from the first inserted vertex
-  int32_t cur = order_[0];
+  int32_t cur = order_[walk_pos_];
   double dcur = sqd(p, pt(cur));
   for (;;) {
     const int32_t *l = &pool_[lstart_[cur]];
@@ -164,13 +172,37 @@ bool DelaunayBuilder::start_with(const int32_t first4[4]) {
   }
   for (int64_t v = 0; v < n_; ++v)
     if (!done_[v]) order_.push_back((int32_t)v);
+  ascending_ = std::is_sorted(order_.begin(), order_.end());
   return orient3d(pt(first4[0]), pt(first4[1]), pt(first4[2]), pt(first4[3])) != 0;
 }
 
-bool DelaunayBuilder::init_first_tet() {
-  if (n_ < 4) return false;
+bool DelaunayBuilder::set_order(std::vector<int32_t> order) {
+  if (ninserted_ != 0) return false;
+  for (int32_t v : order)
+    if (v < 0 || v >= n_) return false;
+  order_ = std::move(order);
+  ascending_ = std::is_sorted(order_.begin(), order_.end());
+  return true;
+}
+
+void DelaunayBuilder::grow(const double *pts, int64_t n) {
   if (order_.empty())
     for (int64_t v = 0; v < n_; ++v) order_.push_back((int32_t)v);
+  P_ = pts;
+  for (int64_t v = n_; v < n; ++v) order_.push_back((int32_t)v);
+  vtet_.resize(n, -1);
+  lstart_.resize(n, 0);
+  llen_.resize(n, 0);
+  lcap_.resize(n, 0);
+  vmark_.resize(n, 0);
+  gone_.resize(n, 0);
+  n_ = n;
+}
+
+bool DelaunayBuilder::init_first_tet() {
+  if (order_.empty())
+    for (int64_t v = 0; v < n_; ++v) order_.push_back((int32_t)v);
+  if (order_.size() < 4) return false;
   int32_t v[4] = {order_[0], order_[1], order_[2], order_[3]};
   int o = orient3d(pt(v[0]), pt(v[1]), pt(v[2]), pt(v[3]));
   if (o == 0) return false;
@@ -214,6 +246,7 @@ bool DelaunayBuilder::init_first_tet() {
   nbrs_.assign(order_.begin(), order_.begin() + 3);
   std::sort(nbrs_.begin(), nbrs_.end());
   ninserted_ = 4;
+  live_ = 4;
   return true;
 }
 
@@ -349,20 +382,226 @@ BuildStatus DelaunayBuilder::insert_next() {
   std::sort(nbrs_.begin(), nbrs_.end());
   for (int32_t i : nbrs_) append(i, j);
   ++ninserted_;
+  ++live_;
+  return kBuildOk;
+}
+
+void DelaunayBuilder::set_list(int32_t v, const int32_t *ent, int32_t len) {
+  llen_[v] = 0;
+  for (int32_t e = 0; e < len; ++e) append(v, ent[e]);
+}
+
+// Would inserting site p (id v) destroy tetrahedron t of this triangulation, whose vertex
+// ids map to ids[] of the caller (kInf stays)?  The perturbation of the construction lowers
+// the lifted coordinate of every site by an amount that dominates all those of older sites.
+// For a sphere through p and t's four sites, the newest of the five with a non-zero effect
+// decides: p itself puts p inside; a vertex w puts p inside iff p's barycentric coordinate
+// for w is negative (lowering w lowers the lifted plane at p exactly when it is).  Ghosts
+// use the construction's own test when p is newer than the facet's sites, else only
+// "strictly beyond the facet, or strictly inside its circle".
+bool DelaunayBuilder::destroyed_by(int32_t t, const double *p, int32_t v, const int32_t *ids) const {
+  const int32_t *tv = &tv_[4 * (int64_t)t];
+  int32_t vmax = -1;
+  bool ghost = false;
+  for (int i = 0; i < 4; ++i) {
+    if (tv[i] == kInf) ghost = true;
+    else vmax = std::max(vmax, ids[tv[i]]);
+  }
+  if (ghost) return conflict(t, p, v < vmax);
+  const double *q[4] = {pt(tv[0]), pt(tv[1]), pt(tv[2]), pt(tv[3])};
+  const int s = insphere(q[0], q[1], q[2], q[3], p);
+  if (s != 0) return s > 0;
+  // on the sphere: walk the five sites from the newest down
+  int idx[4] = {0, 1, 2, 3};
+  std::sort(idx, idx + 4, [&](int a, int b) { return ids[tv[a]] > ids[tv[b]]; });
+  for (int w : idx) {
+    if (ids[tv[w]] < v) return true;   // p is the newest left: inside
+    const double *r[4] = {q[0], q[1], q[2], q[3]};
+    r[w] = p;
+    const int o = orient3d(r[0], r[1], r[2], r[3]);
+    if (o != 0) return o < 0;
+  }
+  return true;
+}
+
+BuildStatus DelaunayBuilder::remove(int32_t v) {
+  if (v < 0 || v >= n_ || gone_[v] || vtet_[v] < 0 || !ascending_) return kBuildInternal;
+  if (live_ < 6) return kBuildDegenerateStart;   // keep at least five sites
+  // star of v: the tetrahedra through v, connected across the faces through v
+  const uint32_t ep = ++epoch_;
+  star_.clear();
+  star_.push_back(vtet_[v]);
+  stamp_[vtet_[v]] = ep;
+  for (size_t s = 0; s < star_.size(); ++s) {
+    const int32_t t = star_[s];
+    for (int h = 0; h < 4; ++h) {
+      if (tv_[4 * (int64_t)t + h] == v) continue;
+      const int32_t u = tn_[4 * (int64_t)t + h];
+      if (stamp_[u] != ep) {
+        stamp_[u] = ep;
+        star_.push_back(u);
+      }
+    }
+  }
+  // v's link: the facet opposite v in every star tetrahedron, with the tetrahedron beyond
+  struct LinkFace { int32_t key[3]; int32_t outer, outer_face; bool used; };
+  std::vector<LinkFace> link;
+  std::vector<int32_t> lv;   // finite link vertices
+  for (int32_t t : star_) {
+    int hv = -1;
+    for (int k = 0; k < 4; ++k)
+      if (tv_[4 * (int64_t)t + k] == v) hv = k;
+    if (hv < 0) return kBuildInternal;
+    LinkFace f;
+    int c = 0;
+    for (int k = 0; k < 4; ++k)
+      if (k != hv) {
+        f.key[c++] = tv_[4 * (int64_t)t + k];
+        if (tv_[4 * (int64_t)t + k] != kInf) lv.push_back(tv_[4 * (int64_t)t + k]);
+      }
+    std::sort(f.key, f.key + 3);
+    f.outer = tn_[4 * (int64_t)t + hv];
+    f.outer_face = -1;
+    for (int k = 0; k < 4; ++k)
+      if (tn_[4 * (int64_t)f.outer + k] == t) f.outer_face = k;
+    if (f.outer_face < 0) return kBuildInternal;
+    f.used = false;
+    link.push_back(f);
+  }
+  std::sort(lv.begin(), lv.end(), [&](int32_t a, int32_t b) { return rank_of(a) < rank_of(b); });
+  lv.erase(std::unique(lv.begin(), lv.end()), lv.end());
+  if (lv.size() == 3 && link.size() == 4) {
+    // a hull corner with three finite neighbours: its star is one finite tetrahedron and
+    // three ghosts, and without v the facet of the three becomes a hull facet.  The ghost
+    // keeps the finite tetrahedron's vertex order with v replaced by infinity (v lay beyond
+    // that facet, which is the ghost's orientation rule).
+    int32_t t0 = -1;
+    for (int32_t t : star_) {
+      bool ghost = false;
+      for (int k = 0; k < 4; ++k) ghost |= tv_[4 * (int64_t)t + k] == kInf;
+      if (!ghost) t0 = t;
+    }
+    if (t0 < 0) return kBuildInternal;
+    int32_t w[4];
+    for (int k = 0; k < 4; ++k) w[k] = tv_[4 * (int64_t)t0 + k] == v ? kInf : tv_[4 * (int64_t)t0 + k];
+    int fm[4];
+    for (int k = 0; k < 4; ++k) {
+      int32_t key[3];
+      int c = 0;
+      for (int m = 0; m < 4; ++m)
+        if (m != k) key[c++] = w[m];
+      std::sort(key, key + 3);
+      fm[k] = -1;
+      for (size_t f = 0; f < link.size(); ++f)
+        if (link[f].key[0] == key[0] && link[f].key[1] == key[1] && link[f].key[2] == key[2])
+          fm[k] = (int)f;
+      if (fm[k] < 0) return kBuildInternal;
+    }
+    for (int32_t t : star_) free_.push_back(t);
+    const int32_t g = alloc_tet();
+    for (int k = 0; k < 4; ++k) {
+      tv_[4 * (int64_t)g + k] = w[k];
+      if (w[k] != kInf) vtet_[w[k]] = g;
+      const LinkFace &f = link[fm[k]];
+      tn_[4 * (int64_t)g + k] = f.outer;
+      tn_[4 * (int64_t)f.outer + f.outer_face] = g;
+    }
+    vtet_[v] = -1;
+    gone_[v] = 1;
+    llen_[v] = 0;
+    --live_;
+    while (walk_pos_ < ninserted_ && gone_[order_[walk_pos_]]) ++walk_pos_;
+    return kBuildOk;
+  }
+  if (lv.size() < 4) return kBuildDegenerateStart;
+  // triangulation of the link vertices, inserted oldest first (local id = position in lv)
+  std::vector<double> lp(3 * lv.size());
+  std::vector<int32_t> lrank(lv.size());
+  for (size_t u = 0; u < lv.size(); ++u) {
+    std::memcpy(&lp[3 * u], pt(lv[u]), 3 * sizeof(double));
+    lrank[u] = rank_of(lv[u]);
+  }
+  DelaunayBuilder dt(lp.data(), (int64_t)lv.size());
+  int64_t bad = -1;
+  const BuildStatus bs = dt.build(&bad);
+  if (bs != kBuildOk) return bs;
+  // the cavity v would carve out of it
+  std::vector<char> dead(dt.stamp_.size(), 0);
+  for (int32_t t : dt.free_) dead[t] = 1;
+  std::vector<int32_t> cav, newid(dt.stamp_.size(), -1);
+  for (size_t t = 0; t < dt.stamp_.size(); ++t)
+    if (!dead[t] && dt.destroyed_by((int32_t)t, pt(v), rank_of(v), lrank.data())) {
+      newid[t] = (int32_t)cav.size();
+      cav.push_back((int32_t)t);
+    }
+  // its boundary must be v's link, facet for facet
+  auto gid = [&](int32_t u) { return u == kInf ? kInf : lv[u]; };
+  std::vector<std::pair<int32_t, int>> match;   // per cavity boundary face: link index
+  for (int32_t t : cav)
+    for (int k = 0; k < 4; ++k) {
+      const int32_t u = dt.tn_[4 * (int64_t)t + k];
+      if (newid[u] >= 0) continue;
+      int32_t key[3];
+      int c = 0;
+      for (int m = 0; m < 4; ++m)
+        if (m != k) key[c++] = gid(dt.tv_[4 * (int64_t)t + m]);
+      std::sort(key, key + 3);
+      int found = -1;
+      for (size_t f = 0; f < link.size(); ++f)
+        if (!link[f].used && link[f].key[0] == key[0] && link[f].key[1] == key[1] &&
+            link[f].key[2] == key[2]) {
+          found = (int)f;
+          break;
+        }
+      if (found < 0) return kBuildInternal;
+      link[found].used = true;
+      match.push_back({found, 0});
+    }
+  if (match.size() != link.size()) return kBuildInternal;
+  // commit: the star goes, the cavity's tetrahedra come in
+  for (int32_t t : star_) free_.push_back(t);
+  std::vector<int32_t> gt(cav.size());
+  for (size_t a = 0; a < cav.size(); ++a) gt[a] = alloc_tet();
+  size_t mi = 0;
+  for (size_t a = 0; a < cav.size(); ++a) {
+    const int32_t t = cav[a], g = gt[a];
+    for (int k = 0; k < 4; ++k) {
+      const int32_t w = gid(dt.tv_[4 * (int64_t)t + k]);
+      tv_[4 * (int64_t)g + k] = w;
+      if (w != kInf) vtet_[w] = g;
+    }
+    for (int k = 0; k < 4; ++k) {
+      const int32_t u = dt.tn_[4 * (int64_t)t + k];
+      if (newid[u] >= 0) {
+        tn_[4 * (int64_t)g + k] = gt[newid[u]];
+      } else {
+        const LinkFace &f = link[match[mi++].first];
+        tn_[4 * (int64_t)g + k] = f.outer;
+        tn_[4 * (int64_t)f.outer + f.outer_face] = g;
+      }
+    }
+  }
+  vtet_[v] = -1;
+  gone_[v] = 1;
+  llen_[v] = 0;
+  --live_;
+  while (walk_pos_ < ninserted_ && gone_[order_[walk_pos_]]) ++walk_pos_;
   return kBuildOk;
 }
 
 BuildStatus DelaunayBuilder::build(int64_t *bad_rank) {
-  while (ninserted_ < n_) {
+  if (order_.empty())
+    for (int64_t v = 0; v < n_; ++v) order_.push_back((int32_t)v);
+  while (ninserted_ < (int64_t)order_.size()) {
     int64_t j = ninserted_;
-    if (n_ < 4) {
+    if (order_.size() < 4) {
       // fewer than four sites: pairwise adjacency unless collinear ordering hides a pair
       // (handled by the caller rejecting n < 4 clouds that are degenerate)
       return kBuildDegenerateStart;
     }
     BuildStatus s = insert_next();
     if (s != kBuildOk) {
-      if (bad_rank) *bad_rank = (s == kBuildDegenerateStart) ? 3 : j;
+      if (bad_rank) *bad_rank = order_[(s == kBuildDegenerateStart) ? 3 : j];
       return s;
     }
   }
@@ -426,6 +665,7 @@ bool DelaunayBuilder::validate(std::string *why) const {
   }
   for (int64_t pos = 0; pos < ninserted_; ++pos) {
     const int32_t v = order_[pos];
+    if (gone_[v]) continue;
     int32_t t = vtet_[v];
     bool ok = t >= 0 && !dead[t];
     if (ok) {
@@ -451,7 +691,7 @@ bool DelaunayBuilder::validate_empty_spheres(std::string *why) const {
     if (ghost) continue;
     for (int64_t pos = 0; pos < ninserted_; ++pos) {
       const int32_t q = order_[pos];
-      if (q == v[0] || q == v[1] || q == v[2] || q == v[3]) continue;
+      if (gone_[q] || q == v[0] || q == v[1] || q == v[2] || q == v[3]) continue;
       int s = insphere(pt(v[0]), pt(v[1]), pt(v[2]), pt(v[3]), pt((int32_t)q));
       // a site exactly on the sphere is allowed only if it is older than some vertex
       // (the perturbation puts the newest of the five inside)

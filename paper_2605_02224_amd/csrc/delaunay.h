@@ -54,6 +54,10 @@ class DelaunayBuilder {
   bool validate_empty_spheres(std::string *why) const;
 
   int64_t num_tets() const;
+  // Tetrahedron slots (some free); tet(t, v) copies slot t's vertices and returns false
+  // for a free slot.
+  int64_t num_tet_slots() const { return (int64_t)stamp_.size(); }
+  bool tet(int64_t t, int32_t v[4]) const;
   int64_t exact_fallbacks() const;
 
   // Finite Delaunay neighbours of the vertex inserted last (ascending ids).
@@ -68,6 +72,28 @@ class DelaunayBuilder {
   // first four ids; the remaining ids are then inserted in increasing order (skipping
   // these four).  Returns false if they are coplanar.
   bool start_with(const int32_t first4[4]);
+
+  // Insert only the given ids, in the given order (before the first insertion); ids not
+  // listed are never inserted.
+  bool set_order(std::vector<int32_t> order);
+  // The point array now holds n points (the first ones unchanged, the array possibly
+  // moved); the new ids join the end of the insertion order.
+  void grow(const double *pts, int64_t n);
+  // Number of ids in the insertion order (inserted or still to insert).
+  int64_t order_size() const { return (int64_t)order_.size(); }
+  // 1-NN of p among the inserted sites and its squared distance.
+  int32_t nearest(const double *p, double *d) const { return nearest_inserted(p, d); }
+
+  // Removes the inserted vertex v (the insertion order must be ascending in id).  Its star is replaced by the tetrahedra of the
+  // triangulation of its link vertices (built here, in id order) that v would destroy if
+  // inserted there, under the same perturbation as the construction; the result is the
+  // triangulation the construction gives without v.  On failure (fewer than five sites
+  // left, a local triangulation that cannot start, or a cavity whose boundary does not
+  // match v's link) nothing is changed.  v's own list is emptied; the lists of other
+  // vertices are the caller's to fix (set_list), since point location walks them.
+  BuildStatus remove(int32_t v);
+  // Replaces v's list (the successor list point location walks).
+  void set_list(int32_t v, const int32_t *ent, int32_t len);
 
  private:
   const double *P_;
@@ -100,7 +126,14 @@ class DelaunayBuilder {
   const double *pt(int32_t v) const { return P_ + 3 * (int64_t)v; }
   int32_t alloc_tet();
   bool conflict(int32_t t, const double *p, bool strict = false) const;
+  bool destroyed_by(int32_t t, const double *p, int32_t v, const int32_t *ids) const;
   std::vector<int32_t> order_;      // insertion order of ids (identity unless start_with)
+  std::vector<char> gone_;          // removed vertices
+  int64_t live_ = 0;                // inserted and not removed
+  int64_t walk_pos_ = 0;            // order_ position of the oldest vertex not removed
+  bool ascending_ = true;           // order_ ascending in id (identity, or set_order's)
+  // the perturbation ranks vertices by insertion; with an ascending order that is the id
+  int32_t rank_of(int32_t v) const { return v; }
   std::vector<char> done_;
   int32_t nearest_inserted(const double *p, double *dbest) const;
   int32_t locate(int32_t near, const double *p);

@@ -196,6 +196,7 @@ mknn_status delete_ranks_host(mknn_cloud *c, const int32_t *ranks, int64_t count
       adds.clear();
       mknn_status st = redistribute(c, i, &adds);
       if (st != MKNN_OK) {
+        c->ins.reset();
         if (i != del.front()) {
           // earlier ranks of the batch are already applied: the host lists have moved on,
           // and a device copy stays stale until the next upload
@@ -228,7 +229,21 @@ mknn_status delete_ranks_host(mknn_cloud *c, const int32_t *ranks, int64_t count
       }
     }
     c->csr_dirty = true;
+    if (c->ins) {
+      // the triangulation kept for insertion loses the deleted sites too, and the lists its
+      // point location walks follow the cloud's; a removal it cannot do drops it (the next
+      // insertion triangulates the live sites again)
+      DelaunayBuilder &dt = *c->ins->dt;
+      for (int32_t i : del)
+        if (dt.remove(i) != kBuildOk) {
+          c->ins.reset();
+          break;
+        }
+      if (c->ins)
+        for (int32_t r : *changed) dt.set_list(r, c->dsucc.begin(r), c->dsucc.size(r));
+    }
   } catch (const std::bad_alloc &) {
+    c->ins.reset();
     c->csr_dirty = true;
     ++c->version;   // possibly half-applied: treat every device copy as stale
     return set_error(MKNN_ENOMEM, "mknn_delete: out of host memory");

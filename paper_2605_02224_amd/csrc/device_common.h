@@ -96,13 +96,14 @@ inline void fill_cloud_args(const mknn_cloud *c, QueryArgs *a) {
   a->n = c->n;
 }
 
-// Deletion split in two: delete_prepare edits the host lists and gathers the rewritten
-// list segments (or, when the arena's slack would run out, a complete new image of the
-// lists); delete_apply enqueues their copy and the descriptor switch (or the switch to a new
-// arena) on a stream, asynchronously.  The delta must stay alive until the stream has
-// executed the copies.
+// A list change in two steps: delete_prepare / insert_prepare edit the host lists and
+// gather the rewritten list segments (or, when the arena's slack or the descriptor array
+// would run out, a complete new image of the lists); apply_delta enqueues their copy and
+// the descriptor switch (or the switch to a new arena) on a stream, asynchronously.  The
+// delta must stay alive until the stream has executed the copies.
 mknn_status delete_prepare(mknn_cloud *c, const int32_t *ranks, int64_t count, DeviceDelta *d);
-mknn_status delete_apply(mknn_cloud *c, DeviceDelta *d, hipStream_t s);
+mknn_status insert_prepare(mknn_cloud *c, const float *xyz, int64_t count, DeviceDelta *d);
+mknn_status apply_delta(mknn_cloud *c, DeviceDelta *d, hipStream_t s);
 // After a re-pack, the replaced arena is freed by the caller once no work reads it.
 void release_old_arena(DeviceDelta *d);
 mknn_status pack_lists(mknn_cloud *c, HostPack *p);

@@ -342,8 +342,10 @@ mknn_status pack_lists(mknn_cloud *c, HostPack *p) {
 mknn_status install_pack(mknn_cloud *c, const HostPack *p, hipStream_t s) {
   void *ent = nullptr;
   uint64_t *lst = nullptr;
+  // descriptors for appended points: an eighth more than the points present
+  const int64_t lst_cap = (int64_t)p->lst.size() + std::max<int64_t>((int64_t)p->lst.size() / 8, 1024);
   hipError_t e = hipMalloc(&ent, sizeof(float4) * (size_t)p->cap);
-  if (e == hipSuccess) e = hipMalloc((void **)&lst, sizeof(uint64_t) * p->lst.size());
+  if (e == hipSuccess) e = hipMalloc((void **)&lst, sizeof(uint64_t) * (size_t)lst_cap);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ent, p->ent.data(), sizeof(float) * p->ent.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
@@ -356,7 +358,8 @@ mknn_status install_pack(mknn_cloud *c, const HostPack *p, hipStream_t s) {
   }
   c->d_ent = ent;
   c->d_lst = lst;
-  c->dev_bytes = (int64_t)(sizeof(float4) * (size_t)p->cap + sizeof(uint64_t) * p->lst.size());
+  c->dev_bytes = (int64_t)(sizeof(float4) * (size_t)p->cap + sizeof(uint64_t) * (size_t)lst_cap);
+  c->lst_cap = lst_cap;
   c->ent_used = p->nnz;
   c->ent_cap = p->cap - kEntPad;
   c->dev_head = c->head;
@@ -365,22 +368,17 @@ mknn_status install_pack(mknn_cloud *c, const HostPack *p, hipStream_t s) {
 }
 
 // ---- deletion: host preparation and device application of the list deltas
-mknn_status delete_prepare(mknn_cloud *c, const int32_t *ranks, int64_t count, DeviceDelta *d) {
-  d->on_device = c->d_ent && c->dev_version == c->version;
-  std::vector<int32_t> changed;
-  mknn_status st = delete_ranks_host(c, ranks, count, &changed);
-  if (st != MKNN_OK) return st;   // a half-applied batch has bumped c->version
-  if (!d->on_device) {
-    ++c->version;
-    return MKNN_OK;
-  }
-  // on the device the version moves when the delta is applied
+// The device side of a list change on the host (deletion or insertion): `changed` lists
+// are copied on write into fresh arena segments, or -- when the arena's slack or the
+// descriptor array would run out -- a complete new image is built here, off the caller's
+// launch path.
+static mknn_status fill_delta(mknn_cloud *c, const std::vector<int32_t> &changed, DeviceDelta *d,
+                              const char *who) {
   int64_t need = 0;
   for (int32_t r : changed) need += c->dsucc.size(r);
-  if (c->ent_used + need > c->ent_cap) {
-    // out of slack: build a complete new image here, off the caller's launch path
+  if (c->ent_used + need > c->ent_cap || c->n > c->lst_cap) {
     d->repack = true;
-    st = pack_lists(c, &d->pack);
+    mknn_status st = pack_lists(c, &d->pack);
     if (st != MKNN_OK) ++c->version;   // the host lists have moved on without the device
     return st;
   }
@@ -408,12 +406,37 @@ mknn_status delete_prepare(mknn_cloud *c, const int32_t *ranks, int64_t count, D
     }
   } catch (const std::bad_alloc &) {
     ++c->version;
-    return set_error(MKNN_ENOMEM, "mknn_delete: out of host memory");
+    return set_error(MKNN_ENOMEM, std::string(who) + ": out of host memory");
   }
   return MKNN_OK;
 }
 
-mknn_status delete_apply(mknn_cloud *c, DeviceDelta *d, hipStream_t s) {
+mknn_status delete_prepare(mknn_cloud *c, const int32_t *ranks, int64_t count, DeviceDelta *d) {
+  d->on_device = c->d_ent && c->dev_version == c->version;
+  std::vector<int32_t> changed;
+  mknn_status st = delete_ranks_host(c, ranks, count, &changed);
+  if (st != MKNN_OK) return st;   // a half-applied batch has bumped c->version
+  if (!d->on_device) {
+    ++c->version;
+    return MKNN_OK;
+  }
+  // on the device the version moves when the delta is applied
+  return fill_delta(c, changed, d, "mknn_delete");
+}
+
+mknn_status insert_prepare(mknn_cloud *c, const float *xyz, int64_t count, DeviceDelta *d) {
+  d->on_device = c->d_ent && c->dev_version == c->version;
+  std::vector<int32_t> changed;
+  mknn_status st = insert_points_host(c, xyz, count, &changed);
+  if (st != MKNN_OK) return st;   // a half-applied batch has bumped c->version
+  if (!d->on_device) {
+    ++c->version;
+    return MKNN_OK;
+  }
+  return fill_delta(c, changed, d, "mknn_insert");
+}
+
+mknn_status apply_delta(mknn_cloud *c, DeviceDelta *d, hipStream_t s) {
   if (!d->on_device) return MKNN_OK;
   ++c->version;   // the device copy is stale until the delta below is complete
   const int64_t need = (int64_t)(d->rec.size() / 4);
@@ -435,21 +458,21 @@ mknn_status delete_apply(mknn_cloud *c, DeviceDelta *d, hipStream_t s) {
   }
   void *d_tmp = nullptr;
   const size_t tmp_bytes = sizeof(int32_t) * d->ranks.size() + sizeof(uint64_t) * d->desc.size() + 16;
-  HIP_TRY(hipMallocAsync(&d_tmp, tmp_bytes, s), "mknn_delete: scratch");
+  HIP_TRY(hipMallocAsync(&d_tmp, tmp_bytes, s), "apply list delta: scratch");
   uint64_t *d_dd = (uint64_t *)d_tmp;
   int32_t *d_rr = (int32_t *)(d_dd + d->desc.size());
   if (need)
     HIP_TRY(hipMemcpyAsync((float4 *)c->d_ent + c->ent_used, d->rec.data(), sizeof(float) * d->rec.size(),
-                           hipMemcpyHostToDevice, s), "mknn_delete: copy records");
+                           hipMemcpyHostToDevice, s), "apply list delta: copy records");
   HIP_TRY(hipMemcpyAsync(d_dd, d->desc.data(), sizeof(uint64_t) * d->desc.size(), hipMemcpyHostToDevice, s),
-          "mknn_delete: copy descriptors");
+          "apply list delta: copy descriptors");
   HIP_TRY(hipMemcpyAsync(d_rr, d->ranks.data(), sizeof(int32_t) * d->ranks.size(), hipMemcpyHostToDevice, s),
-          "mknn_delete: copy ranks");
+          "apply list delta: copy ranks");
   const uint32_t blocks = (uint32_t)((d->ranks.size() + 255) / 256);
   hipLaunchKernelGGL(apply_descriptors_kernel, dim3(blocks), dim3(256), 0, s, c->d_lst, d_rr, d_dd,
                      (int64_t)d->ranks.size());
-  HIP_TRY(hipGetLastError(), "mknn_delete: launch");
-  HIP_TRY(hipFreeAsync(d_tmp, s), "mknn_delete: free scratch");
+  HIP_TRY(hipGetLastError(), "apply list delta: launch");
+  HIP_TRY(hipFreeAsync(d_tmp, s), "apply list delta: free scratch");
   c->ent_used += need;
   c->dev_head = c->head;
   c->dev_version = c->version.load();
@@ -927,9 +950,26 @@ mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void
   if (st != MKNN_OK) return st;
   if (!d.on_device) return MKNN_OK;
   hipStream_t s = (hipStream_t)stream;
-  st = delete_apply(c, &d, s);
+  st = apply_delta(c, &d, s);
   if (st != MKNN_OK) return st;
   HIP_TRY(hipStreamSynchronize(s), "mknn_delete: synchronize");
+  release_old_arena(&d);
+  return MKNN_OK;
+}
+
+mknn_status mknn_insert(mknn_cloud *c, const float *xyz, int64_t count, void *stream) {
+  clear_error();
+  if (!c) return set_error(MKNN_EINVAL, "mknn_insert: cloud is NULL");
+  if (count < 0 || (count > 0 && !xyz)) return set_error(MKNN_EINVAL, "mknn_insert: bad points");
+  if (count == 0) return MKNN_OK;
+  DeviceDelta d;
+  mknn_status st = insert_prepare(c, xyz, count, &d);
+  if (st != MKNN_OK) return st;
+  if (!d.on_device) return MKNN_OK;
+  hipStream_t s = (hipStream_t)stream;
+  st = apply_delta(c, &d, s);
+  if (st != MKNN_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s), "mknn_insert: synchronize");
   release_old_arena(&d);
   return MKNN_OK;
 }

@@ -309,7 +309,7 @@ static void scheduler_loop(mknn_server *s) {
         const double t0 = now_s();
         op->t_launch = t0;
         s->repacks += op->delta.repack ? 1 : 0;
-        mknn_status st = delete_apply(c, &op->delta, s->del_stream);
+        mknn_status st = apply_delta(c, &op->delta, s->del_stream);
         s->t_apply += now_s() - t0;
         if (st != MKNN_OK) {
           op->status = st;

@@ -111,3 +111,29 @@ def test_compact_after_deletions_keeps_results(env):
     ri, _, rD = oracle.knn_bruteforce(P, Q[:1500], 21, live=live)
     compare_rows(after[0].cpu().numpy()[:1500], after[1].cpu().numpy()[:1500], ri[:, :20],
                  rD[:, :20], rD[:, 20])
+
+
+def test_queries_after_insertions_and_deletions(env):
+    """Points appended on the device (copy-on-write list segments and new descriptors, then
+    a re-pack once the descriptor slack runs out) answer k-NN over the grown cloud and over
+    prefixes that end before, at and after the appended ranks."""
+    torch, oracle, A, W = env
+    c = W.random_cloud(26000, seed=23, shape="torus")
+    P = c.by_rank
+    n0 = 20000
+    cl = A.Cloud.build(P[:n0]).upload()
+    live = np.ones(26000, np.uint8)
+    rng = np.random.default_rng(5)
+    lo, hi = W.bbox_expanded(P, 1.1)
+    Q = W.uniform_in_box(rng, 10000, lo, hi)
+    n = n0
+    for step, cnt in enumerate((1000, 1500, 1500, 2000)):   # the third batch outgrows the slack
+        if step == 2:
+            dead = rng.choice(n, 300, replace=False)
+            cl.delete(dead)
+            live[dead] = 0
+        assert list(cl.insert(P[n:n + cnt])) == list(range(n, n + cnt))
+        n += cnt
+        assert cl.n == n
+        for k, m in ((16, None), (8, n - cnt // 2), (33, n0 - 10)):
+            assert _check(env, cl, P[:n], live[:n], Q, k, m) <= 2, (step, k, m)
