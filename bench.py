@@ -403,9 +403,129 @@ def bench_serving(args) -> int:
     return 0
 
 
+def bench_dynamic(args) -> int:
+    """The dynamic benchmark (insertions, queries and deletions interleaved; Sec. 5.4
+    evaluation): per iteration insert 200 points, answer 2,000 queries with k=20; delete 100
+    random live points every 50 iterations and insert 2,000 more every 100.  Insertions and
+    deletions update the device lists (copy-on-write deltas) before the next query batch.
+    Queries are drawn on the host per iteration and copied in (part of the query time)."""
+    import torch
+    from paper_2605_02224_amd import workloads as W
+    from paper_2605_02224_amd.api import Cloud
+    out = {}
+    for scenario in ("surface", "volume"):
+        w = W.dynamic_stream(scenario, iterations=args.dyn_iterations)
+        P = w.points
+        cl = Cloud.build(P[:w.n0]).upload()
+        n = w.n0
+        live = np.zeros(P.shape[0], bool)
+        live[:n] = True
+        t = collections.defaultdict(float)
+        cnt = collections.defaultdict(int)
+        idx = torch.empty((w.queries_per_iter, w.k), dtype=torch.int32, device="cuda")
+        dist = torch.empty((w.queries_per_iter, w.k), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        for it in range(1, w.iterations + 1):
+            t0 = time.perf_counter()
+            cl.insert(P[n:n + w.insert_per_iter])
+            live[n:n + w.insert_per_iter] = True
+            n += w.insert_per_iter
+            t1 = time.perf_counter()
+            t["insert"] += t1 - t0
+            cnt["insert"] += w.insert_per_iter
+            q = W.uniform_in_box(w.rng, w.queries_per_iter, w.qlo, w.qhi)
+            qd = torch.from_numpy(q).cuda(non_blocking=False)
+            cl.knn(qd, w.k, out=(idx, dist))
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            t["query"] += t2 - t1
+            cnt["query"] += w.queries_per_iter
+            if it % w.delete_every == 0:
+                dead = w.rng.choice(np.flatnonzero(live), w.delete_count, replace=False)
+                cl.delete(dead)
+                live[dead] = False
+                t3 = time.perf_counter()
+                t["delete"] += t3 - t2
+                cnt["delete"] += w.delete_count
+                t2 = t3
+            if it % w.batch_every == 0:
+                cl.insert(P[n:n + w.batch_count])
+                live[n:n + w.batch_count] = True
+                n += w.batch_count
+                t["insert"] += time.perf_counter() - t2
+                cnt["insert"] += w.batch_count
+        total = time.perf_counter() - t_all
+        log(f"{scenario}: {w.iterations} iterations in {total:.2f} s; final n={n}, "
+            f"live={cl.live_count}")
+        out[scenario] = {
+            "total_s": round(total, 3),
+            "insert_us_per_point": round(1e6 * t["insert"] / max(cnt["insert"], 1), 2),
+            "query_ms_per_iteration": round(1e3 * t["query"] / w.iterations, 4),
+            "queries_per_s": round(cnt["query"] / t["query"], 1),
+            "delete_us_per_point": round(1e6 * t["delete"] / max(cnt["delete"], 1), 2),
+            "final_points": int(n), "final_live": int(cl.live_count),
+        }
+    line = {
+        "metric": "dynamic benchmark: total time of the interleaved insert/query/delete run",
+        "value": out["surface"]["total_s"], "unit": "s", "n_gpus": 1,
+        "steps": args.dyn_iterations, "warmup": 0,
+        "ms_per_step": round(1e3 * out["surface"]["total_s"] / args.dyn_iterations, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dynamic_5k_plus_200_per_iteration_k20",
+                   "iterations": args.dyn_iterations, "n0": 5000, "insert_per_iteration": 200,
+                   "queries_per_iteration": 2000, "k": 20, "delete": "100 every 50",
+                   "batch_insert": "2000 every 100"},
+        "extra": out,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_plane(args) -> int:
+    """k-NN with a plane fit per row (the scan convergence statistic): the headline cloud
+    (torus, 1M points), 1M probes on the surface (noise 1e-3), k=20, m=n; against the
+    same queries without the fit."""
+    import torch
+    from paper_2605_02224_amd import workloads as W
+    from paper_2605_02224_amd.api import Cloud
+    w = W.torus_paper_scale(n=args.n, nq=args.nq, k=20)
+    cl = Cloud.build(w.cloud.by_rank).upload()
+    q = torch.from_numpy(w.queries_b).cuda()
+    nq, k = q.shape[0], 20
+    res = {}
+    for name, fn in (("knn", lambda: cl.knn(q, k)), ("knn_plane", lambda: cl.knn_plane(q, k))):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[name] = (nq / dt, dt)
+        log(f"{name}: {nq / dt / 1e6:.1f} M queries/s, {dt * 1e3:.3f} ms per batch")
+    line = {
+        "metric": "k-NN + local plane fit: probes/s",
+        "value": round(res["knn_plane"][0], 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(res["knn_plane"][1] * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "torus_1M_surface_probes_k20_plane_fit", "n": args.n,
+                   "nq": nq, "k": k},
+        "extra": {"knn_only_qps": round(res["knn"][0], 1),
+                  "fit_overhead": round(res["knn_plane"][1] / res["knn"][1] - 1, 4)},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="torus", choices=["torus", "batched", "serving"])
+    ap.add_argument("--workload", default="torus",
+                    choices=["torus", "batched", "serving", "dynamic", "plane"])
+    ap.add_argument("--dyn-iterations", type=int, default=2000, help="dynamic: iterations")
     ap.add_argument("--requests", type=int, default=20000, help="serving: measured requests")
     ap.add_argument("--warm-requests", type=int, default=1000)
     ap.add_argument("--sat-requests", type=int, default=5000)
@@ -439,6 +559,10 @@ def main() -> int:
         return 2
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "dynamic":
+        return bench_dynamic(args)
+    if args.workload == "plane":
+        return bench_plane(args)
     if args.workload == "serving":
         if args.clouds == 256:
             args.clouds = 64

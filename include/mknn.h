@@ -222,6 +222,23 @@ mknn_status mknn_tune_load(const char *path);
 void mknn_tune_reset(void);
 
 /* ---------------------------------------------------------------------------------------
+ * k-NN with a local plane fit (the neighbourhood statistic of the paper's scan convergence
+ * study, Sec. 5.3.1: a plane fitted by PCA to each probe's k nearest neighbours in a prefix).
+ *
+ * mknn_knn_plane: the rows of mknn_knn, and per query 8 floats in d_plane (device float32
+ * [nq][8], caller-owned): the centroid c of the k' <= k neighbours found (3), the unit
+ * normal (3): the eigenvector of the smallest eigenvalue l0 of their covariance
+ * (1/k') sum (p - c)(p - c)^T, with its largest-magnitude component positive, the residual
+ * sqrt(l0) (RMS distance of the neighbours to the plane), and the surface variation
+ * l0 / (l0 + l1 + l2).  With fewer than three neighbours the last five are NaN (all eight
+ * with none).  Computed in float64 (cyclic Jacobi on the 3x3 covariance) by a second kernel
+ * that reads the rows just written, on the same stream.  Errors as mknn_knn.
+ */
+mknn_status mknn_knn_plane(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
+                           int32_t m, int32_t *d_idx, float *d_dist, float *d_plane,
+                           void *stream);
+
+/* ---------------------------------------------------------------------------------------
  * Work counters (diagnostics for the memory roofline).
  *
  * mknn_knn_counts: runs the same query path as mknn_knn and writes, per query, the number of
@@ -296,7 +313,8 @@ int64_t mknn_live_count(const mknn_cloud *c);
 int32_t mknn_head(const mknn_cloud *c);
 
 /* ---------------------------------------------------------------------------------------
- * Serving: continuous batching over resident clouds, deletions between batches.
+ * Serving: continuous batching over resident clouds, deletions (and insertions) between
+ * batches.
  *
  * A server owns `nstreams` stream slots (default priority) and a scheduler thread.
  * Requests and deletion batches are queued in arrival order.  Whenever a slot is free, the
@@ -332,16 +350,23 @@ mknn_status mknn_server_submit(mknn_server *s, const mknn_request *req, int32_t 
 /* Queue a deletion batch (host int32 ranks, copied). */
 mknn_status mknn_server_delete(mknn_server *s, mknn_cloud *c, const int32_t *ranks, int64_t count,
                                uint64_t *ticket);
+/* Queue an insertion batch (host float32 [count][3], copied; see mknn_insert).  Insertion
+ * and deletion batches of one cloud are one ordered stream of update batches, handled
+ * exactly like the deletions above; the new points take the ranks from the cloud's size
+ * when the batch is applied, so batches on one cloud number their points in arrival
+ * order. */
+mknn_status mknn_server_insert(mknn_server *s, mknn_cloud *c, const float *xyz, int64_t count,
+                               uint64_t *ticket);
 /* *done = 1 once the operation has completed. */
 mknn_status mknn_server_poll(mknn_server *s, uint64_t ticket, int32_t *done);
 /* Block until the operation completes, then forget the ticket.  times (may be NULL)
  * receives, in seconds of mknn_server_now(): [0] submission, [1] launch (a request's wave
  * was launched; a deletion's device delta was enqueued), [2] completion observed (after the
- * copies to host memory).  deletions_seen (may be NULL) receives, for a request, the number
- * of deletion batches of this server applied to its cloud when it was launched.  Returns
- * the operation's own status. */
+ * copies to host memory).  updates_seen (may be NULL) receives, for a request, the number
+ * of update batches (deletions and insertions) of this server applied to its cloud when it
+ * was launched.  Returns the operation's own status. */
 mknn_status mknn_server_wait(mknn_server *s, uint64_t ticket, double *times,
-                             int64_t *deletions_seen);
+                             int64_t *updates_seen);
 /* Waves launched so far and the requests they held. */
 mknn_status mknn_server_stats(mknn_server *s, int64_t *waves, int64_t *wave_requests);
 /* Monotonic clock of the server, in seconds. */

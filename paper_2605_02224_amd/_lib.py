@@ -27,6 +27,7 @@ SIGNATURES = {
     "mknn_upload": (ctypes.c_int, [_P, _P]),
     "mknn_device_bytes": (_I64, [_P]),
     "mknn_knn": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P]),
+    "mknn_knn_plane": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P, _P]),
     "mknn_knn_var": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P]),
     "mknn_knn_counts": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P, _P]),
     "mknn_timing_enable": (ctypes.c_int, [ctypes.c_int]),
@@ -65,6 +66,7 @@ SIGNATURES.update({
     "mknn_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(Request), _P, _P,
                                           ctypes.POINTER(ctypes.c_uint64)]),
     "mknn_server_delete": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(ctypes.c_uint64)]),
+    "mknn_server_insert": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(ctypes.c_uint64)]),
     "mknn_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_I32)]),
     "mknn_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(_I64)]),

@@ -139,6 +139,20 @@ class Cloud:
                                   _stream(stream)))
         return idx, dist
 
+    def knn_plane(self, q, k: int, m: Optional[int] = None, stream=None):
+        """k-NN rows plus a plane fitted to each row's neighbours: (idx, dist, plane) with
+        plane float32 [nq, 8] = centroid xyz, unit normal xyz, RMS residual, variation."""
+        import torch
+        q = q.contiguous()
+        nq = q.shape[0]
+        m = self.n if m is None else int(m)
+        idx = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        plane = torch.empty((nq, 8), dtype=torch.float32, device=q.device)
+        check(_lib.lib().mknn_knn_plane(self._h, _ptr(q), nq, int(k), m, _ptr(idx), _ptr(dist),
+                                        _ptr(plane), _stream(stream)))
+        return idx, dist, plane
+
     def knn_var(self, q, k_per_query, m_per_query, stream=None):
         """Per-query k and m; returns (idx, dist, row_off) with ragged rows (flat tensors)."""
         import torch
@@ -309,13 +323,23 @@ class Server:
         self._keep[t.value] = (r,)
         return t.value
 
+    def insert(self, cloud, points):
+        """Queue an insertion batch (float32 [count, 3]); ranks follow arrival order."""
+        pts = np.ascontiguousarray(np.asarray(points, dtype=np.float32).reshape(-1, 3))
+        t = ctypes.c_uint64()
+        check(_lib.lib().mknn_server_insert(self._h, cloud.handle, _ptr(pts), pts.shape[0],
+                                            ctypes.byref(t)))
+        self._keep[t.value] = (pts,)
+        return t.value
+
     def done(self, ticket) -> bool:
         d = ctypes.c_int32()
         check(_lib.lib().mknn_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(d)))
         return bool(d.value)
 
     def wait(self, ticket, with_seen: bool = False):
-        """Block until done; returns (submit_time, done_time, buffers[, deletions_seen])."""
+        """Block until done; returns (submit_time, done_time, buffers[, updates_seen]):
+        updates_seen counts the deletion and insertion batches a request saw."""
         t = (ctypes.c_double * 3)()
         v = ctypes.c_int64()
         st = _lib.lib().mknn_server_wait(self._h, ctypes.c_uint64(ticket), t, ctypes.byref(v))

@@ -45,6 +45,7 @@ struct InsertState {
 struct HostPack {
   std::vector<float> ent;          // 4 floats per record
   std::vector<uint64_t> lst;
+  std::vector<float> pts;          // 4 floats per rank {x, y, z, 0}
   int64_t nnz = 0;                 // records in use
   int64_t cap = 0;                 // records to allocate (slack for later deltas + padding)
 };
@@ -56,15 +57,19 @@ struct DeviceDelta {
   std::vector<uint32_t> lens;      // their new lengths
   std::vector<float> rec;          // their new records {x, y, z, rank bits}, concatenated
   std::vector<uint64_t> desc;      // new descriptors (filled when applied)
+  std::vector<float> new_pts;      // appended points {x, y, z, 0}, ranks pts_from ..
+  int64_t pts_from = 0;
   bool repack = false;             // apply `pack` as a new arena instead
   HostPack pack;
   void *old_ent = nullptr;         // arena replaced by a re-pack: free once its readers are done
   uint64_t *old_lst = nullptr;
+  void *old_pts = nullptr;
 };
 }  // namespace mknn
 
 struct mknn_cloud {
-  int64_t n = 0;
+  std::atomic<int64_t> n{0};       // ranks so far (atomic: a server's clients read it while a
+                                   // worker appends points)
   std::vector<float> xyz;          // n x 3 float32 by rank
   std::vector<int32_t> order;      // rank -> caller id
   mknn::Csr succ;                  // successor lists (ranks ascending)
@@ -86,11 +91,18 @@ struct mknn_cloud {
   int device = -1;
   void *d_ent = nullptr;           // 16-byte records {x, y, z, rank}, padded
   uint64_t *d_lst = nullptr;       // per rank: start | (length << 32)
+  void *d_pts = nullptr;           // per rank: {x, y, z, 0} (for statistics of k-NN rows)
   int64_t ent_used = 0, ent_cap = 0;   // records in use / allocated (slack takes deltas)
   int64_t lst_cap = 0;             // descriptors allocated (slack for appended points)
   int64_t dev_bytes = 0;
   std::atomic<uint64_t> dev_version{~0ull};
+  // What the device lists describe, recorded when they were installed or last updated:
+  // query launches read these, never the host fields above, which a worker thread of a
+  // server may be changing for the next update batch.
   int32_t dev_head = 0;            // the head of the lists on the device
+  float dev_hxyz[3] = {0, 0, 0};   // its coordinates
+  int64_t dev_n = 0;               // ranks the device lists cover
+  float dev_lo[3] = {0, 0, 0}, dev_hi[3] = {0, 0, 0};   // bounding box (for query bucketing)
 };
 
 namespace mknn {

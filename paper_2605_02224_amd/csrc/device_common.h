@@ -45,14 +45,28 @@ __host__ __device__ __forceinline__ uint32_t morton30(float x, float y, float z,
   return (spread3(u[0]) << 2) | (spread3(u[1]) << 1) | spread3(u[2]);
 }
 
-inline BoxArgs box_of(const mknn_cloud *c) {
+inline BoxArgs box_of(const float lo[3], const float hi[3]) {
   BoxArgs b;
   for (int k = 0; k < 3; ++k) {
-    float ext = c->hi[k] - c->lo[k];
-    b.lo[k] = c->lo[k];
+    float ext = hi[k] - lo[k];
+    b.lo[k] = lo[k];
     b.scale[k] = ext > 0.f ? 1024.f / ext : 0.f;
   }
   return b;
+}
+// the box of the host points (packing) and of the lists on the device (query bucketing)
+inline BoxArgs box_of(const mknn_cloud *c) { return box_of(c->lo, c->hi); }
+inline BoxArgs dev_box_of(const mknn_cloud *c) { return box_of(c->dev_lo, c->dev_hi); }
+
+// Record what the device lists now describe (after an upload or an applied update).
+inline void note_device_state(mknn_cloud *c) {
+  c->dev_head = c->head;
+  for (int k = 0; k < 3; ++k) {
+    c->dev_hxyz[k] = c->xyz[3 * (int64_t)c->head + k];
+    c->dev_lo[k] = c->lo[k];
+    c->dev_hi[k] = c->hi[k];
+  }
+  c->dev_n = c->n;
 }
 
 template <typename T>
@@ -90,10 +104,10 @@ inline void fill_cloud_args(const mknn_cloud *c, QueryArgs *a) {
   a->ent = (const float4 *)c->d_ent;
   a->lst = c->d_lst;
   a->head = c->dev_head;
-  a->hx = c->xyz[3 * (int64_t)c->dev_head];
-  a->hy = c->xyz[3 * (int64_t)c->dev_head + 1];
-  a->hz = c->xyz[3 * (int64_t)c->dev_head + 2];
-  a->n = c->n;
+  a->hx = c->dev_hxyz[0];
+  a->hy = c->dev_hxyz[1];
+  a->hz = c->dev_hxyz[2];
+  a->n = c->dev_n;
 }
 
 // A list change in two steps: delete_prepare / insert_prepare edit the host lists and

@@ -418,7 +418,7 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
     if (st != MKNN_OK) return st;
     if (q.k > MKNN_KMAX) return set_error(MKNN_EUNSUPPORTED, who + ": k above MKNN_KMAX");
     if (q.k < 1) return set_error(MKNN_EINVAL, who + ": k must be >= 1");
-    if (q.m < 0 || q.m > q.cloud->n) return set_error(MKNN_EINVAL, who + ": m out of [0, n]");
+    if (q.m < 0 || q.m > q.cloud->dev_n) return set_error(MKNN_EINVAL, who + ": m out of [0, n]");
     if (q.nq < 0) return set_error(MKNN_EINVAL, who + ": nq < 0");
     if (q.nq > 0 && (!q.d_q || !q.d_idx || !q.d_dist))
       return set_error(MKNN_EINVAL, who + ": NULL buffer");
@@ -430,7 +430,7 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   // ---- tiles: requests on queues by largest-processing-time first, per class
   std::vector<double> cost((size_t)nreq);
   for (int32_t r = 0; r < nreq; ++r)
-    cost[r] = (double)reqs[r].nq * (reqs[r].k + 8) * std::log2((double)reqs[r].cloud->n + 2.0);
+    cost[r] = (double)reqs[r].nq * (reqs[r].k + 8) * std::log2((double)reqs[r].cloud->dev_n + 2.0);
   std::vector<int32_t> order((size_t)nreq);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
@@ -483,15 +483,15 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   for (int32_t r = 0; r < nreq; ++r) {
     const mknn_request &q = reqs[r];
     fill_cloud_args(q.cloud, &args[r]);
-    args[r].merge_min = config_for(q.k, false, q.cloud->n).merge_min;
+    args[r].merge_min = config_for(q.k, false, q.cloud->dev_n).merge_min;
     args[r].q = q.d_q;
     args[r].qs = p->sort ? p->d_qs + qoff[r] : nullptr;
     args[r].nq = q.nq;
     args[r].k = q.k;
-    args[r].m = q.m == 0 ? (int32_t)q.cloud->n : q.m;
+    args[r].m = q.m == 0 ? (int32_t)q.cloud->dev_n : q.m;
     args[r].out_idx = q.d_idx;
     args[r].out_dist = q.d_dist;
-    boxes[r] = box_of(q.cloud);
+    boxes[r] = dev_box_of(q.cloud);
   }
   for (int32_t r = 0; r <= nreq; ++r) d_qoff[r] = qoff[r];
   // ---- run (graph replay or eager)

@@ -30,6 +30,7 @@
 #include "device_common.h"
 #include "knn_group.h"
 #include "knn_rows.h"
+#include "planefit.h"
 
 namespace mknn {
 
@@ -267,8 +268,10 @@ __global__ __launch_bounds__(256) void morton_scatter_kernel(const float *q, int
 static void free_device(mknn_cloud *c) {
   if (c->d_ent) (void)hipFree(c->d_ent);
   if (c->d_lst) (void)hipFree(c->d_lst);
+  if (c->d_pts) (void)hipFree(c->d_pts);
   c->d_ent = nullptr;
   c->d_lst = nullptr;
+  c->d_pts = nullptr;
   c->dev_bytes = 0;
   c->dev_version = ~0ull;
 }
@@ -283,8 +286,10 @@ __global__ __launch_bounds__(256) void apply_descriptors_kernel(uint64_t *lst, c
 void release_old_arena(DeviceDelta *d) {
   if (d->old_ent) (void)hipFree(d->old_ent);
   if (d->old_lst) (void)hipFree(d->old_lst);
+  if (d->old_pts) (void)hipFree(d->old_pts);
   d->old_ent = nullptr;
   d->old_lst = nullptr;
+  d->old_pts = nullptr;
 }
 
 // ---- the device image of the lists
@@ -309,6 +314,9 @@ mknn_status pack_lists(mknn_cloud *c, HostPack *p) {
       return set_error(MKNN_EUNSUPPORTED, "mknn_upload: more than 2^32 list entries");
     p->ent.assign((size_t)(nnz + kEntPad) * 4, 0.f);
     p->lst.resize((size_t)n);
+    p->pts.assign((size_t)n * 4, 0.f);
+    for (int64_t r = 0; r < n; ++r)
+      for (int k = 0; k < 3; ++k) p->pts[4 * r + k] = c->xyz[3 * r + k];
     uint64_t cur = 0;
     for (int64_t t = 0; t < n; ++t) {
       int64_t r = (int64_t)(key[t] & 0xffffffffu);
@@ -340,29 +348,35 @@ mknn_status pack_lists(mknn_cloud *c, HostPack *p) {
 // host image must stay alive until `s` has passed the copies.  The previous arena is not
 // touched; c->d_ent / c->d_lst are replaced.
 mknn_status install_pack(mknn_cloud *c, const HostPack *p, hipStream_t s) {
-  void *ent = nullptr;
+  void *ent = nullptr, *pts = nullptr;
   uint64_t *lst = nullptr;
-  // descriptors for appended points: an eighth more than the points present
+  // descriptors and points for appended ranks: an eighth more than the points present
   const int64_t lst_cap = (int64_t)p->lst.size() + std::max<int64_t>((int64_t)p->lst.size() / 8, 1024);
   hipError_t e = hipMalloc(&ent, sizeof(float4) * (size_t)p->cap);
   if (e == hipSuccess) e = hipMalloc((void **)&lst, sizeof(uint64_t) * (size_t)lst_cap);
+  if (e == hipSuccess) e = hipMalloc(&pts, sizeof(float4) * (size_t)lst_cap);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ent, p->ent.data(), sizeof(float) * p->ent.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(lst, p->lst.data(), sizeof(uint64_t) * p->lst.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(pts, p->pts.data(), sizeof(float) * p->pts.size(), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) {
     if (ent) (void)hipFree(ent);
     if (lst) (void)hipFree(lst);
+    if (pts) (void)hipFree(pts);
     return set_error(e == hipErrorOutOfMemory ? MKNN_ENOMEM : MKNN_EHIP,
                      std::string("mknn_upload: ") + hipGetErrorName(e));
   }
   c->d_ent = ent;
   c->d_lst = lst;
-  c->dev_bytes = (int64_t)(sizeof(float4) * (size_t)p->cap + sizeof(uint64_t) * (size_t)lst_cap);
+  c->d_pts = pts;
+  c->dev_bytes = (int64_t)(sizeof(float4) * (size_t)p->cap +
+                           (sizeof(uint64_t) + sizeof(float4)) * (size_t)lst_cap);
   c->lst_cap = lst_cap;
   c->ent_used = p->nnz;
   c->ent_cap = p->cap - kEntPad;
-  c->dev_head = c->head;
+  note_device_state(c);
   c->dev_version = c->version.load();
   return MKNN_OK;
 }
@@ -383,6 +397,11 @@ static mknn_status fill_delta(mknn_cloud *c, const std::vector<int32_t> &changed
     return st;
   }
   try {
+    // appended points (insertion), for the per-rank point array
+    d->pts_from = c->dev_n;
+    d->new_pts.assign((size_t)(c->n - c->dev_n) * 4, 0.f);
+    for (int64_t r = c->dev_n; r < c->n; ++r)
+      for (int k = 0; k < 3; ++k) d->new_pts[4 * (r - c->dev_n) + k] = c->xyz[3 * r + k];
     // copy-on-write: every changed list gets a fresh segment at the end of the arena, so
     // work that already read the old descriptor keeps reading the old, untouched records
     d->ranks = changed;
@@ -442,12 +461,13 @@ mknn_status apply_delta(mknn_cloud *c, DeviceDelta *d, hipStream_t s) {
   const int64_t need = (int64_t)(d->rec.size() / 4);
   if (d->repack) {
     // a new arena; the old one is kept for the work that still reads it (d->old_*)
-    void *old_ent = c->d_ent;
+    void *old_ent = c->d_ent, *old_pts = c->d_pts;
     uint64_t *old_lst = c->d_lst;
     mknn_status st = install_pack(c, &d->pack, s);
     if (st != MKNN_OK) return st;
     d->old_ent = old_ent;
     d->old_lst = old_lst;
+    d->old_pts = old_pts;
     return MKNN_OK;
   }
   d->desc.resize(d->ranks.size());
@@ -464,6 +484,10 @@ mknn_status apply_delta(mknn_cloud *c, DeviceDelta *d, hipStream_t s) {
   if (need)
     HIP_TRY(hipMemcpyAsync((float4 *)c->d_ent + c->ent_used, d->rec.data(), sizeof(float) * d->rec.size(),
                            hipMemcpyHostToDevice, s), "apply list delta: copy records");
+  if (!d->new_pts.empty())
+    HIP_TRY(hipMemcpyAsync((float4 *)c->d_pts + d->pts_from, d->new_pts.data(),
+                           sizeof(float) * d->new_pts.size(), hipMemcpyHostToDevice, s),
+            "apply list delta: copy points");
   HIP_TRY(hipMemcpyAsync(d_dd, d->desc.data(), sizeof(uint64_t) * d->desc.size(), hipMemcpyHostToDevice, s),
           "apply list delta: copy descriptors");
   HIP_TRY(hipMemcpyAsync(d_rr, d->ranks.data(), sizeof(int32_t) * d->ranks.size(), hipMemcpyHostToDevice, s),
@@ -474,7 +498,7 @@ mknn_status apply_delta(mknn_cloud *c, DeviceDelta *d, hipStream_t s) {
   HIP_TRY(hipGetLastError(), "apply list delta: launch");
   HIP_TRY(hipFreeAsync(d_tmp, s), "apply list delta: free scratch");
   c->ent_used += need;
-  c->dev_head = c->head;
+  note_device_state(c);
   c->dev_version = c->version.load();
   return MKNN_OK;
 }
@@ -651,7 +675,7 @@ static mknn_status prepare_queries(const mknn_cloud *c, const float *d_q, int64_
   HIP_TRY(hipMallocAsync(scratch, bytes, s), "query sort scratch");
   uint32_t *hist = (uint32_t *)*scratch;
   float4 *qs = (float4 *)(hist + kMortonBins);
-  BoxArgs b = box_of(c);
+  BoxArgs b = dev_box_of(c);
   const int threads = 256;
   const uint32_t blocks = (uint32_t)((nq + threads - 1) / threads);
   hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(kMortonBins / threads), dim3(threads), 0, s,
@@ -668,7 +692,8 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
                              int32_t m, const int32_t *d_k, const int32_t *d_m,
                              const int64_t *d_row_off, int32_t kmax, int32_t *d_idx,
                              float *d_dist, int32_t *d_ce, int32_t *d_cl, int32_t *d_ci,
-                             hipStream_t s, const char *who, const TuneConfig *force = nullptr) {
+                             hipStream_t s, const char *who, const TuneConfig *force = nullptr,
+                             float *d_plane = nullptr) {
   QueryArgs a;
   fill_cloud_args(c, &a);
   a.q = d_q;
@@ -689,7 +714,7 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
   if (st != MKNN_OK) return st;
   a.qs = qs;
   const bool exact = (d_k == nullptr);
-  const TuneConfig cfg = force ? *force : config_for(kmax, exact, c->n);
+  const TuneConfig cfg = force ? *force : config_for(kmax, exact, c->dev_n);
   a.merge_min = cfg.merge_min;
   hipError_t e = timing_mark(s, true);
   if (e == hipSuccess) {
@@ -701,6 +726,9 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
       e = d_ce ? dispatch_group<true>(a, kmax, exact, s) : dispatch_group<false>(a, kmax, exact, s);
   }
   if (e == hipSuccess) e = timing_mark(s, false);
+  // the plane fit reads the rows just written (and the sorted queries, for their order)
+  if (e == hipSuccess && d_plane)
+    e = launch_plane_fit((const float4 *)c->d_pts, d_idx, qs, nq, k, d_plane, s);
   if (scratch) (void)hipFreeAsync(scratch, s);
   if (e != hipSuccess)
     return set_error(MKNN_EHIP, std::string(who) + ": launch failed: " + hipGetErrorName(e));
@@ -743,6 +771,7 @@ mknn_status mknn_compact(mknn_cloud *c, void *stream) {
   DeviceDelta old;
   old.old_ent = c->d_ent;
   old.old_lst = c->d_lst;
+  old.old_pts = c->d_pts;
   st = install_pack(c, &pack, s);
   if (st != MKNN_OK) return st;
   HIP_TRY(hipStreamSynchronize(s), "mknn_compact: synchronize");
@@ -760,11 +789,28 @@ mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t 
   if (nq < 0 || nq > 0x7fffffffll) return set_error(MKNN_EINVAL, "mknn_knn: nq out of range");
   mknn_status st = check_uploaded(c, "mknn_knn");
   if (st != MKNN_OK) return st;
-  if (m < 1 || m > c->n) return set_error(MKNN_EINVAL, "mknn_knn: m must be in [1, n]");
+  if (m < 1 || m > c->dev_n) return set_error(MKNN_EINVAL, "mknn_knn: m must be in [1, n]");
   if (nq == 0) return MKNN_OK;
   if (!d_q || !d_idx || !d_dist) return set_error(MKNN_EINVAL, "mknn_knn: NULL buffer");
   return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, d_idx, d_dist, nullptr,
                    nullptr, nullptr, (hipStream_t)stream, "mknn_knn");
+}
+
+mknn_status mknn_knn_plane(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
+                           int32_t m, int32_t *d_idx, float *d_dist, float *d_plane,
+                           void *stream) {
+  clear_error();
+  if (k > MKNN_KMAX) return set_error(MKNN_EUNSUPPORTED, "mknn_knn_plane: k above MKNN_KMAX");
+  if (k < 1) return set_error(MKNN_EINVAL, "mknn_knn_plane: k must be >= 1");
+  if (nq < 0 || nq > 0x7fffffffll) return set_error(MKNN_EINVAL, "mknn_knn_plane: nq out of range");
+  mknn_status st = check_uploaded(c, "mknn_knn_plane");
+  if (st != MKNN_OK) return st;
+  if (m < 1 || m > c->dev_n) return set_error(MKNN_EINVAL, "mknn_knn_plane: m must be in [1, n]");
+  if (nq == 0) return MKNN_OK;
+  if (!d_q || !d_idx || !d_dist || !d_plane)
+    return set_error(MKNN_EINVAL, "mknn_knn_plane: NULL buffer");
+  return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, d_idx, d_dist, nullptr,
+                   nullptr, nullptr, (hipStream_t)stream, "mknn_knn_plane", nullptr, d_plane);
 }
 
 mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, const int32_t *d_k,
@@ -792,7 +838,7 @@ mknn_status mknn_knn_counts(const mknn_cloud *c, const float *d_q, int64_t nq, i
   if (nq < 0 || nq > 0x7fffffffll) return set_error(MKNN_EINVAL, "mknn_knn_counts: nq out of range");
   mknn_status st = check_uploaded(c, "mknn_knn_counts");
   if (st != MKNN_OK) return st;
-  if (m < 1 || m > c->n) return set_error(MKNN_EINVAL, "mknn_knn_counts: m must be in [1, n]");
+  if (m < 1 || m > c->dev_n) return set_error(MKNN_EINVAL, "mknn_knn_counts: m must be in [1, n]");
   if (nq == 0) return MKNN_OK;
   if (!d_q || !d_entries || !d_lists) return set_error(MKNN_EINVAL, "mknn_knn_counts: NULL buffer");
   return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, nullptr, nullptr, d_entries,
@@ -809,8 +855,8 @@ mknn_status mknn_autotune(const mknn_cloud *c, const float *d_q, int64_t nq, int
   if (!d_q || (max_tried > 0 && !tried)) return set_error(MKNN_EINVAL, "mknn_autotune: NULL buffer");
   mknn_status st = check_uploaded(c, "mknn_autotune");
   if (st != MKNN_OK) return st;
-  if (m == 0) m = (int32_t)c->n;
-  if (m < 1 || m > c->n) return set_error(MKNN_EINVAL, "mknn_autotune: m must be in [0, n]");
+  if (m == 0) m = (int32_t)c->dev_n;
+  if (m < 1 || m > c->dev_n) return set_error(MKNN_EINVAL, "mknn_autotune: m must be in [0, n]");
   const int S = (k + 15) / 16;
   std::vector<TuneConfig> cand;
   for (int pw : {4, 8}) {
@@ -857,7 +903,7 @@ mknn_status mknn_autotune(const mknn_cloud *c, const float *d_q, int64_t nq, int
   (void)hipGetDevice(&dev);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(dev, S, k == 16 * S, c->n)] = cand[bi];
+    g_tune[tune_key(dev, S, k == 16 * S, c->dev_n)] = cand[bi];
   }
   const int32_t n_out = (int32_t)std::min<size_t>(cand.size(), max_tried > 0 ? (size_t)max_tried : 0);
   for (int32_t t = 0; t < n_out; ++t)

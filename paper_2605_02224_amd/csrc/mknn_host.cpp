@@ -155,7 +155,7 @@ mknn_status mknn_build(const float *xyz, int64_t n, const int32_t *order, mknn_c
   return MKNN_OK;
 }
 
-int64_t mknn_size(const mknn_cloud *c) { return c ? c->n : 0; }
+int64_t mknn_size(const mknn_cloud *c) { return c ? c->n.load() : 0; }
 
 mknn_status mknn_successors(const mknn_cloud *c, const int64_t **offsets, const int32_t **ranks,
                             int64_t *nnz) {

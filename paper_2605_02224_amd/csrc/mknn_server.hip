@@ -22,6 +22,10 @@
 // MKNN_SERVER_BIND_AT_ADMISSION a request binds to the lists current when its wave is
 // launched, so requests never wait for the host part of a deletion.
 //
+// Insertion batches (points appended as new ranks) are update batches of the same kind:
+// they share the per-cloud order, the worker threads, the delta path and the counts of
+// update batches a request saw.  Below, "deletion" stands for either kind.
+//
 // In plain mode (the baseline) every request is its own mknn_knn launch.  All of them go,
 // in FIFO order and back to back, onto one stream; up to kPlainSlots are in flight, each
 // with its own completion event, and the requests in flight hold at most the pool.
@@ -54,15 +58,17 @@ static double now_s() {
 
 struct ServerOp {
   uint64_t ticket = 0;
-  bool is_delete = false;
+  bool is_update = false;           // a list update batch: a deletion, or an insertion
+  bool is_insert = false;
   mknn_request req{};
   int32_t *h_idx = nullptr;
   float *h_dist = nullptr;
   mknn_cloud *cloud = nullptr;
-  std::vector<int32_t> ranks;
+  std::vector<int32_t> ranks;       // deletion
+  std::vector<float> xyz;           // insertion, [count][3]
   DeviceDelta delta;
   double t_submit = 0, t_launch = 0, t_done = 0;
-  int64_t seen = 0;                 // deletion batches applied to the cloud at launch
+  int64_t seen = 0;                 // update batches applied to the cloud at launch
   mknn_status status = MKNN_OK;
   std::string err;
   bool done = false;
@@ -106,7 +112,7 @@ struct mknn_server {
   std::atomic<bool> dirty{false};   // new operations or finished host work since the last pass
   std::deque<int> plain_order;      // plain mode: busy slots in launch order (one stream)
   std::list<OpPtr> pending;         // arrival order
-  int64_t pending_deletes = 0;
+  int64_t pending_updates = 0;
   std::unordered_map<uint64_t, OpPtr> ops;
   std::unordered_set<mknn_cloud *> blocked;   // a deletion is in its host or device part
   std::unordered_map<mknn_cloud *, int64_t> applied;   // deletion batches applied per cloud
@@ -162,6 +168,9 @@ static void launch_wave(mknn_server *s, int x, std::vector<OpPtr> &wave) {
     sl.clouds.insert(op->cloud);
     auto it = s->applied.find(op->cloud);
     op->seen = it == s->applied.end() ? 0 : it->second;
+    // a prefix beyond the lists the request runs on (possible when bound at admission
+    // while an insertion of its submitter was pending) covers them all
+    if (op->req.m > op->cloud->dev_n) op->req.m = 0;
   }
   for (mknn_cloud *c : sl.clouds) {
     auto it = s->ready_ev.find(c);
@@ -170,7 +179,7 @@ static void launch_wave(mknn_server *s, int x, std::vector<OpPtr> &wave) {
   mknn_status st = MKNN_OK;
   if (s->plain) {
     const mknn_request &r = wave[0]->req;
-    st = mknn_knn(r.cloud, r.d_q, r.nq, r.k, r.m == 0 ? (int32_t)r.cloud->n : r.m, r.d_idx,
+    st = mknn_knn(r.cloud, r.d_q, r.nq, r.k, r.m == 0 ? (int32_t)r.cloud->dev_n : r.m, r.d_idx,
                   r.d_dist, sl.stream);
   } else {
     std::vector<mknn_request> reqs;
@@ -214,9 +223,11 @@ static void worker_loop(mknn_server *s) {
     OpPtr op = s->del_queue.front();
     s->del_queue.pop_front();
     lk.unlock();
-    // host part of Alg. 3
+    // host part of Alg. 3, or of an insertion
     const double t0 = now_s();
-    op->status = delete_prepare(op->cloud, op->ranks.data(), (int64_t)op->ranks.size(), &op->delta);
+    op->status = op->is_insert
+                     ? insert_prepare(op->cloud, op->xyz.data(), (int64_t)op->xyz.size() / 3, &op->delta)
+                     : delete_prepare(op->cloud, op->ranks.data(), (int64_t)op->ranks.size(), &op->delta);
     if (op->status != MKNN_OK) op->err = mknn_last_error();
     const double dt = now_s() - t0;
     lk.lock();
@@ -338,7 +349,7 @@ static void scheduler_loop(mknn_server *s) {
       for (auto it = s->pending.begin(); it != s->pending.end();) {
         const OpPtr &op = *it;
         mknn_cloud *c = op->cloud;
-        if (op->is_delete || (s->strict && (s->blocked.count(c) || held.count(c)))) {
+        if (op->is_update || (s->strict && (s->blocked.count(c) || held.count(c)))) {
           if (s->strict) held.insert(c);
           ++it;
           continue;
@@ -358,12 +369,12 @@ static void scheduler_loop(mknn_server *s) {
     }
     // ---- start deletions: one at a time per cloud, in arrival order; in strict order only
     //      once no earlier request on the cloud is still waiting
-    if (s->pending_deletes > 0) {
+    if (s->pending_updates > 0) {
       std::unordered_set<mknn_cloud *> held, del_held;
       for (auto it = s->pending.begin(); it != s->pending.end();) {
         const OpPtr &op = *it;
         mknn_cloud *c = op->cloud;
-        if (!op->is_delete) {
+        if (!op->is_update) {
           held.insert(c);
           ++it;
           continue;
@@ -371,7 +382,7 @@ static void scheduler_loop(mknn_server *s) {
         if (!s->blocked.count(c) && !del_held.count(c) && !(s->strict && held.count(c))) {
           s->blocked.insert(c);
           s->del_queue.push_back(op);
-          --s->pending_deletes;
+          --s->pending_updates;
           s->cv_work.notify_one();
           it = s->pending.erase(it);
         } else {
@@ -477,7 +488,7 @@ mknn_status mknn_server_delete(mknn_server *s, mknn_cloud *c, const int32_t *ran
   if (!s || !c || !ticket || count < 0 || (count > 0 && !ranks))
     return set_error(MKNN_EINVAL, "mknn_server_delete: bad argument");
   OpPtr op = std::make_shared<ServerOp>();
-  op->is_delete = true;
+  op->is_update = true;
   op->cloud = c;
   op->ranks.assign(ranks, ranks + count);
   op->t_submit = now_s();
@@ -487,7 +498,29 @@ mknn_status mknn_server_delete(mknn_server *s, mknn_cloud *c, const int32_t *ran
   *ticket = op->ticket;
   s->ops[op->ticket] = op;
   s->pending.push_back(op);
-  ++s->pending_deletes;
+  ++s->pending_updates;
+  wake_scheduler(s);
+  return MKNN_OK;
+}
+
+mknn_status mknn_server_insert(mknn_server *s, mknn_cloud *c, const float *xyz, int64_t count,
+                               uint64_t *ticket) {
+  clear_error();
+  if (!s || !c || !ticket || count < 0 || (count > 0 && !xyz))
+    return set_error(MKNN_EINVAL, "mknn_server_insert: bad argument");
+  OpPtr op = std::make_shared<ServerOp>();
+  op->is_update = true;
+  op->is_insert = true;
+  op->cloud = c;
+  op->xyz.assign(xyz, xyz + 3 * count);
+  op->t_submit = now_s();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return set_error(MKNN_EINVAL, "mknn_server_insert: server is stopping");
+  op->ticket = s->next_ticket++;
+  *ticket = op->ticket;
+  s->ops[op->ticket] = op;
+  s->pending.push_back(op);
+  ++s->pending_updates;
   wake_scheduler(s);
   return MKNN_OK;
 }
@@ -503,7 +536,7 @@ mknn_status mknn_server_poll(mknn_server *s, uint64_t ticket, int32_t *done) {
 }
 
 mknn_status mknn_server_wait(mknn_server *s, uint64_t ticket, double *times,
-                             int64_t *deletions_seen) {
+                             int64_t *updates_seen) {
   clear_error();
   if (!s) return set_error(MKNN_EINVAL, "mknn_server_wait: server is NULL");
   std::unique_lock<std::mutex> lk(s->mu);
@@ -517,7 +550,7 @@ mknn_status mknn_server_wait(mknn_server *s, uint64_t ticket, double *times,
     times[1] = op->t_launch;
     times[2] = op->t_done;
   }
-  if (deletions_seen) *deletions_seen = op->seen;
+  if (updates_seen) *updates_seen = op->seen;
   if (op->status != MKNN_OK) return set_error(op->status, op->err);
   return MKNN_OK;
 }

@@ -329,6 +329,54 @@ def serving_clouds(num: int = 64, n_lo: int = 10_000, n_hi: int = 2_000_000,
     return ServingWorkload(f"serving_{num}_clouds", clouds, st[S_REQ])
 
 
+@dataclasses.dataclass
+class DynamicWorkload:
+    """The dynamic benchmark of Sec. 5.4 (after ikd-Tree's): start with n0
+    points; every iteration inserts `insert_per_iter` points and answers `queries_per_iter`
+    queries with k neighbours; every `delete_every` iterations `delete_count` random live
+    points are deleted, every `batch_every` iterations `batch_count` more are inserted."""
+    name: str
+    points: np.ndarray          # float32 [N, 3], in insertion order (the stream)
+    n0: int
+    iterations: int
+    insert_per_iter: int
+    queries_per_iter: int
+    k: int
+    delete_every: int
+    delete_count: int
+    batch_every: int
+    batch_count: int
+    qlo: np.ndarray
+    qhi: np.ndarray
+    rng: np.random.Generator    # queries and deletion picks, drawn in iteration order
+
+
+def dynamic_stream(scenario: str = "surface", iterations: int = 2000, seed: int = 0,
+                   n0: int = 5000, insert_per_iter: int = 200, queries_per_iter: int = 2000,
+                   k: int = 20, delete_every: int = 50, delete_count: int = 100,
+                   batch_every: int = 100, batch_count: int = 2000) -> DynamicWorkload:
+    """scenario "surface": points on the torus (normal noise 1e-3) standing in for a scanned
+    model, queries uniform in the 2x bounding box; "volume": points and queries uniform in
+    [-10, 10]^3."""
+    st = _streams(seed)
+    total = n0 + iterations * insert_per_iter + (iterations // batch_every) * batch_count
+    if scenario == "surface":
+        gen = lambda m: sample_torus(st[S_POINTS], m, 1e-3)
+    elif scenario == "volume":
+        gen = lambda m: st[S_POINTS].uniform(-10.0, 10.0, (m, 3))
+    else:
+        raise ValueError(scenario)
+    p = _dedupe_f32(gen(total), gen)
+    p = np.ascontiguousarray(p[st[S_ORDER].permutation(total)])
+    if scenario == "surface":
+        lo, hi = bbox_expanded(p, 2.0)
+    else:
+        lo, hi = np.full(3, -10.0), np.full(3, 10.0)
+    return DynamicWorkload(f"dynamic_{scenario}", p, n0, iterations, insert_per_iter,
+                           queries_per_iter, k, delete_every, delete_count, batch_every,
+                           batch_count, lo, hi, st[S_REQ])
+
+
 # --------------------------------------------------------------------------------------
 # small helpers for tests
 # --------------------------------------------------------------------------------------

@@ -183,3 +183,62 @@ def test_errors_and_empty_requests(env):
     assert idx.cpu().numpy()[:, 0].tolist() == list(range(5))
     assert (dist.cpu().numpy() == 0).all()
     srv.close()
+
+
+def test_insertions_and_deletions_between_batches(env):
+    """Insertion batches go through the same ordered update path as deletions: every
+    request sees exactly the update batches submitted before it on its cloud, and equals
+    the oracle on the points present after those (new points take the next ranks)."""
+    torch, oracle, A, W = env
+    Pfull = [W.random_cloud(n, seed=90 + i, shape=W.SHAPES[i % 3]).by_rank
+             for i, n in enumerate((6000, 15000))]
+    n0 = [2000, 9000]
+    clouds = [(P, A.Cloud.build(P[:n]).upload()) for P, n in zip(Pfull, n0)]
+    torch.cuda.synchronize()
+    # per cloud: the list of (n, live mask over the full stream) after v update batches
+    states = [[(n, np.concatenate([np.ones(n, np.uint8), np.zeros(P.shape[0] - n, np.uint8)]))]
+              for (P, _), n in zip(clouds, n0)]
+    rng = np.random.default_rng(12)
+    srv = A.Server(pool_queries=1 << 15, nstreams=2, max_wave_requests=16)
+    log = []
+    for step in range(60):
+        c = int(rng.integers(2))
+        P, cl = clouds[c]
+        n, live = states[c][-1]
+        u = rng.uniform()
+        if u < 0.2 and n + 600 <= P.shape[0]:
+            cnt = int(rng.integers(1, 600))
+            nxt = live.copy()
+            nxt[n:n + cnt] = 1
+            states[c].append((n + cnt, nxt))
+            log.append(("ins", srv.insert(cl, P[n:n + cnt]), c, None, None, None))
+        elif u < 0.3:
+            alive = np.flatnonzero(live)
+            dead = rng.choice(alive, int(rng.integers(1, 100)), replace=False)
+            nxt = live.copy()
+            nxt[dead] = 0
+            states[c].append((n, nxt))
+            log.append(("del", srv.delete(cl, dead), c, None, None, None))
+        else:
+            nq = int(rng.choice([50, 500, 2000]))
+            k = int(rng.choice([4, 16, 40]))
+            Q = W.uniform_in_box(rng, nq, *W.bbox_expanded(P, 1.1))
+            log.append(("knn", srv.submit(cl, torch.from_numpy(Q).cuda(), k), c, Q, k,
+                        len(states[c]) - 1))
+    res = {t: srv.wait(t, with_seen=True) for _, t, *_ in log}
+    srv.close()
+    assert any(kind == "ins" for kind, *_ in log)
+    for kind, t, c, Q, k, before in log:
+        if kind != "knn":
+            continue
+        _, _, (_, idx, dist, *_), seen = res[t]
+        assert seen == before
+        n, live = states[c][seen]
+        P = clouds[c][0][:n]
+        sel = np.arange(min(100, Q.shape[0]))
+        ri, _, rD = oracle.knn_bruteforce(P, Q[sel], k + 1, live=live[:n])
+        compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k], rD[:, :k],
+                     rD[:, k])
+    for c, (P, cl) in enumerate(clouds):
+        n, live = states[c][-1]
+        assert cl.n == n and cl.live_count == int(live.sum())
