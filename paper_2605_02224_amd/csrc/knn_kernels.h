@@ -5,7 +5,7 @@
 //   ent[]  16-byte records {x, y, z, rank} (float, float, float, int32 bit pattern).  The
 //          entries of list L_i are contiguous and ascending in rank (Sec. 3); whole lists
 //          are placed in the Morton order of their owner points.  The array is padded with
-//          kEntPad records so a lane may load a 4-record chunk past the end of a list.
+//          kEntPad records so a 16-lane chunk may reach 15 records past the end of a list.
 //   lst[r] 64-bit descriptor: start index of L_r in ent (low 32 bits) | length (high 32).
 // Each list entry carries its point's coordinates, so scanning a list is one contiguous
 // read and no second gather is needed to evaluate the distance.
@@ -15,7 +15,7 @@
 
 namespace mknn {
 
-constexpr int kEntPad = 4;
+constexpr int kEntPad = 16;
 constexpr int32_t kEmpty = 0x7fffffff;   // rank of an empty candidate slot
 
 struct QueryArgs {

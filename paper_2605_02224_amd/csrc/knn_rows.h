@@ -139,16 +139,16 @@ struct RowWalker {
     const bool active = phase != kRowIdle;
     const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
     const uint32_t e = base + (uint32_t)l;
-    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (active && e < len) c = ent[st + e];
+    // every lane loads, without a branch: a chunk never reaches more than 15 records past
+    // the end of a list (or of the arena's used part), which the arena's padding covers;
+    // records past the list are ignored
+    const float4 c = ent[st + e];
     const int32_t r = __float_as_int(c.w);
     const bool valid = active && e < len && r < m;
-    double dd = INFINITY;
-    if (valid) {
-      const double dx = (double)qx - (double)c.x, dy = (double)qy - (double)c.y,
-                   dz = (double)qz - (double)c.z;
-      dd = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-    }
+    const double dx = (double)qx - (double)c.x, dy = (double)qy - (double)c.y,
+                 dz = (double)qz - (double)c.z;
+    const double dv = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    const double dd = valid ? dv : INFINITY;
     const uint32_t vmask = row_bits(__ballot(valid), g);
     const uint32_t jm = row_bits(__ballot(valid && phase == kRowDescent && dd < dcur), g);
     const int j = jm ? __ffs(jm) - 1 : 0;
