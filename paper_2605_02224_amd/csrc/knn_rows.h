@@ -136,7 +136,11 @@ struct RowWalker {
   // come in separately so that callers can keep them in scalar registers.
   __device__ __forceinline__ void step(const QueryArgs &a, const float4 *ent,
                                        const uint64_t *lst, int merge_min, int l, int g) {
-    const bool active = phase != kRowIdle;
+    // Descent steps first: while any row of the wavefront is in its descent, the rows in
+    // their expansion wait.  Descent chunks are cheap (no candidate step for k <= 16), and
+    // the candidate step then runs when all rows have candidates to offer.
+    const bool any_descent = __ballot(phase == kRowDescent) != 0;
+    const bool active = any_descent ? phase == kRowDescent : phase != kRowIdle;
     const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
     const uint32_t e = base + (uint32_t)l;
     // every lane loads, without a branch: a chunk never reaches more than 15 records past
