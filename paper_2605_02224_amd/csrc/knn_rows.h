@@ -145,8 +145,10 @@ struct RowWalker {
     const uint32_t e = base + (uint32_t)l;
     // every lane loads, without a branch: a chunk never reaches more than 15 records past
     // the end of a list (or of the arena's used part), which the arena's padding covers;
-    // records past the list are ignored
-    const float4 c = ent[st + e];
+    // records past the list are ignored.  Rows not stepping read record 0: an idle row's
+    // descriptor may belong to another request's cloud (batched form), whose arena can be
+    // larger than this one.
+    const float4 c = ent[active ? st + e : 0u];
     const int32_t r = __float_as_int(c.w);
     const bool valid = active && e < len && r < m;
     const double dx = (double)qx - (double)c.x, dy = (double)qy - (double)c.y,

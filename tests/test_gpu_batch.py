@@ -147,3 +147,30 @@ def test_256_clouds_paper_scale_sampled(env):
                             rD[:, k])
     assert exc <= 3
     plan.close()
+
+
+def test_waves_moving_between_clouds_of_very_different_size(env):
+    """Wavefronts take tiles of one request after another; rows idle at a switch still hold
+    the descriptor of the previous request's cloud, which must never be used to address the
+    next cloud's (much smaller) arena.  Tiny clouds interleaved with a large one, small
+    tiles, and every result checked against the oracle."""
+    torch, oracle, A, W, clouds = env
+    rng = np.random.default_rng(41)
+    big = W.random_cloud(120000, seed=42, shape="torus").by_rank
+    parts = [(big, A.Cloud.build(big).upload())]
+    for i in range(12):
+        P = W.random_cloud(int(rng.integers(8, 40)), seed=60 + i, shape=W.SHAPES[i % 3]).by_rank
+        parts.append((P, A.Cloud.build(P).upload()))
+    items, host = [], []
+    for rep in range(3):
+        for P, cl in parts:
+            nq = 3000 if P.shape[0] > 1000 else 64
+            k = int(rng.choice([4, 16, 24]))
+            Q = W.uniform_in_box(rng, nq, *W.bbox_expanded(P, 1.1))
+            items.append((cl, torch.from_numpy(Q).cuda(), k, 0))
+            host.append((P, Q, k, 0))
+    items = A.alloc_outputs(items)
+    plan = A.BatchPlan(len(items), 20000, tile_queries=4, sort=True, graph=False)
+    plan.run(items)
+    torch.cuda.synchronize()
+    assert _check(env, items, host) <= 3
