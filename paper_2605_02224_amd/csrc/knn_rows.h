@@ -134,12 +134,16 @@ struct RowWalker {
   // One chunk for every row of the wavefront (call from uniform control flow).  A row that
   // completes its query writes the result (through `a`) and becomes idle.  The list arrays
   // come in separately so that callers can keep them in scalar registers.
+  //
+  // descent_first (uniform): while any row of the wavefront is in its descent, the rows in
+  // their expansion wait.  Descent chunks are cheap (no candidate step for k <= 16), and the
+  // candidate step then runs when all rows have candidates to offer.  Worth it only when
+  // every row holds one query for the whole launch; rows refilled with new queries would
+  // stall the others' expansions at every refill.
   __device__ __forceinline__ void step(const QueryArgs &a, const float4 *ent,
-                                       const uint64_t *lst, int merge_min, int l, int g) {
-    // Descent steps first: while any row of the wavefront is in its descent, the rows in
-    // their expansion wait.  Descent chunks are cheap (no candidate step for k <= 16), and
-    // the candidate step then runs when all rows have candidates to offer.
-    const bool any_descent = __ballot(phase == kRowDescent) != 0;
+                                       const uint64_t *lst, int merge_min, int l, int g,
+                                       bool descent_first) {
+    const bool any_descent = descent_first && __ballot(phase == kRowDescent) != 0;
     const bool active = any_descent ? phase == kRowDescent : phase != kRowIdle;
     const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
     const uint32_t e = base + (uint32_t)l;
@@ -238,7 +242,7 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
       next += 4;
     }
     if (__ballot(w.phase != kRowIdle) == 0) break;
-    w.step(a, a.ent, a.lst, a.merge_min, l, g);
+    w.step(a, a.ent, a.lst, a.merge_min, l, g, per_wave == 4);
   }
 }
 
