@@ -69,6 +69,8 @@ struct RowWalker {
   // site is answered at once (empty row) and leaves the row idle.
   __device__ __forceinline__ void begin(const QueryArgs &a, int64_t s, int l) {
     phase = kRowIdle;
+    dsc = 0;   // an idle row reads record 0 of whatever arena the wavefront is on
+    base = 0;
     if (a.qs) {
       const float4 v = a.qs[s];
       qx = v.x;
@@ -129,30 +131,31 @@ struct RowWalker {
       }
     }
     phase = kRowIdle;
+    dsc = 0;
+    base = 0;
   }
 
   // One chunk for every row of the wavefront (call from uniform control flow).  A row that
   // completes its query writes the result (through `a`) and becomes idle.  The list arrays
   // come in separately so that callers can keep them in scalar registers.
   //
-  // descent_first (uniform): while any row of the wavefront is in its descent, the rows in
-  // their expansion wait.  Descent chunks are cheap (no candidate step for k <= 16), and the
+  // DESCENT_FIRST: while any row of the wavefront is in its descent, the rows in their
+  // expansion wait.  Descent chunks are cheap (no candidate step for k <= 16), and the
   // candidate step then runs when all rows have candidates to offer.  Worth it only when
   // every row holds one query for the whole launch; rows refilled with new queries would
   // stall the others' expansions at every refill.
+  template <bool DESCENT_FIRST>
   __device__ __forceinline__ void step(const QueryArgs &a, const float4 *ent,
-                                       const uint64_t *lst, int merge_min, int l, int g,
-                                       bool descent_first) {
-    const bool any_descent = descent_first && __ballot(phase == kRowDescent) != 0;
+                                       const uint64_t *lst, int merge_min, int l, int g) {
+    const bool any_descent = DESCENT_FIRST && __ballot(phase == kRowDescent) != 0;
     const bool active = any_descent ? phase == kRowDescent : phase != kRowIdle;
     const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
     const uint32_t e = base + (uint32_t)l;
     // every lane loads, without a branch: a chunk never reaches more than 15 records past
     // the end of a list (or of the arena's used part), which the arena's padding covers;
-    // records past the list are ignored.  Rows not stepping read record 0: an idle row's
-    // descriptor may belong to another request's cloud (batched form), whose arena can be
-    // larger than this one.
-    const float4 c = ent[active ? st + e : 0u];
+    // records past the list are ignored.  An idle row's descriptor is 0 (begin and finish
+    // reset it), so it never points into another request's arena in the batched form.
+    const float4 c = ent[st + e];
     const int32_t r = __float_as_int(c.w);
     const bool valid = active && e < len && r < m;
     const double dx = (double)qx - (double)c.x, dy = (double)qy - (double)c.y,
@@ -224,7 +227,7 @@ struct RowWalker {
 
 // Plain launch: a wavefront owns `per_wave` consecutive sorted queries; row g takes
 // positions g, g + 4, g + 8, ... of them, so the rows stay on Morton neighbours.
-template <int S, bool EXACTK>
+template <int S, bool EXACTK, bool DESCENT_FIRST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
 void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
   const int lane = threadIdx.x & 63;
@@ -242,7 +245,7 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
       next += 4;
     }
     if (__ballot(w.phase != kRowIdle) == 0) break;
-    w.step(a, a.ent, a.lst, a.merge_min, l, g, per_wave == 4);
+    w.template step<DESCENT_FIRST>(a, a.ent, a.lst, a.merge_min, l, g);
   }
 }
 

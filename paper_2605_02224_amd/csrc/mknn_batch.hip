@@ -235,7 +235,7 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
       if (exhausted && preq < 0) return;
       continue;
     }
-    w.step(reqs[req], ent, lst, merge_min, l, g, false);
+    w.template step<false>(reqs[req], ent, lst, merge_min, l, g);
   }
 }
 
