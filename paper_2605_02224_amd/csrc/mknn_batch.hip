@@ -171,10 +171,12 @@ __device__ __forceinline__ void claim_tile(const BatchHeader *h, const BatchEntr
   }
 }
 
-// Row-scheduled batched kernel.  Every wavefront claims tiles on its own and its four rows
-// (knn_rows.h) take the tile's queries one at a time as they become idle, so rows never
-// wait for each other at tile boundaries.  A wavefront serves one request at a time: a
-// claimed tile of another request is held until every row has finished the current one.
+// Row-scheduled batched kernel.  Every wavefront claims tiles on its own; its four rows
+// (knn_rows.h) take four queries of the tile at once and run them to the end together,
+// descent steps first, as a wavefront of the plain launch does (refilling a row as soon as
+// it is idle would stall the other rows' expansions behind its new descent).  A wavefront
+// serves one request at a time: a claimed tile of another request is held until every row
+// has finished the current one.
 template <int S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
 void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const BatchEntry *ents,
@@ -192,10 +194,12 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
   RowWalker<S, false> w;
   w.N.init();
   for (;;) {
-    // ---- give idle rows queries of the current tile, claiming tiles as needed
+    // ---- once every row is idle, give the rows the next queries of the current tile
+    //      (claiming tiles as needed); the four rows then run their queries to the end
+    //      together, descent steps first, as a wavefront of the plain launch does
     for (;;) {
+      if (__ballot(w.phase != kRowIdle) != 0) break;
       const uint64_t idle = __ballot(w.phase == kRowIdle && l == 0);
-      if (idle == 0) break;
       if (tnext < tend) {
         const int rank = __popcll(idle & ((1ull << (16 * g)) - 1));
         const int64_t s = tnext + rank;
@@ -235,7 +239,7 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
       if (exhausted && preq < 0) return;
       continue;
     }
-    w.template step<false>(reqs[req], ent, lst, merge_min, l, g);
+    w.template step<true>(reqs[req], ent, lst, merge_min, l, g);
   }
 }
 
