@@ -1,18 +1,18 @@
-// Device half of the C ABI: residency of successor lists in HBM and the query kernels.
+// Device half of the C ABI: residency of successor lists in HBM, query batch preparation,
+// the query kernels and their launch configuration (with the autotuner's table), list
+// deltas for deletion and insertion, and the plane fit.
 //
-// Per query (one lane), the kernel runs the 1-NN descent of Alg. 1 and the k-expansion of
-// Alg. 2 with the prefix bound of Sec. 4.2:
-//   descent:  cur = head; scan L_cur in order; at the first entry strictly closer than cur,
-//             jump to it and restart on its list; stop at the end of a list or at the first
-//             rank >= m (lists are ascending, Sec. 3).  The last site reached is the 1-NN.
-//   seeding:  every examined entry, in particular every transition site, is inserted into
-//             the candidate list N (capacity k, sorted by (D, rank)).  Inserting more true
-//             sites than Alg. 1 does never changes the result, and it makes the final,
-//             completely scanned list of the descent serve as Alg. 2's first iteration.
-//   expansion: for i = 2..k-1 (1-based) scan L_{N[i]} inserting each entry not in N.
-// N lives in registers: a fully unrolled sorted array of K (D, rank) pairs, so no slot is
-// ever addressed dynamically.  Distances are evaluated in float64 exactly as the brute-force
-// definition (each operation rounded, no FMA), so ties resolve identically.
+// Three kernel families compute the same rows (the 1-NN descent of Alg. 1, the k-expansion
+// of Alg. 2, the prefix bound of Sec. 4.2), with identical float64 keys (D, rank):
+//   lane  (knn_lane_kernel, below): one query per lane, N a register-resident sorted array;
+//   group (knn_group.h): 16 lanes per query, the four rows of a wavefront in lockstep phases
+//         (it also carries the work-counting variant);
+//   rows  (knn_rows.h): 16 lanes per query, rows scheduled independently -- the default.
+// In the lane kernel every examined entry, transition sites included, is offered to N;
+// offering more true sites than Alg. 1 does never changes the result, and it lets the
+// final, completely scanned list of the descent serve as Alg. 2's first iteration.
+// Distances are evaluated in float64 exactly as the brute-force definition (each operation
+// rounded, no FMA), so ties resolve identically.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,11 +21,10 @@
 #include <cmath>
 #include <cstring>
 #include <new>
-#include <string>
 #include <map>
 #include <mutex>
+#include <string>
 #include <vector>
-#include <map>
 
 #include "device_common.h"
 #include "knn_group.h"
@@ -33,9 +32,6 @@
 #include "planefit.h"
 
 namespace mknn {
-
-
-
 
 template <int K>
 struct TopK {
@@ -212,10 +208,6 @@ constexpr int kMortonBits = 16;
 constexpr int kMortonBins = 1 << kMortonBits;
 constexpr int64_t kSortMinQueries = 8192;
 
-
-
-
-
 __global__ __launch_bounds__(256) void morton_hist_kernel(const float *q, int64_t nq, BoxArgs b,
                                                           uint32_t *hist) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -263,7 +255,6 @@ __global__ __launch_bounds__(256) void morton_scatter_kernel(const float *q, int
 // ---------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------
-
 
 static void free_device(mknn_cloud *c) {
   if (c->d_ent) (void)hipFree(c->d_ent);
@@ -525,7 +516,6 @@ hipError_t timing_mark(hipStream_t s, bool start) {
   }
   return hipEventRecord(g_events[g_events_used++].second, s);
 }
-
 
 // ---------------------------------------------------------------------------------------
 // Launch configuration and the autotuner's table
