@@ -176,9 +176,10 @@ __device__ __forceinline__ void claim_tile(const BatchHeader *h, const BatchEntr
 // descent steps first, as a wavefront of the plain launch does (refilling a row as soon as
 // it is idle would stall the other rows' expansions behind its new descent).  A wavefront
 // serves one request at a time: a claimed tile of another request is held until every row
-// has finished the current one.
+// has finished the current one.  For k <= 16 the tile and request bookkeeping would spill
+// about 18 registers at 8 waves per SIMD; 7 waves with almost no spills measure faster.
 template <int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 7 : 1, 8)))
 void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const BatchEntry *ents,
                            uint32_t *counters, int cls) {
   const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4;
