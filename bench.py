@@ -33,11 +33,15 @@ def log(msg: str) -> None:
 
 
 def csrc_digest() -> str:
-    """Hash of the kernel sources, to tell whether stored counter readings still apply."""
+    """Hash of the sources the kernels are compiled from (the HIP translation units and
+    every header), to tell whether stored counter readings still apply.  Host-only C++
+    (construction, deletion, insertion) does not enter."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2605_02224_amd", "csrc", "*"))):
+    csrc = os.path.join(ROOT, "paper_2605_02224_amd", "csrc")
+    files = glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))
+    for f in sorted(files):
         h.update(os.path.basename(f).encode())
         h.update(open(f, "rb").read())
     return h.hexdigest()

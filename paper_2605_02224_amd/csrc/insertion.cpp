@@ -116,13 +116,12 @@ mknn_status insert_points_host(mknn_cloud *c, const float *xyz, int64_t count,
       c->live.push_back(1);
       c->order.push_back((int32_t)r);
       ++c->nlive;
+      for (int k = 0; k < 3; ++k) {   // the bounding box covers every point inserted
+        c->lo[k] = std::min(c->lo[k], c->xyz[3 * (int64_t)r + k]);
+        c->hi[k] = std::max(c->hi[k], c->xyz[3 * (int64_t)r + k]);
+      }
       c->n = r + 1;
     }
-    for (int64_t r = n0; r < n1; ++r)
-      for (int k = 0; k < 3; ++k) {
-        c->lo[k] = std::min(c->lo[k], c->xyz[3 * r + k]);
-        c->hi[k] = std::max(c->hi[k], c->xyz[3 * r + k]);
-      }
     c->csr_dirty = true;
   } catch (const std::bad_alloc &) {
     c->ins.reset();
