@@ -489,7 +489,8 @@ def bench_dynamic(args) -> int:
 
 def bench_plane(args) -> int:
     """k-NN with a plane fit per row (the scan convergence statistic): the headline cloud
-    (torus, 1M points), 1M probes on the surface (noise 1e-3), k=20, m=n; against the
+    (torus, 1M points), 1M probes near the surface (torus samples jittered by 1e-2), k=20,
+    m=n; against the
     same queries without the fit."""
     import torch
     from paper_2605_02224_amd import workloads as W
