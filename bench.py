@@ -490,8 +490,7 @@ def bench_dynamic(args) -> int:
 def bench_plane(args) -> int:
     """k-NN with a plane fit per row (the scan convergence statistic): the headline cloud
     (torus, 1M points), 1M probes near the surface (torus samples jittered by 1e-2), k=20,
-    m=n; against the
-    same queries without the fit."""
+    m=n; against the same queries without the fit."""
     import torch
     from paper_2605_02224_amd import workloads as W
     from paper_2605_02224_amd.api import Cloud
