@@ -294,8 +294,9 @@ mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void
  * n, n+1, ...; their caller ids are their ranks.  Afterwards the successor lists equal those
  * of the live points plus the new ones inserted in rank order: each new rank is appended to
  * the lists of its Delaunay neighbours among the live points (and earlier new points), and
- * its own list starts empty.  The triangulation of the live points is kept in the cloud for
- * this (about 40 B per point); a deletion drops it and the next insertion builds it again.
+ * its own list starts empty.  The triangulation of the live points is built at the first
+ * insertion and kept in the cloud (a few hundred bytes per point); deletions remove their
+ * points from it (if one cannot, it is dropped and the next insertion builds it again).
  * If the cloud is uploaded, the changed lists and the new descriptors are applied on
  * `stream` as for deletions (copy on write; a re-pack when the slack runs out); the call
  * synchronises `stream` before returning.
