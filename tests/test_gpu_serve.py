@@ -185,7 +185,8 @@ def test_errors_and_empty_requests(env):
     srv.close()
 
 
-def test_insertions_and_deletions_between_batches(env):
+@pytest.mark.parametrize("plain", [False, True])
+def test_insertions_and_deletions_between_batches(env, plain):
     """Insertion batches go through the same ordered update path as deletions: every
     request sees exactly the update batches submitted before it on its cloud, and equals
     the oracle on the points present after those (new points take the next ranks)."""
@@ -199,7 +200,7 @@ def test_insertions_and_deletions_between_batches(env):
     states = [[(n, np.concatenate([np.ones(n, np.uint8), np.zeros(P.shape[0] - n, np.uint8)]))]
               for (P, _), n in zip(clouds, n0)]
     rng = np.random.default_rng(12)
-    srv = A.Server(pool_queries=1 << 15, nstreams=2, max_wave_requests=16)
+    srv = A.Server(pool_queries=1 << 15, nstreams=2, max_wave_requests=16, plain=plain)
     log = []
     for step in range(60):
         c = int(rng.integers(2))
