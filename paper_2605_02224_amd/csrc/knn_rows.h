@@ -17,6 +17,8 @@
 //               iteration, exactly as in the group kernel).
 //   expansion : every entry of the list of N's slot `it` is offered (it = 1 .. k-2).
 #pragma once
+#include <type_traits>
+
 #include "knn_group.h"
 
 namespace mknn {
@@ -50,10 +52,13 @@ __device__ __forceinline__ double *ring_d(const QueryArgs &) { return g_ring_d +
 __device__ __forceinline__ int32_t *ring_r(const QueryArgs &) { return g_ring_r + 16 * (threadIdx.x >> 4); }
 
 // The state of one row's current query.  Row-uniform values, held by every lane of the row.
-template <int S, bool EXACTK>
+// WIDE_Q: hold the query in float64 (widened once rather than at every chunk), where the
+// registers allow it.
+template <int S, bool EXACTK, bool WIDE_Q = (S == 1)>
 struct RowWalker {
   RowTopK<S, EXACTK> N;
-  float qx = 0, qy = 0, qz = 0;     // the query, widened where it is used (registers are tight)
+  using QCoord = typename std::conditional<WIDE_Q, double, float>::type;
+  QCoord qx = 0, qy = 0, qz = 0;   // the query
   double dcur = 0;
   int32_t qi = 0;                  // caller index of the query (nq < 2^31)
   int32_t k = 0, m = 0, cur = 0, it = 0;

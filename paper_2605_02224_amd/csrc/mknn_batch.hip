@@ -192,7 +192,7 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
   const float4 *ent = nullptr;     // the current request's lists, in scalar registers
   const uint64_t *lst = nullptr;
   int merge_min = 1;
-  RowWalker<S, false> w;
+  RowWalker<S, false, false> w;   // the query in float32: the bookkeeping needs the registers
   w.N.init();
   for (;;) {
     // ---- once every row is idle, give the rows the next queries of the current tile
