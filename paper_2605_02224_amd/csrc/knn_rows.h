@@ -88,8 +88,10 @@ struct RowWalker {
       qy = a.q[3 * s + 1];
       qz = a.q[3 * s + 2];
     }
-    k = a.kq ? a.kq[qi] : a.k;
-    int64_t mm = a.mq ? (int64_t)a.mq[qi] : (int64_t)a.m;
+    // EXACTK launches are plain calls: one k (= 16 S) and one m for the batch, no per-query
+    // arrays (so their pointers need no registers)
+    k = !EXACTK && a.kq ? a.kq[qi] : a.k;
+    int64_t mm = !EXACTK && a.mq ? (int64_t)a.mq[qi] : (int64_t)a.m;
     if (mm > a.n) mm = a.n;
     m = (int32_t)mm;
     if (k < 1 || k > 16 * S || m < 1) return;
@@ -125,7 +127,7 @@ struct RowWalker {
   }
 
   __device__ __forceinline__ void finish(const QueryArgs &a, int l) {
-    const int64_t row = a.row_off ? a.row_off[qi] : qi * (int64_t)a.k;
+    const int64_t row = !EXACTK && a.row_off ? a.row_off[qi] : qi * (int64_t)a.k;
 #pragma unroll
     for (int t = 0; t < S; ++t) {
       const int j = 16 * t + l;
