@@ -53,8 +53,9 @@ __device__ __forceinline__ int32_t *ring_r(const QueryArgs &) { return g_ring_r 
 
 // The state of one row's current query.  Row-uniform values, held by every lane of the row.
 // WIDE_Q: hold the query in float64 (widened once rather than at every chunk), where the
-// registers allow it.
-template <int S, bool EXACTK, bool WIDE_Q = (S == 1)>
+// registers allow it.  UNIFORM: one k and one m for the whole launch (or, batched, for the
+// request the wavefront is on) -- no per-query arrays, and k and m stay scalars.
+template <int S, bool EXACTK, bool WIDE_Q = (S == 1), bool UNIFORM = EXACTK>
 struct RowWalker {
   RowTopK<S, EXACTK> N;
   using QCoord = typename std::conditional<WIDE_Q, double, float>::type;
@@ -88,16 +89,14 @@ struct RowWalker {
       qy = a.q[3 * s + 1];
       qz = a.q[3 * s + 2];
     }
-    // EXACTK launches are plain calls: one k (= 16 S) and one m for the batch, no per-query
-    // arrays (so their pointers need no registers)
-    k = !EXACTK && a.kq ? a.kq[qi] : a.k;
-    int64_t mm = !EXACTK && a.mq ? (int64_t)a.mq[qi] : (int64_t)a.m;
+    k = !UNIFORM && a.kq ? a.kq[qi] : a.k;
+    int64_t mm = !UNIFORM && a.mq ? (int64_t)a.mq[qi] : (int64_t)a.m;
     if (mm > a.n) mm = a.n;
     m = (int32_t)mm;
     if (k < 1 || k > 16 * S || m < 1) return;
     N.init();
     if (a.head >= m) {
-      finish(a, l);
+      finish(a, l, k);
       return;
     }
     cur = a.head;
@@ -126,8 +125,10 @@ struct RowWalker {
     phase = kRowDescent;
   }
 
-  __device__ __forceinline__ void finish(const QueryArgs &a, int l) {
-    const int64_t row = !EXACTK && a.row_off ? a.row_off[qi] : qi * (int64_t)a.k;
+  // uk: the launch's (request's) k when UNIFORM, held by the caller in a scalar register
+  __device__ __forceinline__ void finish(const QueryArgs &a, int l, int32_t uk) {
+    const int32_t k = EXACTK ? 16 * S : (UNIFORM ? uk : this->k);
+    const int64_t row = !UNIFORM && a.row_off ? a.row_off[qi] : qi * (int64_t)k;
 #pragma unroll
     for (int t = 0; t < S; ++t) {
       const int j = 16 * t + l;
@@ -152,8 +153,13 @@ struct RowWalker {
   // every row holds one query for the whole launch; rows refilled with new queries would
   // stall the others' expansions at every refill.
   template <bool DESCENT_FIRST>
+  // uk, um (UNIFORM): the launch's (request's) k and m clamped to n, in scalar registers.
   __device__ __forceinline__ void step(const QueryArgs &a, const float4 *ent,
-                                       const uint64_t *lst, int merge_min, int l, int g) {
+                                       const uint64_t *lst, int merge_min, int l, int g,
+                                       int32_t uk, int32_t um) {
+    // uniform launches: k and m are the same for every row, so they stay scalars
+    const int32_t k = EXACTK ? 16 * S : (UNIFORM ? uk : this->k);
+    const int32_t m = UNIFORM ? um : this->m;
     const bool any_descent = DESCENT_FIRST && __ballot(phase == kRowDescent) != 0;
     const bool active = any_descent ? phase == kRowDescent : phase != kRowIdle;
     const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
@@ -203,7 +209,7 @@ struct RowWalker {
       N.r[0] = l < have ? ring_r(a)[src] : kEmpty;
       N.refresh_threshold(k);
       if (k == 1) {
-        finish(a, l);
+        finish(a, l, k);
       } else {
         phase = kRowExpand;
         it = 0;
@@ -225,7 +231,7 @@ struct RowWalker {
           dsc = lst[pr];
           base = 0;
         } else {
-          finish(a, l);
+          finish(a, l, k);
         }
       }
     }
@@ -234,7 +240,7 @@ struct RowWalker {
 
 // Plain launch: a wavefront owns `per_wave` consecutive sorted queries; row g takes
 // positions g, g + 4, g + 8, ... of them, so the rows stay on Morton neighbours.
-template <int S, bool EXACTK, bool DESCENT_FIRST>
+template <int S, bool EXACTK, bool DESCENT_FIRST, bool UNIFORM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
 void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
   const int lane = threadIdx.x & 63;
@@ -243,7 +249,7 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
       ((int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t begin = wave * per_wave;
   const int64_t end = begin + per_wave < a.nq ? begin + per_wave : a.nq;
-  RowWalker<S, EXACTK> w;
+  RowWalker<S, EXACTK, (S == 1), UNIFORM> w;
   w.N.init();
   int64_t next = begin + g;
   for (;;) {
@@ -252,7 +258,8 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
       next += 4;
     }
     if (__ballot(w.phase != kRowIdle) == 0) break;
-    w.template step<DESCENT_FIRST>(a, a.ent, a.lst, a.merge_min, l, g);
+    w.template step<DESCENT_FIRST>(a, a.ent, a.lst, a.merge_min, l, g, a.k,
+                                   (int32_t)(a.m < a.n ? (int64_t)a.m : a.n));
   }
 }
 

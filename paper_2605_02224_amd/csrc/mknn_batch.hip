@@ -192,7 +192,10 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
   const float4 *ent = nullptr;     // the current request's lists, in scalar registers
   const uint64_t *lst = nullptr;
   int merge_min = 1;
-  RowWalker<S, false, false> w;   // the query in float32: the bookkeeping needs the registers
+  // the query in float32 (the bookkeeping needs the registers); a request has one k and one
+  // m, held below in scalar registers with its lists
+  RowWalker<S, false, false, true> w;
+  int32_t rk = 0, rm = 0;
   w.N.init();
   for (;;) {
     // ---- once every row is idle, give the rows the next queries of the current tile
@@ -218,6 +221,8 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
         ent = reqs[req].ent;
         lst = reqs[req].lst;
         merge_min = reqs[req].merge_min;
+        rk = reqs[req].k;
+        rm = (int32_t)(reqs[req].m < reqs[req].n ? (int64_t)reqs[req].m : reqs[req].n);
         continue;
       }
       if (exhausted) break;
@@ -240,7 +245,7 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
       if (exhausted && preq < 0) return;
       continue;
     }
-    w.template step<true>(reqs[req], ent, lst, merge_min, l, g);
+    w.template step<true>(reqs[req], ent, lst, merge_min, l, g, rk, rm);
   }
 }
 

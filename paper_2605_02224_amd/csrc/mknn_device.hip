@@ -636,11 +636,20 @@ template <int S, bool EXACTK>
 static hipError_t launch_rows(const QueryArgs &a, int32_t per_wave, hipStream_t s) {
   const int64_t waves = (a.nq + per_wave - 1) / per_wave;
   const uint32_t blocks = (uint32_t)((waves + 3) / 4);
-  // descent steps first only when every row keeps its one query for the whole launch
-  if (per_wave == 4)
-    hipLaunchKernelGGL((knn_rows_kernel<S, EXACTK, true>), dim3(blocks), dim3(256), 0, s, a, per_wave);
-  else
-    hipLaunchKernelGGL((knn_rows_kernel<S, EXACTK, false>), dim3(blocks), dim3(256), 0, s, a, per_wave);
+  // descent steps first only when every row keeps its one query for the whole launch;
+  // k and m as scalars when there are no per-query arrays (always so for exact k)
+  const bool uniform = !a.kq && !a.mq;
+  if (EXACTK || uniform) {
+    if (per_wave == 4)
+      hipLaunchKernelGGL((knn_rows_kernel<S, EXACTK, true, true>), dim3(blocks), dim3(256), 0, s, a, per_wave);
+    else
+      hipLaunchKernelGGL((knn_rows_kernel<S, EXACTK, false, true>), dim3(blocks), dim3(256), 0, s, a, per_wave);
+  } else if constexpr (!EXACTK) {
+    if (per_wave == 4)
+      hipLaunchKernelGGL((knn_rows_kernel<S, false, true, false>), dim3(blocks), dim3(256), 0, s, a, per_wave);
+    else
+      hipLaunchKernelGGL((knn_rows_kernel<S, false, false, false>), dim3(blocks), dim3(256), 0, s, a, per_wave);
+  }
   return hipGetLastError();
 }
 
