@@ -251,15 +251,22 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
   const int64_t end = begin + per_wave < a.nq ? begin + per_wave : a.nq;
   RowWalker<S, EXACTK, (S == 1), UNIFORM> w;
   w.N.init();
-  int64_t next = begin + g;
-  for (;;) {
-    while (w.phase == kRowIdle && next < end) {
-      w.begin(a, next, l);
-      next += 4;
+  const int32_t m = (int32_t)(a.m < a.n ? (int64_t)a.m : a.n);
+  if constexpr (DESCENT_FIRST) {
+    // 4 queries per wavefront: each row takes its one query and runs it to the end
+    if (begin + g < end) w.begin(a, begin + g, l);
+    while (__ballot(w.phase != kRowIdle) != 0)
+      w.template step<true>(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
+  } else {
+    int64_t next = begin + g;
+    for (;;) {
+      while (w.phase == kRowIdle && next < end) {
+        w.begin(a, next, l);
+        next += 4;
+      }
+      if (__ballot(w.phase != kRowIdle) == 0) break;
+      w.template step<false>(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
     }
-    if (__ballot(w.phase != kRowIdle) == 0) break;
-    w.template step<DESCENT_FIRST>(a, a.ent, a.lst, a.merge_min, l, g, a.k,
-                                   (int32_t)(a.m < a.n ? (int64_t)a.m : a.n));
   }
 }
 
