@@ -162,10 +162,19 @@ struct RowTopK {
   // Insert the row-uniform candidate (cd, cr) unless already present.  Only called for a
   // candidate that beats the current k-th key.  Returns 1 if inserted.
   __device__ __forceinline__ int insert(double cd, int32_t cr, int l, int g, int k) {
+    if (!place(cd, cr, l, g)) return 0;
+    refresh_threshold(k);
+    return 1;
+  }
+
+  // Shift the row-uniform candidate (cd, cr) into the sorted slots unless the row already
+  // holds its rank; the threshold is left as it was.  A candidate that ranks past the last
+  // slot changes nothing.  Returns false if the rank was held.
+  __device__ __forceinline__ bool place(double cd, int32_t cr, int l, int g) {
     bool has = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) has |= (r[s] == cr);
-    if (row_bits(__ballot(has), g)) return 0;
+    if (row_bits(__ballot(has), g)) return false;
     int pos = 0;
 #pragma unroll
     for (int s = 0; s < S; ++s)
@@ -193,13 +202,7 @@ struct RowTopK {
       wd = last_d;
       wr = last_r;
     }
-    if (EXACTK) {
-      thr_d = dpp_f64<kDppRowBcast15>(d[S - 1], d[S - 1]);
-      thr_r = dpp_i32<kDppRowBcast15>(r[S - 1], r[S - 1]);
-    } else {
-      slot(k - 1, thr_d, thr_r);
-    }
-    return 1;
+    return true;
   }
 
   // k <= 16 (one slot per lane): merge every lane's candidate with `better` set at once.
@@ -299,6 +302,21 @@ struct RowTopK {
       slot(k - 1, thr_d, thr_r);
     }
     return better ? 1 : 0;
+  }
+
+  // k > 16 (S slots per lane): insert the flagged candidates of each row one by one, in
+  // lane order, and refresh the threshold once at the end (slot k-1 takes a cross-lane read
+  // when k < 16 S).  A candidate is not tested against the threshold again after each
+  // insertion: one that no longer ranks lands past the last slot and changes nothing.
+  __device__ __forceinline__ void insert_each(bool cand, double dd, int32_t rr, int l, int g,
+                                              int k) {
+    uint32_t mask = row_bits(__ballot(cand), g);   // uniform in the row
+    while (mask) {
+      const int j = __ffs(mask) - 1;
+      mask &= mask - 1u;
+      place(__shfl(dd, j, 16), __shfl(rr, j, 16), l, g);
+    }
+    refresh_threshold(k);
   }
 
   // Offer every lane's (dd, rr) with `better` set; updates the threshold as it goes.

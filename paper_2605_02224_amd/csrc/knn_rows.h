@@ -38,7 +38,10 @@ __device__ __forceinline__ void offer_all(RowTopK<S, EXACTK> &N, bool cand, doub
       N.mergeS(cand, dd, rr, l, g, k);
     return;
   }
-  N.insert_all(cand, dd, rr, l, g, k);
+  if constexpr (S == 1)
+    N.insert_all(cand, dd, rr, l, g, k);
+  else
+    N.insert_each(cand, dd, rr, l, g, k);
 }
 
 constexpr int32_t kRowDescent = 0, kRowExpand = 1, kRowIdle = 2;
