@@ -69,6 +69,9 @@ struct RowWalker {
   int32_t phase = kRowIdle;
   uint64_t dsc = 0;
   uint32_t base = 0;
+  // key of the confirmed neighbour whose list an expansion row scans (slot `it` of N)
+  double od = 0;
+  int32_t orr = 0;
   // k <= 16: the transition sites of the descent (Alg. 1) go to a ring of 16 in LDS (entry
   // t % 16 for the t-th); each is strictly closer than the one before, so the last 16 are
   // the only ones that can rank among the k nearest and the ring holds them sorted.
@@ -184,11 +187,17 @@ struct RowWalker {
     // k <= 16: descent rows offer nothing (their transition sites go to the ring and the
     // final list is scanned again as the first expansion).  Otherwise a jumping row offers
     // its transition site only (Alg. 1) and the other rows every entry.
+    // An expansion row scans the list of slot `it`, and slots 0 .. it are final by then
+    // (Theorem 1: each further neighbour is a transition site or in the list of a nearer
+    // one, all of whose lists came first), so an entry whose key is not above slot it's
+    // is already in N and is not offered.
     bool cand;
     if constexpr (S == 1)
-      cand = valid && phase == kRowExpand && key_less(dd, r, N.thr_d, N.thr_r);
+      cand = valid && phase == kRowExpand && key_less(od, orr, dd, r) &&
+             key_less(dd, r, N.thr_d, N.thr_r);
     else
-      cand = (jm ? l == j : valid) && key_less(dd, r, N.thr_d, N.thr_r);
+      cand = (jm ? l == j : valid) && (phase != kRowExpand || key_less(od, orr, dd, r)) &&
+             key_less(dd, r, N.thr_d, N.thr_r);
     offer_all(N, cand, dd, r, l, g, k, merge_min);
     if (jm) {
       dcur = __shfl(dd, j, 16);
@@ -211,6 +220,8 @@ struct RowWalker {
       N.d[0] = l < have ? ring_d(a)[src] : INFINITY;
       N.r[0] = l < have ? ring_r(a)[src] : kEmpty;
       N.refresh_threshold(k);
+      od = dcur;   // slot 0: the nearest site, p_cur
+      orr = cur;
       if (k == 1) {
         finish(a, l, k);
       } else {
@@ -226,11 +237,11 @@ struct RowWalker {
         it = phase == kRowDescent ? 1 : it + 1;
         phase = kRowExpand;
         int32_t pr = kEmpty;
-        if (it < k - 1) {
-          double pd;
-          N.slot(it, pd, pr);
-        }
+        double pd = 0;
+        if (it < k - 1) N.slot(it, pd, pr);
         if (pr != kEmpty) {
+          od = pd;
+          orr = pr;
           dsc = lst[pr];
           base = 0;
         } else {
