@@ -117,3 +117,33 @@ def test_walker_rejects_incomplete_lists():
         if broken >= 3:
             break
     assert broken >= 3
+
+
+@pytest.mark.parametrize("seed", [6, 7])
+def test_entries_nearer_than_a_confirmed_neighbour_are_confirmed(seed):
+    """The property the query kernels' expansion uses (from Theorem 1): when the list of the
+    i-th nearest site (0-based, i < k-1) is scanned, sites 0 .. i are final, so every entry
+    of that list below the prefix bound whose key (D, rank) is below site i's key is one of
+    sites 0 .. i-1.  Checked against brute force on the exact lists."""
+    import oracle
+    oracle.build(force=False)
+    from paper_2605_02224_amd import workloads as W
+    P = W.random_cloud(26, seed=seed, shape="sphere", noise=5e-2).by_rank
+    L = S.successor_lists(P)
+    rng = np.random.default_rng(seed)
+    Q = rng.uniform(-1.6, 1.6, (60, 3)).astype(np.float32)
+    checked = 0
+    for m in (2, 9, 17, 26):
+        ref_idx, _, ref_D = oracle.knn_bruteforce(P, Q, m, m)
+        for q in range(Q.shape[0]):
+            order = ref_idx[q].tolist()
+            key = {r: (ref_D[q][t], r) for t, r in enumerate(order)}
+            for i in range(m - 1):
+                owner = order[i]
+                for c in L[owner]:
+                    if c >= m:
+                        break
+                    if key[c] < key[owner]:
+                        assert c in order[:i], (m, q, i, c)
+                        checked += 1
+    assert checked > 100
