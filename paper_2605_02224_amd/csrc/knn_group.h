@@ -304,6 +304,36 @@ struct RowTopK {
     return better ? 1 : 0;
   }
 
+  // k <= 16 (one slot per lane): insert the flagged candidates of each row one by one, in
+  // lane order, and refresh the threshold once at the end.  A candidate is not tested
+  // against the threshold again after each insertion: one that no longer ranks compares
+  // above every slot and changes nothing.  Per candidate, slot l keeps its key if that key
+  // is smaller (or the row already holds the candidate's rank), takes the candidate if it
+  // is the first slot that does not, and otherwise takes slot l-1's key (DPP row_shr:1).
+  __device__ __forceinline__ void insert_each16(bool cand, double dd, int32_t rr, int l, int g,
+                                                int k) {
+    static_assert(S == 1, "insert_each16 serves one slot per lane");
+    uint32_t mask = row_bits(__ballot(cand), g);   // uniform in the row
+    while (mask) {
+      const int j = __ffs(mask) - 1;
+      mask &= mask - 1u;
+      const double cd = __shfl(dd, j, 16);
+      const int32_t cr = __shfl(rr, j, 16);
+      const bool held = row_bits(__ballot(r[0] == cr), g) != 0;
+      const bool keep = held || key_less(d[0], r[0], cd, cr);
+      // lane l-1's "moved" flag; lane 0 reads 0 (no source lane: either DPP bound mode
+      // leaves or writes 0)
+      const int32_t prev_moved =
+          __builtin_amdgcn_update_dpp(0, keep ? 0 : 1, kDppRowShr1, 0xf, 0xf, true);
+      const double pd = dpp_f64<kDppRowShr1>(d[0], d[0]);
+      const int32_t pr = dpp_i32<kDppRowShr1>(r[0], r[0]);
+      const bool take = prev_moved == 0;
+      d[0] = keep ? d[0] : (take ? cd : pd);
+      r[0] = keep ? r[0] : (take ? cr : pr);
+    }
+    refresh_threshold(k);
+  }
+
   // k > 16 (S slots per lane): insert the flagged candidates of each row one by one, in
   // lane order, and refresh the threshold once at the end (slot k-1 takes a cross-lane read
   // when k < 16 S).  A candidate is not tested against the threshold again after each

@@ -39,7 +39,7 @@ __device__ __forceinline__ void offer_all(RowTopK<S, EXACTK> &N, bool cand, doub
     return;
   }
   if constexpr (S == 1)
-    N.insert_all(cand, dd, rr, l, g, k);
+    N.insert_each16(cand, dd, rr, l, g, k);
   else
     N.insert_each(cand, dd, rr, l, g, k);
 }
