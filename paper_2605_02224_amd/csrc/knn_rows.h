@@ -15,7 +15,8 @@
 //               is offered to N and the walk jumps to its list.  A list without one is the
 //               final list of the descent, offered whole (it doubles as Alg. 2's first
 //               iteration, exactly as in the group kernel).
-//   expansion : every entry of the list of N's slot `it` is offered (it = 1 .. k-2).
+//   expansion : every entry of the list of N's slot `it` whose key lies above that slot's
+//               key is offered (it = 1 .. k-2); the nearer ones are already in N.
 #pragma once
 #include <type_traits>
 
