@@ -145,3 +145,58 @@ def test_errors(api):
     with pytest.raises(MknnError) as e:
         api.Cloud.build(P, np.zeros(50, np.int32))
     assert e.value.status == EINVAL
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 5])
+def test_lattice_confirmed_prefix_property(api, seed):
+    """On the lattice's built lists (ties everywhere), the property the query kernels'
+    expansion relies on still holds: an entry of the i-th nearest site's list (below the
+    prefix bound) whose key (D, rank) is below that site's key is one of sites 0 .. i-1."""
+    import oracle
+    from paper_2605_02224_amd import workloads as W
+    P = W.lattice_cloud(3, seed).by_rank
+    L = api.Cloud.build(P).lists()
+    n = P.shape[0]
+    rng = np.random.default_rng(seed)
+    Q = rng.uniform(-0.5, 2.5, (200, 3)).astype(np.float32)
+    Q[:20] = P[:20]
+    checked = 0
+    for m in (5, 14, n):
+        ref, _, refD = oracle.knn_bruteforce(P, Q, m, m)
+        for q in range(Q.shape[0]):
+            order = ref[q].tolist()
+            key = {r: (refD[q][t], r) for t, r in enumerate(order)}
+            for i in range(m - 1):
+                for c in L[order[i]]:
+                    if c >= m:
+                        break
+                    if key[c] < key[order[i]]:
+                        assert c in order[:i], (m, q, i, c)
+                        checked += 1
+    assert checked > 100
+
+
+def test_confirmed_prefix_property_20k(api):
+    """The same property on the built lists of a 20k-point torus, for the first 16 sites
+    of every query's order, with and without a prefix bound."""
+    import oracle
+    from paper_2605_02224_amd import workloads as W
+    P = W.random_cloud(20000, seed=8, shape="torus").by_rank
+    L = api.Cloud.build(P).lists()
+    lo, hi = W.bbox_expanded(P, 1.1)
+    Q = W.uniform_in_box(np.random.default_rng(2), 300, lo, hi)
+    checked = 0
+    for k, m in ((17, 20000), (17, 3000)):
+        ref, _, refD = oracle.knn_bruteforce(P, Q, k, m)
+        for q in range(Q.shape[0]):
+            order = ref[q].tolist()
+            key = {r: (refD[q][t], r) for t, r in enumerate(order)}
+            for i in range(k - 1):
+                for c in L[order[i]]:
+                    if c >= m:
+                        break
+                    # an entry outside the k nearest has a key above every one of them
+                    if c in key and key[c] < key[order[i]]:
+                        assert c in order[:i], (m, q, i, c)
+                        checked += 1
+    assert checked > 1000
