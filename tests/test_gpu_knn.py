@@ -128,6 +128,24 @@ def test_edge_cases(env):
         cl.knn(qd, 4, 5001)
 
 
+def test_lattice_ties(env):
+    """Integer lattice: cospherical and coplanar sets everywhere, so many distances tie
+    exactly and the rank decides; queries on lattice points, on cell centres and at random.
+    The expansion's owner-key filter and the duplicate tests are exercised on lists that
+    hold weakly adjacent pairs."""
+    torch, oracle, A = env
+    from paper_2605_02224_amd import workloads as W
+    for side, seed in ((6, 1), (8, 3)):
+        P = W.lattice_cloud(side, seed).by_rank
+        n = P.shape[0]
+        cl = A.Cloud.build(P).upload()
+        rng = np.random.default_rng(seed)
+        Q = np.concatenate([rng.uniform(-0.5, side - 0.5, (700, 3)), P[:60], P[:60] + 0.5,
+                            np.full((5, 3), (side - 1) / 2)]).astype(np.float32)
+        for k, m in ((1, n), (6, n), (16, n), (16, 100), (27, n), (33, 200), (64, n)):
+            assert _run(env, cl, P, Q, k, m) == 0, (side, k, m)
+
+
 def test_work_counts_match_reference_walk(env):
     """Entries examined and lists opened by the kernel equal those of the reference walk."""
     torch, oracle, A = env
