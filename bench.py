@@ -554,7 +554,7 @@ def main() -> int:
                     help="also run one plain 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         return 2
 
     import torch

@@ -45,7 +45,7 @@ typedef enum {
   MKNN_EHIP = -5,         /* a HIP runtime call failed (message names the hipError_t) */
   MKNN_ENOTFOUND = -6,    /* deletion of an unknown or already deleted rank */
   MKNN_EBUSY = -7,        /* resource pool full; retry later */
-  MKNN_EUNSUPPORTED = -8  /* valid request outside what this build handles */
+  MKNN_EUNSUPPORTED = -8  /* valid request outside what the library supports */
 } mknn_status;
 
 /* Largest k a query may ask for. */
