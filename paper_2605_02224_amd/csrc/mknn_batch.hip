@@ -59,6 +59,7 @@ struct BatchHeader {
   int32_t nreq;
   int32_t sorted;
   int64_t total_q;
+  int64_t fwaves[kClasses];                // flat launch: wavefronts of work per class
   int32_t qbound[kClasses][kQueues + 1];   // entry index ranges per (class, queue)
   int32_t qtiles[kClasses][kQueues];       // tiles per (class, queue)
   int32_t tile[kClasses];                  // queries per tile, per class
@@ -249,6 +250,56 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
   }
 }
 
+// Flat batched kernel: the plain launch over the concatenated batch.  Class `cls`'s
+// requests (queue entries qbound[cls][0] .. qbound[cls][kQueues]) are laid end to end,
+// request e taking wavefronts woff[e] .. woff[e] + ceil(nq / 4) - 1, each four consecutive
+// sorted queries of that request, one per row, run to the end together as in the plain
+// kernel.  No tiles, atomics or per-wavefront request state: registers as in the plain
+// kernel, 8 waves per SIMD.  The grid is sized for the plan's capacity (fixed, so that one
+// graph replays any batch) and laid XCD-contiguously over the workgroups the batch needs:
+// block 8 i + x runs on XCD x and takes workgroup x * per + i, per = ceil(needed / 8);
+// blocks past that leave at once.
+template <int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
+void knn_batch_flat_kernel(const BatchHeader *h, const QueryArgs *reqs, const BatchEntry *ents,
+                           const int64_t *woff, int cls) {
+  const int64_t nw = h->fwaves[cls];
+  const int64_t need = (nw + 3) >> 2;              // workgroups of four wavefronts
+  const int64_t per = (need + 7) >> 3;
+  const int64_t i = blockIdx.x >> 3, x = blockIdx.x & 7;
+  if (i >= per) return;
+  const int64_t wg = x * per + i;
+  const int64_t wave = __builtin_amdgcn_readfirstlane((int32_t)(4 * wg + (threadIdx.x >> 6)));
+  if (wg >= need || wave >= nw) return;          // whole wavefronts leave
+  // the entry owning this wavefront: the last one whose first wavefront is <= wave
+  int32_t lo = h->qbound[cls][0], hi = h->qbound[cls][kQueues];
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (woff[mid] <= wave) lo = mid; else hi = mid;
+  }
+  const int32_t req = __builtin_amdgcn_readfirstlane(ents[lo].req);
+  const QueryArgs a = reqs[req];
+  const int64_t begin = 4 * (wave - woff[lo]);
+  const int64_t end = begin + 4 < a.nq ? begin + 4 : a.nq;
+  const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4;
+  const int32_t m = (int32_t)(a.m < a.n ? (int64_t)a.m : a.n);
+  RowWalker<S, false, (S == 1), true> w;
+  w.N.init();
+  if (begin + g < end) w.begin(a, begin + g, l);
+  while (__ballot(w.phase != kRowIdle) != 0)
+    w.template step<true>(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
+}
+
+// The persistent tile-claiming kernel instead of the flat one (MKNN_BATCH_PERSISTENT=1).
+static bool batch_persistent() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("MKNN_BATCH_PERSISTENT");
+    v = (e && e[0] && e[0] != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
+
 template <int S>
 static int resident_batch_blocks() {
   static int nb = 0;
@@ -275,7 +326,8 @@ struct mknn_batch_plan {
   bool sort = true, use_graph = true;
   // device: staging mirror | counters | bins | sorted queries
   char *d_base = nullptr;
-  size_t off_hdr = 0, off_reqs = 0, off_ents = 0, off_boxes = 0, off_qoff = 0, stage_bytes = 0;
+  size_t off_hdr = 0, off_reqs = 0, off_ents = 0, off_boxes = 0, off_qoff = 0, off_woff = 0,
+         stage_bytes = 0;
   uint32_t *d_counters = nullptr;
   uint32_t *d_bins = nullptr;
   float4 *d_qs = nullptr;
@@ -286,6 +338,7 @@ struct mknn_batch_plan {
   hipEvent_t done = nullptr;
   bool pending = false;
   uint32_t grid_batch[kClasses] = {1, 1, 1, 1};
+  uint32_t grid_flat = 8;           // flat launch: blocks for the capacity (a multiple of 8)
   uint32_t grid_stream = 1;
 };
 
@@ -309,6 +362,7 @@ static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s) {
   const BatchEntry *ents = (const BatchEntry *)(p->d_base + p->off_ents);
   const BoxArgs *boxes = (const BoxArgs *)(p->d_base + p->off_boxes);
   const int64_t *qoff = (const int64_t *)(p->d_base + p->off_qoff);
+  const int64_t *woff = (const int64_t *)(p->d_base + p->off_woff);
   hipError_t e = hipMemcpyAsync(p->d_base, p->h_stage, p->stage_bytes, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(1), dim3(64), 0, s, p->d_counters,
@@ -329,14 +383,22 @@ static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = timing_mark(s, true);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(knn_batch_rows_kernel<1>, dim3(p->grid_batch[0]), dim3(256), 0, s, hdr, reqs,
-                     ents, p->d_counters, 0);
-  hipLaunchKernelGGL(knn_batch_rows_kernel<2>, dim3(p->grid_batch[1]), dim3(256), 0, s, hdr, reqs,
-                     ents, p->d_counters, 1);
-  hipLaunchKernelGGL(knn_batch_rows_kernel<3>, dim3(p->grid_batch[2]), dim3(256), 0, s, hdr, reqs,
-                     ents, p->d_counters, 2);
-  hipLaunchKernelGGL(knn_batch_rows_kernel<4>, dim3(p->grid_batch[3]), dim3(256), 0, s, hdr, reqs,
-                     ents, p->d_counters, 3);
+  if (batch_persistent()) {
+    hipLaunchKernelGGL(knn_batch_rows_kernel<1>, dim3(p->grid_batch[0]), dim3(256), 0, s, hdr,
+                       reqs, ents, p->d_counters, 0);
+    hipLaunchKernelGGL(knn_batch_rows_kernel<2>, dim3(p->grid_batch[1]), dim3(256), 0, s, hdr,
+                       reqs, ents, p->d_counters, 1);
+    hipLaunchKernelGGL(knn_batch_rows_kernel<3>, dim3(p->grid_batch[2]), dim3(256), 0, s, hdr,
+                       reqs, ents, p->d_counters, 2);
+    hipLaunchKernelGGL(knn_batch_rows_kernel<4>, dim3(p->grid_batch[3]), dim3(256), 0, s, hdr,
+                       reqs, ents, p->d_counters, 3);
+  } else {
+    const dim3 gf(p->grid_flat);
+    hipLaunchKernelGGL(knn_batch_flat_kernel<1>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 0);
+    hipLaunchKernelGGL(knn_batch_flat_kernel<2>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 1);
+    hipLaunchKernelGGL(knn_batch_flat_kernel<3>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 2);
+    hipLaunchKernelGGL(knn_batch_flat_kernel<4>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 3);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return timing_mark(s, false);
@@ -373,6 +435,8 @@ mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, in
   o = align256(o + sizeof(BoxArgs) * (size_t)p->max_req);
   p->off_qoff = o;
   o = align256(o + sizeof(int64_t) * (size_t)(p->max_req + 1));
+  p->off_woff = o;
+  o = align256(o + sizeof(int64_t) * (size_t)p->max_req);
   p->stage_bytes = o;
   const size_t counters_at = o;
   o = align256(o + sizeof(uint32_t) * kClasses * kQueues);
@@ -396,6 +460,17 @@ mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, in
   p->grid_batch[2] = cus * resident_batch_blocks<3>();
   p->grid_batch[3] = cus * resident_batch_blocks<4>();
   p->grid_stream = cus * 8;
+  {
+    // a class holds at most max_q / 4 + max_req wavefronts of work (a partial one per request)
+    const int64_t waves = (p->max_q + 3) / 4 + p->max_req;
+    const int64_t wgs = (waves + 3) / 4;
+    const int64_t blocks = 8 * ((wgs + 7) / 8);
+    if (blocks > (int64_t)0x7fffffff) {
+      plan_release(p);
+      return set_error(MKNN_EINVAL, "mknn_batch_plan_create: capacity too large for one launch");
+    }
+    p->grid_flat = (uint32_t)blocks;
+  }
   p->d_counters = (uint32_t *)(p->d_base + counters_at);
   p->d_bins = p->sort ? (uint32_t *)(p->d_base + bins_at) : nullptr;
   p->d_qs = p->sort ? (float4 *)(p->d_base + qs_at) : nullptr;
@@ -472,20 +547,28 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
     while (t * 2 <= want && t * 2 <= p->tile_q) t *= 2;
     hdr->tile[c] = (int32_t)std::max<int64_t>(4, std::min<int64_t>(t, p->tile_q));
   }
+  int64_t *woff = (int64_t *)(p->h_stage + p->off_woff);
   int32_t ne = 0;
   for (int c = 0; c < kClasses; ++c) {
+    int64_t nw = 0;   // flat launch: wavefronts of the class so far
     for (int x = 0; x < kQueues; ++x) {
       hdr->qbound[c][x] = ne;
       int64_t nt = 0;
       for (int32_t r : queue_reqs[(size_t)c * kQueues + x]) {
         ents[ne].req = r;
         ents[ne].first = (int32_t)nt;
+        woff[ne] = nw;
         ++ne;
         nt += (reqs[r].nq + hdr->tile[c] - 1) / hdr->tile[c];
+        nw += (reqs[r].nq + 3) / 4;
       }
       hdr->qtiles[c][x] = (int32_t)nt;
     }
     hdr->qbound[c][kQueues] = ne;
+    hdr->fwaves[c] = nw;
+    // the flat grid covers every class: 8 ceil(workgroups / 8) blocks (checked, not assumed)
+    if (8 * (((nw + 3) / 4 + 7) / 8) > (int64_t)p->grid_flat)
+      return set_error(MKNN_EINVAL, "mknn_batch_plan_run: batch exceeds the plan's launch size");
   }
   hdr->nreq = nreq;
   hdr->sorted = p->sort ? 1 : 0;
