@@ -129,17 +129,19 @@ mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, cons
                          int32_t *d_idx, float *d_dist, void *stream);
 
 /* ---------------------------------------------------------------------------------------
- * Batched form: many clouds with their own query sets, k and prefixes in one persistent
- * launch per register class (k <= 16, 32, 48, 64).  Same per-query semantics as mknn_knn
- * (Alg. 1 + Alg. 2, Sec. 4.2).
+ * Batched form: many clouds with their own query sets, k and prefixes in one launch per
+ * register class (k <= 16, 32, 48, 64).  Same per-query semantics as mknn_knn (Alg. 1 +
+ * Alg. 2, Sec. 4.2).
  *
- * Each request is cut into tiles of at most `tile_queries` queries (4 .. 2^20; 16 is a good
- * default: small tiles keep concurrent work on nearby queries).  Requests are assigned to 8
- * per-XCD queues (largest estimated cost first, all tiles of a request on one queue).
- * Persistent wavefronts claim tiles from their own queue with an atomic counter and steal
- * from the other queues when it runs dry; their 16-lane rows take queries one at a time.
  * The queries of all requests are bucketed together by (request, Morton code) unless
- * MKNN_BATCH_NO_SORT is set.
+ * MKNN_BATCH_NO_SORT is set.  By default each class is one flat launch over its requests
+ * laid end to end: every wavefront takes four consecutive sorted queries of one request,
+ * the workgroups of a batch spread evenly and contiguously over the 8 XCDs.  With the
+ * environment variable MKNN_BATCH_PERSISTENT=1 a persistent launch is used instead: each
+ * request is cut into tiles of at most `tile_queries` queries (4 .. 2^20; 16 is a good
+ * default), requests go to 8 per-XCD queues (largest estimated cost first), and persistent
+ * wavefronts claim tiles from their own queue with an atomic counter and steal from the
+ * others when it runs dry.  `tile_queries` only matters for the persistent launch.
  */
 typedef struct {
   const mknn_cloud *cloud;   /* an uploaded cloud */
@@ -173,9 +175,10 @@ mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries,
 mknn_status mknn_batch_plan_run(mknn_batch_plan *plan, const mknn_request *reqs, int32_t nreq,
                                 void *stream);
 
-/* Autotuner of the batched form: runs the batch with tile lengths 8, 16, 32, 64 and 256
- * (three timed runs each, HIP events on `stream`), keeps the fastest as the plan's tile
- * length and reports it.  The outputs hold the batch's results afterwards. */
+/* Autotuner of the batched form's persistent launch (MKNN_BATCH_PERSISTENT=1): runs the
+ * batch with tile lengths 8, 16, 32, 64 and 256 (three timed runs each, HIP events on
+ * `stream`), keeps the fastest as the plan's tile length and reports it.  The outputs hold
+ * the batch's results afterwards. */
 mknn_status mknn_batch_plan_tune(mknn_batch_plan *plan, const mknn_request *reqs, int32_t nreq,
                                  void *stream, int32_t *best_tile);
 
