@@ -98,7 +98,7 @@ def build_clouds(clouds, threads: int = 16):
 
 def bench_batched(args) -> int:
     """Many clouds (sizes log-uniform in [1e3, 2e5], sphere/torus/ellipsoid, 4 n_c queries
-    each, k=10): one persistent launch per batch versus one plain launch per cloud."""
+    each, k=10): one flat launch per class and batch versus one plain launch per cloud."""
     import torch
     from paper_2605_02224_amd import workloads as W
     from paper_2605_02224_amd import api as A
@@ -147,7 +147,7 @@ def bench_batched(args) -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"batched_{len(items)}_clouds_k{w.k}", "clouds": len(items),
                    "points": int(sum(c.n for c in w.clouds)), "queries": int(nq), "k": w.k,
-                   "form": "one persistent launch (hipGraph replay) per batch",
+                   "form": "one flat launch per class (hipGraph replay) per batch",
                    "tile_queries": tile},
         "extra": {"plain_qps": round(res["plain"][0], 1),
                   "plain_ms": round(res["plain"][1] * 1e3, 3),

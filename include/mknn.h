@@ -137,7 +137,8 @@ mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, cons
  * MKNN_BATCH_NO_SORT is set.  By default each class is one flat launch over its requests
  * laid end to end: every wavefront takes four consecutive sorted queries of one request,
  * the workgroups of a batch spread evenly and contiguously over the 8 XCDs.  With the
- * environment variable MKNN_BATCH_PERSISTENT=1 a persistent launch is used instead: each
+ * environment variable MKNN_BATCH_PERSISTENT=1 at plan creation, that plan uses a
+ * persistent launch instead: each
  * request is cut into tiles of at most `tile_queries` queries (4 .. 2^20; 16 is a good
  * default), requests go to 8 per-XCD queues (largest estimated cost first), and persistent
  * wavefronts claim tiles from their own queue with an atomic counter and steal from the

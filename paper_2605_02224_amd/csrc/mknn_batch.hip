@@ -297,14 +297,11 @@ void knn_batch_flat_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
     w.template step<true>(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
 }
 
-// The persistent tile-claiming kernel instead of the flat one (MKNN_BATCH_PERSISTENT=1).
+// The persistent tile-claiming kernel instead of the flat one (MKNN_BATCH_PERSISTENT=1 in
+// the environment when a plan is created).
 static bool batch_persistent() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = getenv("MKNN_BATCH_PERSISTENT");
-    v = (e && e[0] && e[0] != '0') ? 1 : 0;
-  }
-  return v == 1;
+  const char *e = getenv("MKNN_BATCH_PERSISTENT");
+  return e && e[0] && e[0] != '0';
 }
 
 template <int S>
@@ -346,6 +343,7 @@ struct mknn_batch_plan {
   bool pending = false;
   uint32_t grid_batch[kClasses] = {1, 1, 1, 1};
   uint32_t grid_flat = 8;           // flat launch: blocks for the capacity (a multiple of 8)
+  bool persistent = false;          // the persistent kernel instead of the flat one
   uint32_t grid_stream = 1;
 };
 
@@ -390,7 +388,7 @@ static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = timing_mark(s, true);
   if (e != hipSuccess) return e;
-  if (batch_persistent()) {
+  if (p->persistent) {
     hipLaunchKernelGGL(knn_batch_rows_kernel<1>, dim3(p->grid_batch[0]), dim3(256), 0, s, hdr,
                        reqs, ents, p->d_counters, 0);
     hipLaunchKernelGGL(knn_batch_rows_kernel<2>, dim3(p->grid_batch[1]), dim3(256), 0, s, hdr,
@@ -429,6 +427,7 @@ mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, in
   p->max_q = max_queries;
   p->tile_q = tile_queries;
   p->sort = !(flags & MKNN_BATCH_NO_SORT);
+  p->persistent = batch_persistent();
   p->use_graph = !(flags & MKNN_BATCH_NO_GRAPH);
   hipError_t e = hipGetDevice(&p->device);
   size_t o = 0;

@@ -1,4 +1,4 @@
-"""GPU parity of the batched form: many clouds in one persistent launch per class, against
+"""GPU parity of the batched form: many clouds in one launch per class, against
 the oracle and bit-for-bit against the plain per-cloud launch."""
 import numpy as np
 import pytest
@@ -73,6 +73,29 @@ def test_batch_matches_oracle_and_plain(env, sort, graph):
             continue
         pi, pd = cl.knn(q, k, None if m == 0 else m)
         assert torch.equal(pi, idx) and torch.equal(pd, dist)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_persistent_launch_matches_plain(env, graph):
+    """The persistent tile-claiming launch (chosen at plan creation by MKNN_BATCH_PERSISTENT)
+    gives the plain launch's bits, like the default flat launch."""
+    import os
+    torch, oracle, A, W, clouds = env
+    items, host = _make_batch(env, seed=3)
+    os.environ["MKNN_BATCH_PERSISTENT"] = "1"
+    try:
+        plan = A.BatchPlan(64, 200000, tile_queries=16, sort=True, graph=graph)
+    finally:
+        del os.environ["MKNN_BATCH_PERSISTENT"]
+    for rep in range(2):
+        plan.run(items)
+        torch.cuda.synchronize()
+        for cl, q, k, m, idx, dist in items:
+            if q.shape[0] == 0:
+                continue
+            pi, pd = cl.knn(q, k, None if m == 0 else m)
+            assert torch.equal(pi, idx) and torch.equal(pd, dist)
+    assert _check(env, items, host, sample=200) <= 3
 
 
 def test_graph_replays_with_changing_batches(env):
