@@ -344,6 +344,8 @@ struct mknn_batch_plan {
   uint32_t grid_batch[kClasses] = {1, 1, 1, 1};
   uint32_t grid_flat = 8;           // flat launch: blocks for the capacity (a multiple of 8)
   bool persistent = false;          // the persistent kernel instead of the flat one
+  uint32_t classes = 0xF;           // register classes that plan_enqueue launches (bit S-1)
+  uint32_t graph_classes = 0;       // the classes the captured graph launches
   uint32_t grid_stream = 1;
 };
 
@@ -388,21 +390,32 @@ static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = timing_mark(s, true);
   if (e != hipSuccess) return e;
+  // only the classes in p->classes: an empty class's launch still dispatches its whole grid
+  const bool c1 = p->classes & 1u, c2 = p->classes & 2u, c3 = p->classes & 4u,
+             c4 = p->classes & 8u;
   if (p->persistent) {
-    hipLaunchKernelGGL(knn_batch_rows_kernel<1>, dim3(p->grid_batch[0]), dim3(256), 0, s, hdr,
-                       reqs, ents, p->d_counters, 0);
-    hipLaunchKernelGGL(knn_batch_rows_kernel<2>, dim3(p->grid_batch[1]), dim3(256), 0, s, hdr,
-                       reqs, ents, p->d_counters, 1);
-    hipLaunchKernelGGL(knn_batch_rows_kernel<3>, dim3(p->grid_batch[2]), dim3(256), 0, s, hdr,
-                       reqs, ents, p->d_counters, 2);
-    hipLaunchKernelGGL(knn_batch_rows_kernel<4>, dim3(p->grid_batch[3]), dim3(256), 0, s, hdr,
-                       reqs, ents, p->d_counters, 3);
+    if (c1)
+      hipLaunchKernelGGL(knn_batch_rows_kernel<1>, dim3(p->grid_batch[0]), dim3(256), 0, s, hdr,
+                         reqs, ents, p->d_counters, 0);
+    if (c2)
+      hipLaunchKernelGGL(knn_batch_rows_kernel<2>, dim3(p->grid_batch[1]), dim3(256), 0, s, hdr,
+                         reqs, ents, p->d_counters, 1);
+    if (c3)
+      hipLaunchKernelGGL(knn_batch_rows_kernel<3>, dim3(p->grid_batch[2]), dim3(256), 0, s, hdr,
+                         reqs, ents, p->d_counters, 2);
+    if (c4)
+      hipLaunchKernelGGL(knn_batch_rows_kernel<4>, dim3(p->grid_batch[3]), dim3(256), 0, s, hdr,
+                         reqs, ents, p->d_counters, 3);
   } else {
     const dim3 gf(p->grid_flat);
-    hipLaunchKernelGGL(knn_batch_flat_kernel<1>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 0);
-    hipLaunchKernelGGL(knn_batch_flat_kernel<2>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 1);
-    hipLaunchKernelGGL(knn_batch_flat_kernel<3>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 2);
-    hipLaunchKernelGGL(knn_batch_flat_kernel<4>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 3);
+    if (c1)
+      hipLaunchKernelGGL(knn_batch_flat_kernel<1>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 0);
+    if (c2)
+      hipLaunchKernelGGL(knn_batch_flat_kernel<2>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 1);
+    if (c3)
+      hipLaunchKernelGGL(knn_batch_flat_kernel<3>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 2);
+    if (c4)
+      hipLaunchKernelGGL(knn_batch_flat_kernel<4>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 3);
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -594,9 +607,21 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   }
   for (int32_t r = 0; r <= nreq; ++r) d_qoff[r] = qoff[r];
   // ---- run (graph replay or eager)
+  uint32_t need = 0;   // the classes with work in this batch
+  for (int c = 0; c < kClasses; ++c)
+    if (class_q[c] > 0) need |= 1u << c;
   hipStream_t s = (hipStream_t)stream;
   if (p->use_graph && !timing_enabled()) {
+    if (p->exec && (need & ~p->graph_classes)) {
+      // a class the graph does not launch: capture again with it (the previous run is done)
+      (void)hipGraphExecDestroy(p->exec);
+      (void)hipGraphDestroy(p->graph);
+      p->exec = nullptr;
+      p->graph = nullptr;
+    }
     if (!p->exec) {
+      p->classes = p->graph_classes | need;
+      p->graph_classes = p->classes;
       HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal),
               "mknn_batch_plan_run: begin capture");
       hipError_t e = plan_enqueue(p, p->cap_stream);
@@ -613,6 +638,7 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
     }
     HIP_TRY(hipGraphLaunch(p->exec, s), "mknn_batch_plan_run: graph launch");
   } else {
+    p->classes = need;
     HIP_TRY(plan_enqueue(p, s), "mknn_batch_plan_run: launch");
   }
   HIP_TRY(hipEventRecord(p->done, s), "mknn_batch_plan_run: record");
