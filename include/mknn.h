@@ -162,10 +162,12 @@ typedef struct mknn_batch_plan mknn_batch_plan; /* opaque, owned by the library 
 /* mknn_batch_plan_create: device buffers for up to max_requests requests and max_queries
  * queries in total (max_queries < 2^31), plus pinned host staging.  Unless
  * MKNN_BATCH_NO_GRAPH is set, the first run captures the whole sequence (descriptor copy,
- * counter clear, query bucketing, the four class launches) into a hipGraph.  Later runs
- * update the descriptors in the pinned staging area and replay the graph: every kernel reads
- * its sizes from device memory and uses a fixed grid.  A plan belongs to the device that was
- * current at creation.  Errors: EINVAL, ENOMEM, EHIP. */
+ * counter clear, query bucketing, the launches of the register classes that have work)
+ * into a hipGraph.  Later runs update the descriptors in the pinned staging area and replay
+ * the graph: every kernel reads its sizes from device memory and uses a fixed grid; a run
+ * with work in a class the graph does not launch captures the graph again, with that class
+ * added.  A plan belongs to the device that was current at creation.
+ * Errors: EINVAL, ENOMEM, EHIP. */
 mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries,
                                    int32_t tile_queries, int32_t flags, mknn_batch_plan **out);
 
