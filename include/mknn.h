@@ -121,8 +121,11 @@ mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t 
  *   d_row_off  device int64 [nq+1]; row q occupies [d_row_off[q], d_row_off[q+1]) of
  *              d_idx / d_dist, and d_row_off[q+1] - d_row_off[q] must equal d_k[q]
  *   kmax       host int32, an upper bound of all d_k (selects the kernel variant)
- * Errors as mknn_knn.  Out-of-range per-query values are not checked on the device: a
- * query with k or m outside its range returns its row untouched.
+ * Before the query runs, a small kernel checks every query's k, m and row length on the
+ * device and the call reads the verdict back, so it synchronises `stream` once.
+ * Errors as mknn_knn, and EINVAL (nothing written) if some query has k outside [1, kmax],
+ * m < 1, or d_row_off[q+1] - d_row_off[q] != d_k[q]; the message names the first such
+ * query.
  */
 mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, const int32_t *d_k,
                          const int32_t *d_m, const int64_t *d_row_off, int32_t kmax,

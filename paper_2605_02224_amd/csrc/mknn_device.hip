@@ -738,6 +738,48 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
   return MKNN_OK;
 }
 
+// Per-query arguments of mknn_knn_var: the smallest index of a query whose k lies outside
+// [1, kmax], whose m is below 1, or whose row length differs from its k.
+__global__ __launch_bounds__(256) void check_per_query_kernel(const int32_t *kq, const int32_t *mq,
+                                                              const int64_t *off, int64_t nq,
+                                                              int32_t kmax, int32_t *first_bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const int32_t k = kq[i], m = mq[i];
+  const int64_t a = off[i], b = off[i + 1];
+  if (k < 1 || k > kmax || m < 1 || a < 0 || b - a != (int64_t)k) atomicMin(first_bad, (int32_t)i);
+}
+
+// Checks the per-query arrays on the device and reads the verdict back (synchronises s).
+static mknn_status check_per_query(const int32_t *d_k, const int32_t *d_m, const int64_t *d_off,
+                                   int64_t nq, int32_t kmax, hipStream_t s) {
+  int32_t *flag = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&flag, sizeof(int32_t), s), "mknn_knn_var: check scratch");
+  hipLaunchKernelGGL(fill_kernel<int32_t>, dim3(1), dim3(64), 0, s, flag, (int64_t)1,
+                     (int32_t)0x7fffffff);
+  hipLaunchKernelGGL(check_per_query_kernel, dim3((uint32_t)((nq + 255) / 256)), dim3(256), 0, s,
+                     d_k, d_m, d_off, nq, kmax, flag);
+  int32_t bad = 0x7fffffff;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  (void)hipFreeAsync(flag, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess)
+    return set_error(MKNN_EHIP, std::string("mknn_knn_var: argument check: ") + hipGetErrorName(e));
+  if (bad != 0x7fffffff) {
+    int32_t k = 0, m = 0;
+    int64_t off[2] = {0, 0};
+    (void)hipMemcpy(&k, d_k + bad, sizeof(k), hipMemcpyDeviceToHost);
+    (void)hipMemcpy(&m, d_m + bad, sizeof(m), hipMemcpyDeviceToHost);
+    (void)hipMemcpy(off, d_off + bad, sizeof(off), hipMemcpyDeviceToHost);
+    return set_error(MKNN_EINVAL, "mknn_knn_var: query " + std::to_string(bad) + " has k=" +
+                                      std::to_string(k) + " (kmax " + std::to_string(kmax) +
+                                      "), m=" + std::to_string(m) + ", row length " +
+                                      std::to_string(off[1] - off[0]));
+  }
+  return MKNN_OK;
+}
+
 }  // namespace mknn
 
 using namespace mknn;
@@ -828,6 +870,8 @@ mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, cons
   if (nq == 0) return MKNN_OK;
   if (!d_q || !d_k || !d_m || !d_row_off || !d_idx || !d_dist)
     return set_error(MKNN_EINVAL, "mknn_knn_var: NULL buffer");
+  st = check_per_query(d_k, d_m, d_row_off, nq, kmax, (hipStream_t)stream);
+  if (st != MKNN_OK) return st;
   return run_query(c, d_q, nq, 0, 0, d_k, d_m, d_row_off, kmax, d_idx, d_dist, nullptr, nullptr,
                    nullptr, (hipStream_t)stream, "mknn_knn_var");
 }

@@ -55,7 +55,7 @@ def _check(env, items, host, sample=400):
         sel = rng.choice(Q.shape[0], min(sample, Q.shape[0]), replace=False)
         ri, _, rD = oracle.knn_bruteforce(P, Q[sel], k + 1, mm)
         ex += compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k],
-                           rD[:, :k], rD[:, k])
+                           rD[:, :k], rD[:, k], P=P, Q=Q[sel], m=mm)
     return ex
 
 
@@ -161,14 +161,19 @@ def test_256_clouds_paper_scale_sampled(env):
     plan.run(items)
     torch.cuda.synchronize()
     rng = np.random.default_rng(5)
-    exc = 0
-    for c, (cl, q, k, m, idx, dist) in zip(w.clouds, items):
-        sel = rng.choice(q.shape[0], 24, replace=False)
-        Qs = q.cpu().numpy()[sel]
-        ri, _, rD = oracle.knn_bruteforce(c.by_rank, Qs, k + 1)
+    exc = rows = 0
+    # 16 clouds in full, 2,000 sampled rows of every other cloud
+    whole = set(rng.choice(len(items), 16, replace=False).tolist())
+    for i, (c, (cl, q, k, m, idx, dist)) in enumerate(zip(w.clouds, items)):
+        Qa = q.cpu().numpy()
+        sel = (np.arange(Qa.shape[0]) if i in whole else
+               rng.choice(Qa.shape[0], min(2000, Qa.shape[0]), replace=False))
+        ri, _, rD = oracle.knn_bruteforce(c.by_rank, Qa[sel], k + 1)
         exc += compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k], rD[:, :k],
-                            rD[:, k])
-    assert exc <= 3
+                            rD[:, k], P=c.by_rank, Q=Qa[sel])
+        rows += sel.size
+    print(f"256 clouds: {rows} rows checked, near-ties excused {exc}")
+    assert exc <= 6
     plan.close()
 
 

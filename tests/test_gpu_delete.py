@@ -25,7 +25,8 @@ def _check(env, cl, P, live, Q, k, m=None):
     idx, dist = cl.knn(torch.from_numpy(Q).cuda(), k, m)
     torch.cuda.synchronize()
     ri, _, rD = oracle.knn_bruteforce(P, Q, k + 1, m, live=live)
-    return compare_rows(idx.cpu().numpy(), dist.cpu().numpy(), ri[:, :k], rD[:, :k], rD[:, k])
+    return compare_rows(idx.cpu().numpy(), dist.cpu().numpy(), ri[:, :k], rD[:, :k], rD[:, k],
+                        P=P, Q=Q, m=m, live=live)
 
 
 def test_queries_after_deletion_batches(env):
@@ -65,10 +66,13 @@ def test_copy_on_write_keeps_earlier_work_on_the_old_lists(env):
     torch.cuda.synchronize()
     live = np.ones(20000, np.uint8)
     ri, _, rD = oracle.knn_bruteforce(P, Q[:2000], 10)
-    compare_rows(before[0].cpu().numpy()[:2000], before[1].cpu().numpy()[:2000], ri, rD)
+    ex = compare_rows(before[0].cpu().numpy()[:2000], before[1].cpu().numpy()[:2000], ri, rD,
+                      P=P, Q=Q[:2000])
     live[dead] = 0
     ri, _, rD = oracle.knn_bruteforce(P, Q[:2000], 10, live=live)
-    compare_rows(after[0].cpu().numpy()[:2000], after[1].cpu().numpy()[:2000], ri, rD)
+    ex += compare_rows(after[0].cpu().numpy()[:2000], after[1].cpu().numpy()[:2000], ri, rD,
+                       P=P, Q=Q[:2000], live=live)
+    assert ex <= 2
 
 
 def test_repack_when_slack_runs_out(env):
@@ -109,8 +113,9 @@ def test_compact_after_deletions_keeps_results(env):
     live = np.ones(20000, np.uint8)
     live[dead] = 0
     ri, _, rD = oracle.knn_bruteforce(P, Q[:1500], 21, live=live)
-    compare_rows(after[0].cpu().numpy()[:1500], after[1].cpu().numpy()[:1500], ri[:, :20],
-                 rD[:, :20], rD[:, 20])
+    ex = compare_rows(after[0].cpu().numpy()[:1500], after[1].cpu().numpy()[:1500], ri[:, :20],
+                      rD[:, :20], rD[:, 20], P=P, Q=Q[:1500], live=live)
+    assert ex <= 2
 
 
 def test_queries_after_insertions_and_deletions(env):

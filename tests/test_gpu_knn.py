@@ -24,7 +24,8 @@ def _run(env, cl, P, Q, k, m=None):
     idx, dist = cl.knn(qd, k, m)
     torch.cuda.synchronize()
     ri, _, rD = oracle.knn_bruteforce(P, Q, k + 1, m)
-    return compare_rows(idx.cpu().numpy(), dist.cpu().numpy(), ri[:, :k], rD[:, :k], rD[:, k])
+    return compare_rows(idx.cpu().numpy(), dist.cpu().numpy(), ri[:, :k], rD[:, :k], rD[:, k],
+                        P=P, Q=Q, m=m)
 
 
 def test_sphere_10k_k8_full(env):
@@ -92,7 +93,8 @@ def test_per_query_k_and_m(env):
     ex = 0
     for t in range(w.queries.shape[0]):
         s, e = roff[t], roff[t + 1]
-        ex += compare_rows(gi[None, s:e], gd[None, s:e], ri[None, s:e], rD[None, s:e])
+        ex += compare_rows(gi[None, s:e], gd[None, s:e], ri[None, s:e], rD[None, s:e],
+                           P=P, Q=w.queries[t:t + 1], m=w.m_per_query[t])
     assert ex <= 4
 
 
@@ -194,7 +196,7 @@ def test_torus_1m_paper_scale_sampled(env):
             sel = rng.choice(Qall.shape[0], 3000, replace=False)
             ri, _, rD = oracle.knn_bruteforce(P, Qall[sel], k + 1)
             ex = compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k],
-                              rD[:, :k], rD[:, k])
+                              rD[:, :k], rD[:, k], P=P, Q=Qall[sel])
             assert ex <= 2
 
 
@@ -224,5 +226,45 @@ def test_heightfield_2m_prefix_paper_scale_sampled(env):
         assert b - a == k
         o = roff[t]
         ex += compare_rows(idx[a:b][None], dist[a:b][None], ri[o:o + k][None], rD[o:o + k][None],
-                           rD[o + k:o + k + 1])
+                           rD[o + k:o + k + 1], P=P, Q=w.queries[i:i + 1],
+                           m=w.m_per_query[i])
     assert ex <= 3
+
+
+def test_per_query_arguments_rejected(env):
+    """mknn_knn_var checks every query's k, m and row length on the device before the query
+    runs, and rejects the call (EINVAL, output untouched) instead of skipping such rows."""
+    torch, oracle, A = env
+    from paper_2605_02224_amd import _lib
+    from paper_2605_02224_amd import workloads as W
+    c = W.random_cloud(3000, seed=4, shape="sphere")
+    cl = A.Cloud.build(c.by_rank).upload()
+    Q = W.uniform_in_box(np.random.default_rng(1), 500, *W.bbox_expanded(c.by_rank, 1.1))
+    qd = torch.from_numpy(Q).cuda()
+    good_k = torch.full((500,), 8, dtype=torch.int32, device="cuda")
+    good_m = torch.full((500,), 3000, dtype=torch.int32, device="cuda")
+    cl.knn_var(qd, good_k, good_m)             # valid: passes the check
+    for bad_at, what in ((0, "k"), (137, "m"), (499, "m")):
+        kq, mq = good_k.clone(), good_m.clone()
+        if what == "k":
+            kq[bad_at] = 0
+        else:
+            mq[bad_at] = 0 if bad_at < 200 else -5
+        with pytest.raises(_lib.MknnError, match=f"query {bad_at} "):
+            cl.knn_var(qd, kq, mq)
+    # k above the kmax the caller states, and a row length that differs from its k
+    L = _lib.lib()
+    row_off = torch.arange(0, 8 * 501, 8, dtype=torch.int64, device="cuda")
+    idx = torch.full((8 * 500,), -7, dtype=torch.int32, device="cuda")
+    dist = torch.empty(8 * 500, dtype=torch.float32, device="cuda")
+    kq = good_k.clone()
+    kq[42] = 9
+    st = L.mknn_knn_var(cl._h, qd.data_ptr(), 500, kq.data_ptr(), good_m.data_ptr(),
+                        row_off.data_ptr(), 8, idx.data_ptr(), dist.data_ptr(), None)
+    assert st == -1 and b"query 42 " in L.mknn_last_error()
+    row_off[300:] += 1
+    st = L.mknn_knn_var(cl._h, qd.data_ptr(), 500, good_k.data_ptr(), good_m.data_ptr(),
+                        row_off.data_ptr(), 8, idx.data_ptr(), dist.data_ptr(), None)
+    assert st == -1 and b"query 299 " in L.mknn_last_error()
+    torch.cuda.synchronize()
+    assert (idx == -7).all()                   # nothing was written

@@ -70,7 +70,8 @@ def test_plane_fit_rows(env, shape, k, m):
     torch.cuda.synchronize()
     gi, gd, gp = idx.cpu().numpy(), dist.cpu().numpy(), plane.cpu().numpy()
     ri, _, rD = oracle.knn_bruteforce(P, Q, k + 1, m)
-    compare_rows(gi, gd, ri[:, :k], rD[:, :k], rD[:, k])
+    ex = compare_rows(gi, gd, ri[:, :k], rD[:, :k], rD[:, k], P=P, Q=Q, m=m)
+    assert ex <= 2
     # the same rows as the plain query
     i2, d2 = cl.knn(torch.from_numpy(Q).cuda(), k, m)
     assert (i2.cpu().numpy() == gi).all() and (d2.cpu().numpy() == gd).all()
@@ -94,5 +95,6 @@ def test_plane_fit_after_insertion(env):
     torch.cuda.synchronize()
     ri, _, rD = oracle.knn_bruteforce(P, Q, 21)
     gi = idx.cpu().numpy()
-    compare_rows(gi, dist.cpu().numpy(), ri[:, :20], rD[:, :20], rD[:, 20])
+    ex = compare_rows(gi, dist.cpu().numpy(), ri[:, :20], rD[:, :20], rD[:, 20], P=P, Q=Q)
+    assert ex <= 2
     _check_planes(P, gi, ri[:, :20], plane.cpu().numpy(), planefit.plane_fit_rows(P, ri[:, :20]))

@@ -72,12 +72,14 @@ def test_each_result_same_alone_and_in_the_mix(env, plain):
         assert torch.equal(ai, bufs[1]) and torch.equal(ad, bufs[2])
     # and the mix agrees with the oracle on a sample of every request
     rng = np.random.default_rng(3)
+    ex = 0
     for (c, Q, q, k, m), bufs in zip(reqs[:40], got[:40]):
         P = clouds[c][0]
         sel = rng.choice(Q.shape[0], min(64, Q.shape[0]), replace=False)
         ri, _, rD = oracle.knn_bruteforce(P, Q[sel], k + 1, m)
-        compare_rows(bufs[1].cpu().numpy()[sel], bufs[2].cpu().numpy()[sel], ri[:, :k],
-                     rD[:, :k], rD[:, k])
+        ex += compare_rows(bufs[1].cpu().numpy()[sel], bufs[2].cpu().numpy()[sel], ri[:, :k],
+                           rD[:, :k], rD[:, k], P=P, Q=Q[sel], m=m)
+    assert ex <= 2
 
 
 def test_host_outputs_match_device_outputs(env):
@@ -135,6 +137,7 @@ def test_deletions_between_batches(env, bind_at_admission):
             log.append(("knn", t, c, Q, k, len(masks[c]) - 1))
     res = {t: srv.wait(t, with_seen=True) for _, t, *_ in log}
     srv.close()
+    ex = 0
     for kind, t, c, Q, k, before in log:
         if kind != "knn":
             continue
@@ -145,8 +148,9 @@ def test_deletions_between_batches(env, bind_at_admission):
         P = clouds[c][0]
         sel = np.arange(min(100, Q.shape[0]))
         ri, _, rD = oracle.knn_bruteforce(P, Q[sel], k + 1, live=masks[c][seen])
-        compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k], rD[:, :k],
-                     rD[:, k])
+        ex += compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k],
+                           rD[:, :k], rD[:, k], P=P, Q=Q[sel], live=masks[c][seen])
+    assert ex <= 2
     for c, (P, cl) in enumerate(clouds):
         assert cl.live_count == int(masks[c][-1].sum())
         assert cl.head == int(np.flatnonzero(masks[c][-1])[0])
@@ -229,6 +233,7 @@ def test_insertions_and_deletions_between_batches(env, plain):
     res = {t: srv.wait(t, with_seen=True) for _, t, *_ in log}
     srv.close()
     assert any(kind == "ins" for kind, *_ in log)
+    ex = 0
     for kind, t, c, Q, k, before in log:
         if kind != "knn":
             continue
@@ -238,8 +243,9 @@ def test_insertions_and_deletions_between_batches(env, plain):
         P = clouds[c][0][:n]
         sel = np.arange(min(100, Q.shape[0]))
         ri, _, rD = oracle.knn_bruteforce(P, Q[sel], k + 1, live=live[:n])
-        compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k], rD[:, :k],
-                     rD[:, k])
+        ex += compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k],
+                           rD[:, :k], rD[:, k], P=P, Q=Q[sel], live=live[:n])
+    assert ex <= 2
     for c, (P, cl) in enumerate(clouds):
         n, live = states[c][-1]
         assert cl.n == n and cl.live_count == int(live.sum())

@@ -38,8 +38,9 @@ def test_autotune_keeps_results(env, k, tmp_path):
     torch.cuda.synchronize()
     assert torch.equal(before[0], after[0]) and torch.equal(before[1], after[1])
     ri, _, rD = oracle.knn_bruteforce(P, Q[:2000], k + 1)
-    compare_rows(after[0].cpu().numpy()[:2000], after[1].cpu().numpy()[:2000], ri[:, :k],
-                 rD[:, :k], rD[:, k])
+    ex = compare_rows(after[0].cpu().numpy()[:2000], after[1].cpu().numpy()[:2000], ri[:, :k],
+                      rD[:, :k], rD[:, k], P=P, Q=Q[:2000])
+    assert ex <= 2
     path = tmp_path / "tune.txt"
     A.tune_save(str(path))
     assert len(path.read_text().splitlines()) == 2

@@ -136,3 +136,16 @@ def test_zero_distance_and_empty_batch(oracle_lib):
     assert idx[0].tolist() == [1, 2] and dist[0, 0] == 0.0 and D[0, 0] == 0.0
     idx, dist, D = oracle_lib.knn_bruteforce(P, np.zeros((0, 3), np.float32), 2)
     assert idx.shape == (0, 2)
+
+
+def test_work_counts_hand_trace():
+    """The work counts of the reference walk (entries examined E, lists opened Lambda, the
+    inputs of the algorithmic-byte figure) equal a hand-counted trace of Alg. 1 + Alg. 2."""
+    from oracle import dpknn
+    g = json.load(open(os.path.join(HERE, "golden", "dpknn_work_counts.json")))
+    P = np.array(g["points_by_rank"], dtype=np.float32)
+    for c in g["cases"]:
+        items, (E, lam) = dpknn.dp_knn(P, g["lists"], np.array(c["q"], np.float32), c["k"],
+                                       c["m"], count=True)
+        assert [r for _, r in items] == c["ranks"], c
+        assert (E, lam) == (c["E"], c["Lambda"]), c
