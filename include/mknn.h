@@ -115,6 +115,21 @@ int64_t mknn_device_bytes(const mknn_cloud *c);
 mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k, int32_t m,
                      int32_t *d_idx, float *d_dist, void *stream);
 
+/* mknn_knn_static: mknn_knn for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, rows and errors as mknn_knn, bit-identical results (the same kernels), but
+ * the query sort's scratch is a fixed array of the library on each GPU
+ * (64 Ki histogram bins + 16 bytes per query for at most 2^20 = 1,048,576 queries, about
+ * 16.3 MiB per GPU, held until the process ends) instead of stream-ordered allocations:
+ * the call makes no hipMalloc/hipFree and no allocating library call.  The array's device
+ * address is looked up on the first call on each device.  Every call on one GPU shares that
+ * GPU's array: calls whose work overlaps on one GPU (other streams, other threads) race on
+ * it and must be serialised by the caller; each call clears what must start at zero.
+ * Errors: as mknn_knn, and EINVAL for nq above 2^20.
+ */
+mknn_status mknn_knn_static(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
+                            int32_t m, int32_t *d_idx, float *d_dist, void *stream);
+
 /* mknn_knn_var: per-query k and prefix m with ragged output rows.
  *   d_k        device int32 [nq], each in [1, MKNN_KMAX]
  *   d_m        device int32 [nq], each in [1, n] (values above n are clamped to n)

@@ -667,16 +667,25 @@ static hipError_t dispatch_rows(const QueryArgs &a, int kmax, bool exact, int32_
   return hipErrorInvalidValue;
 }
 
-// Morton bucketing of the queries into stream-ordered scratch, for batches large enough
-// to pay for it.
+// Bytes of scratch the Morton bucketing of nq queries needs (0 below the sort threshold).
+static size_t sort_scratch_bytes(int64_t nq) {
+  return nq < kSortMinQueries ? 0 : sizeof(uint32_t) * kMortonBins + sizeof(float4) * (size_t)nq;
+}
+
+// Morton bucketing of the queries, for batches large enough to pay for it.  The scratch
+// (sort_scratch_bytes(nq), 256-byte aligned) comes from `fixed` when given, else from the
+// stream-ordered allocator (returned in *scratch for the caller to release).
 static mknn_status prepare_queries(const mknn_cloud *c, const float *d_q, int64_t nq,
-                                   hipStream_t s, float4 **qs_out, void **scratch) {
+                                   hipStream_t s, float4 **qs_out, void **scratch,
+                                   void *fixed = nullptr) {
   *qs_out = nullptr;
   *scratch = nullptr;
   if (nq < kSortMinQueries) return MKNN_OK;
-  size_t bytes = sizeof(uint32_t) * kMortonBins + sizeof(float4) * (size_t)nq;
-  HIP_TRY(hipMallocAsync(scratch, bytes, s), "query sort scratch");
-  uint32_t *hist = (uint32_t *)*scratch;
+  uint32_t *hist = (uint32_t *)fixed;
+  if (!hist) {
+    HIP_TRY(hipMallocAsync(scratch, sort_scratch_bytes(nq), s), "query sort scratch");
+    hist = (uint32_t *)*scratch;
+  }
   float4 *qs = (float4 *)(hist + kMortonBins);
   BoxArgs b = dev_box_of(c);
   const int threads = 256;
@@ -696,7 +705,7 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
                              const int64_t *d_row_off, int32_t kmax, int32_t *d_idx,
                              float *d_dist, int32_t *d_ce, int32_t *d_cl, int32_t *d_ci,
                              hipStream_t s, const char *who, const TuneConfig *force = nullptr,
-                             float *d_plane = nullptr) {
+                             float *d_plane = nullptr, void *fixed_scratch = nullptr) {
   QueryArgs a;
   fill_cloud_args(c, &a);
   a.q = d_q;
@@ -713,13 +722,14 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
   a.cnt_inserts = d_ci;
   void *scratch = nullptr;
   float4 *qs = nullptr;
-  mknn_status st = prepare_queries(c, d_q, nq, s, &qs, &scratch);
+  mknn_status st = prepare_queries(c, d_q, nq, s, &qs, &scratch, fixed_scratch);
   if (st != MKNN_OK) return st;
   a.qs = qs;
   const bool exact = (d_k == nullptr);
   const TuneConfig cfg = force ? *force : config_for(kmax, exact, c->dev_n);
   a.merge_min = cfg.merge_min;
-  hipError_t e = timing_mark(s, true);
+  // the allocation-free entry point records no timing events (they are created on demand)
+  hipError_t e = fixed_scratch ? hipSuccess : timing_mark(s, true);
   if (e == hipSuccess) {
     if (cfg.family == 1)
       e = d_ce ? dispatch_lane<true>(a, kmax, exact, s) : dispatch_lane<false>(a, kmax, exact, s);
@@ -728,7 +738,7 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
     else
       e = d_ce ? dispatch_group<true>(a, kmax, exact, s) : dispatch_group<false>(a, kmax, exact, s);
   }
-  if (e == hipSuccess) e = timing_mark(s, false);
+  if (e == hipSuccess && !fixed_scratch) e = timing_mark(s, false);
   // the plane fit reads the rows just written (and the sorted queries, for their order)
   if (e == hipSuccess && d_plane)
     e = launch_plane_fit((const float4 *)c->d_pts, d_idx, qs, nq, k, d_plane, s);
@@ -777,6 +787,39 @@ static mknn_status check_per_query(const int32_t *d_k, const int32_t *d_m, const
                                       "), m=" + std::to_string(m) + ", row length " +
                                       std::to_string(off[1] - off[0]));
   }
+  return MKNN_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Allocation-free variant of mknn_knn: the query sort's scratch is a fixed device array of
+// this translation unit (one copy per GPU, held until the process ends) instead of
+// stream-ordered allocations.  Host code never passes the array's name to a kernel: the
+// name is a host-side stand-in, and its device address comes from hipGetSymbolAddress, once
+// per device with that device current.
+// ---------------------------------------------------------------------------------------
+constexpr int64_t kStaticMaxQueries = (int64_t)1 << 20;
+constexpr size_t kStaticScratchBytes =
+    sizeof(uint32_t) * kMortonBins + sizeof(float4) * (size_t)kStaticMaxQueries;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device (looked up on the first call there).
+static mknn_status static_scratch(void **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "mknn_knn_static: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(MKNN_EUNSUPPORTED, "mknn_knn_static: device ordinal above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "mknn_knn_static: hipGetSymbolAddress");
+    if (!p) return set_error(MKNN_EHIP, "mknn_knn_static: scratch has no device address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
   return MKNN_OK;
 }
 
@@ -839,6 +882,30 @@ mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t 
   if (!d_q || !d_idx || !d_dist) return set_error(MKNN_EINVAL, "mknn_knn: NULL buffer");
   return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, d_idx, d_dist, nullptr,
                    nullptr, nullptr, (hipStream_t)stream, "mknn_knn");
+}
+
+mknn_status mknn_knn_static(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
+                            int32_t m, int32_t *d_idx, float *d_dist, void *stream) {
+  clear_error();
+  if (k > MKNN_KMAX) return set_error(MKNN_EUNSUPPORTED, "mknn_knn_static: k above MKNN_KMAX");
+  if (k < 1) return set_error(MKNN_EINVAL, "mknn_knn_static: k must be >= 1");
+  if (nq < 0 || nq > kStaticMaxQueries)
+    return set_error(MKNN_EINVAL, "mknn_knn_static: nq must be in [0, " +
+                                      std::to_string(kStaticMaxQueries) +
+                                      "] (the size of the fixed scratch)");
+  mknn_status st = check_uploaded(c, "mknn_knn_static");
+  if (st != MKNN_OK) return st;
+  if (m < 1 || m > c->dev_n) return set_error(MKNN_EINVAL, "mknn_knn_static: m must be in [1, n]");
+  if (nq == 0) return MKNN_OK;
+  if (!d_q || !d_idx || !d_dist) return set_error(MKNN_EINVAL, "mknn_knn_static: NULL buffer");
+  void *buf = nullptr;
+  st = static_scratch(&buf);
+  if (st != MKNN_OK) return st;
+  static_assert(kStaticScratchBytes >= sizeof(uint32_t) * kMortonBins + sizeof(float4) * (size_t)kStaticMaxQueries,
+                "scratch holds the sort of the largest batch");
+  return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, d_idx, d_dist, nullptr,
+                   nullptr, nullptr, (hipStream_t)stream, "mknn_knn_static", nullptr, nullptr,
+                   buf);
 }
 
 mknn_status mknn_knn_plane(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
