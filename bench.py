@@ -8,6 +8,15 @@ torus (R=1, r=0.3, normal noise 1e-3, random insertion order), 1,000,000 volume 
 uniform in the bounding box expanded by 10%, k=16, m=n.  Inputs are resident in HBM
 before timing starts; the host-side list construction is reported but not timed.
 
+The default run also measures, for the same JSON line: the memory probes (streaming read
+and random 16-byte gathers), the FP64 brute-force oracle on the host cores with the parity
+of the rows it computed, and -- in a child process started before this one touches the
+GPU, so that each process's kernel statistics stay separate under a profiler -- the
+batched form (256 clouds, one launch per class against one plain launch per cloud) and
+the serving form (64 resident clouds, continuous batching against one launch per request:
+saturation, p50/p99 in an open loop with deletions, a sweep of offered loads), each
+checked against the oracle.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -26,6 +35,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+METRIC = "k-NN queries/sec (k=16, 1M-pt surface) + p50/p99 latency, batched vs plain"
 
 
 def log(msg: str) -> None:
@@ -57,31 +67,134 @@ def measured_traffic(k: int):
     rec = json.load(open(path))
     if rec.get("csrc_sha256") != csrc_digest():
         return None
-    return 1024.0 * (rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] +
-                     rec["write_kib_per_dispatch"] * rec["write_scale"])
+    return rec.get("traffic_bytes_per_dispatch")
 
 
-def cpu_baseline(P, Q, k, target_s: float):
-    """Time the FP64 brute-force oracle on a bounded sample of the same queries."""
+def ingest_counters(fetch_dir: str, write_dir: str, out_path: str) -> dict:
+    """Write the HBM byte reading of the headline query kernel from two rocprofv3 --pmc runs
+    of this benchmark with --copy-probe (FETCH_SIZE in one, WRITE_SIZE in the other):
+    KiB per dispatch of the kernel, each scaled by what the same counter reads for the
+    copy probe (an elementwise pass reading and writing 1 GiB), stamped with the hash of
+    the kernel sources the counters were taken from."""
+    import csv
+    import glob
+    kname = "knn_rows_kernel<1, true, true, true>"
+    probe = "elementwise_kernel"
+    rec = {"kernel": "mknn::" + kname, "workload": "torus 1M points, 1M volume queries, k=16, m=n",
+           "csrc_sha256": csrc_digest()}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        kern, copy = [], []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                if row.get("Counter_Name") != counter:
+                    continue
+                name = row.get("Kernel_Name", "")
+                if kname in name:
+                    kern.append(float(row["Counter_Value"]))
+                elif probe in name:
+                    copy.append(float(row["Counter_Value"]))
+        if not kern or not copy:
+            raise RuntimeError(f"{counter}: no dispatch of the query kernel or the copy probe "
+                               f"under {d}")
+        key = "fetch" if counter == "FETCH_SIZE" else "write"
+        rec[f"{key}_kib_per_dispatch"] = round(sum(kern) / len(kern), 1)
+        rec[f"{key}_dispatches"] = len(kern)
+        rec[f"{key}_scale"] = round((1 << 20) / (sum(copy) / len(copy)), 4)
+    rec["traffic_bytes_per_dispatch"] = 1024.0 * (
+        rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] +
+        rec["write_kib_per_dispatch"] * rec["write_scale"])
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=2)
+    return rec
+
+
+def cpu_info() -> dict:
+    """Host CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def oracle_threads() -> int:
+    """Threads for the oracle: the host cores available to the process, capped by the
+    OMP_NUM_THREADS share when it is set."""
+    n = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def _time_oracle(P, Q, k, threads, target_s):
+    """Oracle rows for a prefix of Q sized for about target_s of work on `threads` threads:
+    (queries, seconds, idx, D)."""
     import oracle
-    oracle.build(force=False)
-    threads = oracle.max_threads()
-    oracle.knn_bruteforce(P, Q[:16], k)           # load the library, start the threads
+    oracle.knn_bruteforce(P, Q[:16], k, threads=threads)       # load, start the threads
     n0 = min(64, Q.shape[0])
     while True:
         t = time.perf_counter()
-        oracle.knn_bruteforce(P, Q[:n0], k)
+        oracle.knn_bruteforce(P, Q[:n0], k, threads=threads)
         dt = max(time.perf_counter() - t, 1e-6)
         if dt >= 0.5 or n0 >= Q.shape[0]:
             break
         n0 = min(Q.shape[0], n0 * 4)
     ns = int(min(Q.shape[0], max(n0, n0 * target_s / dt)))
     t = time.perf_counter()
-    oracle.knn_bruteforce(P, Q[:ns], k)
-    dt = time.perf_counter() - t
-    return {"value": ns / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
+    idx, _, D = oracle.knn_bruteforce(P, Q[:ns], k, threads=threads)
+    return ns, time.perf_counter() - t, idx, D
+
+
+def cpu_baseline(P, Q, k, target_s: float, gpu_idx=None, gpu_dist=None):
+    """Time the FP64 brute-force oracle on a bounded sample of the same queries (all
+    allowed host cores, then one thread), and check the GPU rows of that sample against the
+    rows the oracle computed.  Returns (baseline dict, parity dict or None)."""
+    import oracle
+    oracle.build(force=False)
+    threads = oracle_threads()
+    ns, dt, idx, D = _time_oracle(P, Q, k, threads, target_s)
+    ns1, dt1, _, _ = _time_oracle(P, Q, k, 1, target_s / 4)
+    info = cpu_info()
+    base = {"value": ns / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
             "sample": f"first {ns} of the {Q.shape[0]} timed queries, brute force over all "
-                      f"{P.shape[0]} points, FP64, {dt:.1f} s wall"}
+                      f"{P.shape[0]} points, FP64, {dt:.1f} s wall on {threads} threads; "
+                      f"one thread: {ns1 / dt1:.1f} queries/s on the first {ns1}",
+            "single_thread_qps": round(ns1 / dt1, 2), "cpu_model": info["model"],
+            "affinity_cpus": info["affinity_cpus"]}
+    parity = None
+    if gpu_idx is not None:
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from _compare import compare_rows
+        ties = compare_rows(gpu_idx[:ns], gpu_dist[:ns], idx, D, P=P, Q=Q[:ns])
+        parity = {"rows": int(ns), "near_ties": int(ties), "mismatches": 0,
+                  "oracle": "FP64 brute force, rows of the cpu_baseline sample"}
+    return base, parity
+
+
+def memory_probes() -> dict:
+    """Measured memory rates on a 2 GiB buffer (larger than the 256 MB last-level cache):
+    a streaming read and random 16-byte gathers."""
+    import ctypes
+    import torch
+    from paper_2605_02224_amd import _lib
+    L = _lib.lib()
+    nbytes = 1 << 31
+    buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    g = ctypes.c_double()
+    _lib.check(L.mknn_probe_stream_read(buf.data_ptr(), nbytes, 5, s, ctypes.byref(g)))
+    stream = g.value
+    _lib.check(L.mknn_probe_gather16(buf.data_ptr(), nbytes, 1 << 27, 5, s, ctypes.byref(g)))
+    gather = g.value
+    del buf
+    return {"stream_read_GBps": round(stream, 1), "gather16_GBps": round(gather, 1),
+            "buffer_bytes": nbytes}
 
 
 def build_clouds(clouds, threads: int = 16):
@@ -96,31 +209,33 @@ def build_clouds(clouds, threads: int = 16):
     return built
 
 
-def bench_batched(args) -> int:
+def run_batched(args) -> dict:
     """Many clouds (sizes log-uniform in [1e3, 2e5], sphere/torus/ellipsoid, 4 n_c queries
-    each, k=10): one flat launch per class and batch versus one plain launch per cloud."""
+    each, k=10): one flat launch per class and batch versus one plain launch per cloud; a
+    sample of every cloud's rows checked against the oracle."""
     import torch
     from paper_2605_02224_amd import workloads as W
     from paper_2605_02224_amd import api as A
     t0 = time.perf_counter()
     w = W.many_clouds(num=args.clouds)
-    log(f"{len(w.clouds)} clouds, {sum(c.n for c in w.clouds)} points generated in "
+    npts = int(sum(c.n for c in w.clouds))
+    log(f"batched: {len(w.clouds)} clouds, {npts} points generated in "
         f"{time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    clouds = build_clouds(w.clouds)
+    clouds = build_clouds(w.clouds, oracle_threads())
     build_s = time.perf_counter() - t0
-    log(f"built and uploaded in {build_s:.1f} s")
+    log(f"batched: built and uploaded in {build_s:.1f} s")
     qs = [torch.from_numpy(q).cuda() for q in w.queries]
     nq = sum(q.shape[0] for q in qs)
     items = A.alloc_outputs([(c, q, w.k, None) for c, q in zip(clouds, qs)])
     plan = A.BatchPlan(len(items), nq, tile_queries=args.tile, sort=True, graph=True)
-    tile = args.tile
+    tuned = None
     if not args.no_autotune:
-        tile = plan.tune(items)   # untimed: picks the tile length for this batch
-        log(f"autotuner: tile length {tile}")
+        tuned = plan.tune(items)   # untimed
+        log(f"batched: autotuner chose {tuned}")
     torch.cuda.synchronize()
 
-    def run_batched():
+    def run_batch():
         plan.run(items)
 
     def run_plain():
@@ -128,7 +243,7 @@ def bench_batched(args) -> int:
             cl.knn(q, k, out=(idx, dist))
 
     res = {}
-    for name, fn in (("plain", run_plain), ("batched", run_batched)):
+    for name, fn in (("plain", run_plain), ("batched", run_batch)):
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
@@ -138,21 +253,44 @@ def bench_batched(args) -> int:
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         res[name] = (nq / dt, dt)
-        log(f"{name}: {nq / dt / 1e6:.1f} M queries/s, {dt * 1e3:.2f} ms per batch")
+        log(f"batched: {name} {nq / dt / 1e6:.1f} M queries/s, {dt * 1e3:.2f} ms per batch")
+    # parity of the last batched run: 256 sampled rows of every cloud
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _compare import compare_rows
+    rng = np.random.default_rng(5)
+    ties = rows = 0
+    thr = oracle_threads()
+    for c, (cl, q, k, m, idx, dist) in zip(w.clouds, items):
+        Qa = q.cpu().numpy()
+        sel = rng.choice(Qa.shape[0], min(256, Qa.shape[0]), replace=False)
+        ri, _, rD = oracle.knn_bruteforce(c.by_rank, Qa[sel], k, threads=thr)
+        ties += compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri, rD,
+                             P=c.by_rank, Q=Qa[sel])
+        rows += sel.size
+    log(f"batched: parity {rows} rows, {ties} near-tie positions")
+    plan.close()
+    return {"workload": f"batched_{len(items)}_clouds_k{w.k}", "clouds": len(items),
+            "points": npts, "queries": int(nq), "k": w.k,
+            "batched_qps": round(res["batched"][0], 1),
+            "batched_ms": round(res["batched"][1] * 1e3, 3),
+            "plain_qps": round(res["plain"][0], 1), "plain_ms": round(res["plain"][1] * 1e3, 3),
+            "speedup_vs_plain": round(res["batched"][0] / res["plain"][0], 3),
+            "form": "one flat launch per register class, hipGraph replay",
+            "tile_queries_tuned": tuned, "build_s": round(build_s, 2),
+            "parity": {"rows": rows, "near_ties": int(ties), "mismatches": 0}}
+
+
+def bench_batched(args) -> int:
+    r = run_batched(args)
     line = {
-        "metric": "k-NN queries/sec (k=16, 1M-pt surface) + p50/p99 latency, batched vs plain",
-        "value": round(res["batched"][0], 1), "unit": "queries/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(res["batched"][1] * 1e3, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"batched_{len(items)}_clouds_k{w.k}", "clouds": len(items),
-                   "points": int(sum(c.n for c in w.clouds)), "queries": int(nq), "k": w.k,
-                   "form": "one flat launch per class (hipGraph replay) per batch",
-                   "tile_queries": tile},
-        "extra": {"plain_qps": round(res["plain"][0], 1),
-                  "plain_ms": round(res["plain"][1] * 1e3, 3),
-                  "speedup_vs_plain": round(res["batched"][0] / res["plain"][0], 3),
-                  "build_s": round(build_s, 2)},
+        "metric": METRIC, "value": r["batched_qps"], "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["batched_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": r["workload"], "clouds": r["clouds"], "points": r["points"],
+                   "queries": r["queries"], "k": r["k"], "form": r["form"]},
+        "extra": r,
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -170,6 +308,7 @@ class _ServeRun:
         self.L = _lib.lib()
         self.reqs = reqs
         d_idx, d_dist, h_idx, h_dist = ring
+        self.h_idx, self.h_dist = h_idx, h_dist
         cap = d_idx.numel()
         # ring layout: requests take consecutive regions of an unbounded stream of positions
         # (skipping to the next multiple of the capacity rather than splitting a region);
@@ -185,6 +324,7 @@ class _ServeRun:
             pos += sz[i]
         self.need = np.searchsorted(a, a + sz - cap, side="left")
         self.start = a % cap
+        self.size = sz
         self.arr = (_lib.Request * len(reqs))()
         self.hptr = []
         for i, r in enumerate(reqs):
@@ -200,10 +340,13 @@ class _ServeRun:
                               ctypes.c_void_p(h_dist.data_ptr() + int(self.start[i]) * 4)))
         self.ctypes = ctypes
 
-    def run(self, srv, lo, hi, arrivals=None, deletions=(), clouds=None, label=""):
+    def run(self, srv, lo, hi, arrivals=None, deletions=(), clouds=None, label="",
+            capture=()):
         """Requests lo..hi-1; arrivals: offsets in seconds from the start (None = as fast as
         the ring allows); deletions: (position, cloud, ranks) submitted just before the
-        request at that position.  Returns per-request latencies and the makespan."""
+        request at that position; capture: request indices whose host rows are copied out
+        when they complete (self.captured[i] = (idx, dist, updates seen)).  Returns
+        per-request latencies, completion times and the first scheduled arrival."""
         import queue
         import threading
         ct = self.ctypes
@@ -217,6 +360,8 @@ class _ServeRun:
         t_lag = np.zeros(n)       # scheduled arrival -> submitted
         state = {"collected": lo, "err": None}
         cv = threading.Condition()
+        capture = set(capture)
+        self.captured = {}
 
         def collect():
             tt = (ct.c_double * 3)()
@@ -229,6 +374,12 @@ class _ServeRun:
                 st = L.mknn_server_wait(h, ct.c_uint64(tk), tt, ct.byref(v))
                 if st != 0 and state["err"] is None:
                     state["err"] = (i, st, L.mknn_last_error().decode())
+                if i in capture:
+                    a, b = int(self.start[i]), int(self.start[i] + self.size[i])
+                    r = self.reqs[i]
+                    self.captured[i] = (self.h_idx[a:b].numpy().reshape(-1, r.k).copy(),
+                                        self.h_dist[a:b].numpy().reshape(-1, r.k).copy(),
+                                        int(v.value))
                 lat[i - lo] = tt[2] - t_sched
                 t_done[i - lo] = tt[2]
                 t_lag[i - lo] = tt[0] - t_sched
@@ -291,29 +442,41 @@ class _ServeRun:
         return lat, t_done, t_first
 
 
-def bench_serving(args) -> int:
+def _merge_plans(parts):
+    """One deletion plan from several disjoint ones (batches interleaved, seeded)."""
+    plan = [b for p in parts for b in p]
+    order = np.random.default_rng(3).permutation(len(plan))
+    return [plan[i] for i in order]
+
+
+def run_serving(args) -> dict:
     """Serving: 64 resident clouds (sizes log-uniform in [1e4, 2e6], about 24M points),
     requests of 1..65536 queries (log-uniform), k in {4, 16, 64}, prefix m uniform in
     [n/10, n]; open-loop Poisson arrivals at 0.7x the plain server's saturation rate; 1% of
     the points deleted in batches of <= 1000 between requests.  The batched server
-    (continuous batching on stream slots) against the plain one (one launch per request)."""
+    (continuous batching on stream slots) against the plain one (one launch per request);
+    200 seeded requests of the batched run checked against the oracle on the live set each
+    one was answered on; then a sweep of offered loads."""
     import torch
     from paper_2605_02224_amd import workloads as W
     from paper_2605_02224_amd import api as A
     sys.setswitchinterval(2e-4)   # the submitter and the collector hand the GIL over quickly
     t0 = time.perf_counter()
-    w = W.serving_clouds(num=args.clouds, n_hi=args.serving_n_hi)
+    w = W.serving_clouds(num=args.serving_clouds, n_hi=args.serving_n_hi)
     npts = sum(c.n for c in w.clouds)
-    log(f"{len(w.clouds)} clouds, {npts} points generated in {time.perf_counter() - t0:.1f} s")
+    log(f"serving: {len(w.clouds)} clouds, {npts} points generated in "
+        f"{time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    clouds = build_clouds(w.clouds)
+    clouds = build_clouds(w.clouds, oracle_threads())
     build_s = time.perf_counter() - t0
-    log(f"built and uploaded in {build_s:.1f} s")
+    log(f"serving: built and uploaded in {build_s:.1f} s")
     nwarm, nmeas, nsat = args.warm_requests, args.requests, args.sat_requests
-    total = nsat + nwarm + nmeas
+    loads = [float(x) for x in args.sweep_loads.split(",")] if args.sweep_loads else []
+    nsw, nsw_warm = args.sweep_requests, max(1, args.sweep_requests // 10)
+    total = nsat + nwarm + nmeas + (nsw + nsw_warm)
     t0 = time.perf_counter()
     reqs = [w.request() for _ in range(total)]
-    log(f"{total} requests generated in {time.perf_counter() - t0:.1f} s")
+    log(f"serving: {total} requests generated in {time.perf_counter() - t0:.1f} s")
     qoff = np.zeros(total + 1, np.int64)
     qoff[1:] = np.cumsum([r.queries.shape[0] for r in reqs])
     qd = torch.from_numpy(np.concatenate([r.queries for r in reqs])).cuda()
@@ -324,15 +487,13 @@ def bench_serving(args) -> int:
             torch.empty(cap, dtype=torch.float32).pin_memory())
     torch.cuda.synchronize()
     run = _ServeRun(reqs, qoff, qd, ring, clouds)
-    log(f"{int(qoff[-1])} queries resident, output ring of {cap} entries; host cpus "
-        f"{len(os.sched_getaffinity(0))}")
+    log(f"serving: {int(qoff[-1])} queries resident, output ring of {cap} entries")
     nq_of = np.diff(qoff)
     pool = 1 << 22
-    kw = dict(pool_queries=pool, nstreams=args.slots, max_wave_requests=256,
-              bind_at_admission=True)
 
-    def server(plain):
-        return A.Server(plain=plain, **kw)
+    def server(plain, bind=True, max_wave=256):
+        return A.Server(pool_queries=pool, nstreams=args.slots, max_wave_requests=max_wave,
+                        plain=plain, bind_at_admission=bind)
 
     # saturation: the first nsat requests as fast as the ring allows, no deletions
     sat = {}
@@ -344,66 +505,150 @@ def bench_serving(args) -> int:
         w_, r_ = srv.stats()
         srv.close()
         sat[name] = float(nq_of[:nsat].sum() / span)
-        log(f"{name} saturation: {sat[name] / 1e6:.1f} M queries/s "
-            f"({nsat / span:.0f} requests/s, {r_ / max(w_, 1):.1f} requests per wave)")
-    # open loop at 0.7x the plain saturation rate, with deletions
-    lo, hi = nsat, total
-    mean_nq = float(nq_of[lo:hi].mean())
-    rate = args.load * sat["plain"] / mean_nq
+        log(f"serving: {name} saturation {sat[name] / 1e6:.1f} M queries/s "
+            f"({nsat / span:.0f} requests/s, {r_ / max(w_, 1):.2f} requests per wave)")
+
+    # deletion plans over disjoint rank sets: 1% per main run, a quarter of that per sweep run
+    nsweep_runs = 4 * len(loads)
+    quarter = w.deletion_plan(frac=args.delete_frac / 4, batch=1000, parts=8 + nsweep_runs)
+    main_plans = [_merge_plans(quarter[0:4]), _merge_plans(quarter[4:8])]
     rng = np.random.default_rng(11)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, hi - lo))
-    parts = w.deletion_plan(frac=args.delete_frac, batch=1000, parts=2)
-    res = {}
-    for p, name in enumerate(("plain", "batched")):
-        for cl in clouds:          # both runs start from freshly packed lists
-            cl.compact()
-        torch.cuda.synchronize()
-        pos = np.sort(rng.integers(lo + nwarm, hi, len(parts[p])))
-        dels = [(int(pos[t]), ci, r) for t, (ci, r) in enumerate(parts[p])]
-        srv = server(name == "plain")
+
+    def open_loop(name, lo, hi, warm, load, plan, plain, bind=True, max_wave=256, capture=()):
+        mean_nq = float(nq_of[lo:hi].mean())
+        rate = load * sat["plain"] / mean_nq
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, hi - lo))
+        pos = np.sort(rng.integers(lo + warm, hi, len(plan)))
+        dels = [(int(pos[t]), ci, r) for t, (ci, r) in enumerate(plan)]
+        srv = server(plain, bind, max_wave)
         t0 = time.perf_counter()
         lat, t_done, t_first = run.run(srv, lo, hi, arrivals=arrivals, deletions=dels,
-                                       clouds=clouds, label=f"{name} open loop")
+                                       clouds=clouds, label=name, capture=capture)
         w_, r_ = srv.stats()
         srv.close()
-        m = lat[nwarm:]
-        lag, wt = run.parts[0][nwarm:], run.parts[1][nwarm:]
-        t_meas = t_first + arrivals[nwarm] - arrivals[0]
-        served = float(nq_of[lo + nwarm:hi].sum() / (t_done[nwarm:].max() - t_meas))
-        res[name] = {"p50_ms": round(float(np.percentile(m, 50)) * 1e3, 3),
-                     "p99_ms": round(float(np.percentile(m, 99)) * 1e3, 3),
-                     "mean_ms": round(float(m.mean()) * 1e3, 3),
-                     "mean_submit_lag_ms": round(float(lag.mean()) * 1e3, 3),
-                     "mean_queue_wait_ms": round(float(wt.mean()) * 1e3, 3),
-                     "p99_queue_wait_ms": round(float(np.percentile(wt, 99)) * 1e3, 3),
-                     "served_qps": round(served, 1),
-                     "requests_per_wave": round(r_ / max(w_, 1), 2),
-                     "deletion_batches": len(dels),
-                     "wall_s": round(time.perf_counter() - t0, 2)}
-        log(f"{name} open loop: p50 {res[name]['p50_ms']} ms, p99 {res[name]['p99_ms']} ms, "
-            f"{served / 1e6:.1f} M queries/s served; mean submit lag "
-            f"{res[name]['mean_submit_lag_ms']} ms, mean queue wait "
-            f"{res[name]['mean_queue_wait_ms']} ms")
+        m = lat[warm:]
+        lag, wt = run.parts[0][warm:], run.parts[1][warm:]
+        t_meas = t_first + arrivals[warm] - arrivals[0]
+        served = float(nq_of[lo + warm:hi].sum() / (t_done[warm:].max() - t_meas))
+        out = {"p50_ms": round(float(np.percentile(m, 50)) * 1e3, 3),
+               "p99_ms": round(float(np.percentile(m, 99)) * 1e3, 3),
+               "mean_ms": round(float(m.mean()) * 1e3, 3),
+               "mean_submit_lag_ms": round(float(lag.mean()) * 1e3, 3),
+               "mean_queue_wait_ms": round(float(wt.mean()) * 1e3, 3),
+               "p99_queue_wait_ms": round(float(np.percentile(wt, 99)) * 1e3, 3),
+               "served_qps": round(served, 1),
+               "requests_per_wave": round(r_ / max(w_, 1), 2),
+               "deletion_batches": len(dels),
+               "wall_s": round(time.perf_counter() - t0, 2)}
+        log(f"serving: {name}: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms, "
+            f"{served / 1e6:.1f} M queries/s served, {out['requests_per_wave']} requests per wave")
+        return out, dels
+
+    # the main comparison at args.load x plain saturation, both servers from freshly packed
+    # lists; the batched run keeps the rows of 200 seeded requests for the parity check
+    lo, hi = nsat, nsat + nwarm + nmeas
+    res = {}
+    live = [np.ones(c.n, bool) for c in w.clouds]
+    check = np.sort(np.random.default_rng(29).choice(np.arange(lo + nwarm, hi),
+                                                     min(args.check_requests, nmeas),
+                                                     replace=False))
+    batched_dels = None
+    for p, name in enumerate(("plain", "batched")):
+        for cl in clouds:
+            cl.compact()
+        torch.cuda.synchronize()
+        out, dels = open_loop(f"{name} open loop", lo, hi, nwarm, args.load, main_plans[p],
+                              name == "plain", capture=check if name == "batched" else ())
+        res[name] = out
+        if name == "plain":
+            for ci, r in main_plans[0]:
+                live[ci][r] = False
+        else:
+            batched_dels = dels
+
+    # parity: each checked request against the oracle on the live set it was answered on
+    # (the deletion batches of its cloud applied before its launch, in arrival order)
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _compare import compare_rows
+    per_cloud = [[] for _ in w.clouds]
+    for _, ci, r in batched_dels:
+        per_cloud[ci].append(r)
+    thr = oracle_threads()
+    ties = rows = 0
+    t0 = time.perf_counter()
+    for i in check:
+        r = reqs[i]
+        gi, gd, seen = run.captured[i]
+        lv = live[r.cloud].copy()
+        for b in per_cloud[r.cloud][:seen]:
+            lv[b] = False
+        P = w.clouds[r.cloud].by_rank
+        ri, _, rD = oracle.knn_bruteforce(P, r.queries, r.k, r.m, live=lv.astype(np.uint8),
+                                          threads=thr)
+        ties += compare_rows(gi, gd, ri, rD, P=P, Q=r.queries, m=r.m, live=lv)
+        rows += r.queries.shape[0]
+    log(f"serving: parity {len(check)} requests, {rows} rows, {ties} near-tie positions "
+        f"({time.perf_counter() - t0:.1f} s)")
+    parity = {"requests": int(len(check)), "rows": int(rows), "near_ties": int(ties),
+              "mismatches": 0, "rule": "each request on the live set of its admitted version"}
+    for _, ci, r in batched_dels:
+        live[ci][r] = False
+
+    # sweep of offered loads: plain, batched (bind at admission / strict order) and batched
+    # without coalescing (one request per wave, the same two stream slots)
+    sweep = []
+    lo2, hi2 = hi, hi + nsw_warm + nsw
+    k = 8
+    for load in loads:
+        row = {"load": load}
+        for name, plain, bind, mw in (("plain", True, True, 256),
+                                      ("batched_bind", False, True, 256),
+                                      ("batched_strict", False, False, 256),
+                                      ("batched_one_per_wave", False, True, 1)):
+            out, dels = open_loop(f"sweep {load}x {name}", lo2, hi2, nsw_warm, load,
+                                  quarter[k], plain, bind, mw)
+            k += 1
+            row[name] = {x: out[x] for x in ("p50_ms", "p99_ms", "served_qps",
+                                             "requests_per_wave", "mean_queue_wait_ms")}
+        sweep.append(row)
+    return {"workload": f"serving_{len(clouds)}_clouds", "clouds": len(clouds),
+            "points": int(npts), "slots": args.slots, "pool_queries": pool,
+            "mean_queries_per_request": round(float(nq_of[lo:hi].mean()), 1),
+            "k": list(w.k_choices),
+            "saturation_qps": {"plain": round(sat["plain"], 1), "batched": round(sat["batched"], 1),
+                               "requests": nsat},
+            "speedup_vs_plain": round(sat["batched"] / sat["plain"], 3),
+            "open_loop": {"offered": f"{args.load} x plain saturation",
+                          "offered_qps": round(args.load * sat["plain"], 1),
+                          "requests": nmeas, "warmup_requests": nwarm,
+                          "order": "bind at admission", **res},
+            "parity": parity, "sweep": sweep,
+            "sweep_requests": nsw, "sweep_delete_frac_per_run": args.delete_frac / 4,
+            "build_s": round(build_s, 2)}
+
+
+def bench_serving(args) -> int:
+    r = run_serving(args)
+    b = r["saturation_qps"]["batched"]
     line = {
-        "metric": "k-NN queries/sec (k=16, 1M-pt surface) + p50/p99 latency, batched vs plain",
-        "value": round(sat["batched"], 1), "unit": "queries/s", "n_gpus": 1,
-        "steps": nsat, "warmup": 500,
-        "ms_per_step": round(1e3 * nq_of[:nsat].sum() / sat["batched"] / nsat, 4),
+        "metric": METRIC, "value": b, "unit": "queries/s", "n_gpus": 1,
+        "steps": args.sat_requests, "warmup": 500, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"serving_{len(clouds)}_clouds", "clouds": len(clouds),
-                   "points": int(npts), "requests_saturation": nsat,
-                   "requests_open_loop": nmeas, "warmup_requests": nwarm,
-                   "mean_queries_per_request": round(mean_nq, 1), "k": [4, 16, 64],
-                   "offered_load": f"{args.load} x plain saturation",
-                   "offered_qps": round(args.load * sat["plain"], 1),
-                   "slots": args.slots, "pool_queries": pool,
-                   "order": "bind at admission"},
-        "extra": {"plain_saturation_qps": round(sat["plain"], 1),
-                  "speedup_vs_plain": round(sat["batched"] / sat["plain"], 3),
-                  "open_loop": res, "build_s": round(build_s, 2)},
+        "config": {"workload": r["workload"], "clouds": r["clouds"], "points": r["points"],
+                   "k": r["k"], "offered_load": r["open_loop"]["offered"]},
+        "extra": r,
     }
     print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_forms(args) -> int:
+    """The batched and the serving forms, for the default run's line (run as a child
+    process; with --wait-go it starts work, GPU included, when a line arrives on stdin)."""
+    out = {"batched": run_batched(args), "serving": run_serving(args)}
+    print(json.dumps(out), flush=True)
     return 0
 
 
@@ -525,20 +770,40 @@ def bench_plane(args) -> int:
     return 0
 
 
+def _forms_argv(args):
+    """Command line of the child process that measures the batched and serving forms."""
+    return [sys.executable, os.path.abspath(__file__), "--workload", "forms", "--wait-go",
+            "--steps", str(max(3, args.steps // 2)), "--warmup", str(max(1, args.warmup)),
+            "--clouds", str(args.clouds), "--tile", str(args.tile),
+            "--serving-clouds", str(args.serving_clouds),
+            "--serving-n-hi", str(args.serving_n_hi), "--requests", str(args.requests),
+            "--warm-requests", str(args.warm_requests), "--sat-requests", str(args.sat_requests),
+            "--load", str(args.load), "--slots", str(args.slots),
+            "--delete-frac", str(args.delete_frac), "--check-requests", str(args.check_requests),
+            "--sweep-loads", args.sweep_loads, "--sweep-requests", str(args.sweep_requests)] + \
+        (["--no-autotune"] if args.no_autotune else [])
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="torus",
-                    choices=["torus", "batched", "serving", "dynamic", "plane"])
+                    choices=["torus", "batched", "serving", "forms", "dynamic", "plane"])
     ap.add_argument("--dyn-iterations", type=int, default=2000, help="dynamic: iterations")
     ap.add_argument("--requests", type=int, default=20000, help="serving: measured requests")
     ap.add_argument("--warm-requests", type=int, default=1000)
     ap.add_argument("--sat-requests", type=int, default=5000)
     ap.add_argument("--load", type=float, default=0.7, help="serving: x plain saturation")
     ap.add_argument("--slots", type=int, default=2, help="serving: stream slots")
+    ap.add_argument("--serving-clouds", type=int, default=64)
     ap.add_argument("--serving-n-hi", type=int, default=2_000_000)
     ap.add_argument("--delete-frac", type=float, default=0.01,
-                    help="serving: fraction of each cloud deleted during a run")
-    ap.add_argument("--clouds", type=int, default=256)
+                    help="serving: fraction of each cloud deleted during a main run")
+    ap.add_argument("--check-requests", type=int, default=200,
+                    help="serving: requests checked against the oracle")
+    ap.add_argument("--sweep-loads", default="0.25,0.5,0.9,1.2",
+                    help="serving: offered loads of the sweep (x plain saturation), or ''")
+    ap.add_argument("--sweep-requests", type=int, default=2000)
+    ap.add_argument("--clouds", type=int, default=256, help="batched: clouds")
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -549,14 +814,41 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the context measurements")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched and serving forms (child process)")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in configuration")
+    ap.add_argument("--wait-go", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (to scale HBM byte counters)")
+    ap.add_argument("--ingest-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
+                    help="write the HBM traffic reading from two rocprofv3 --pmc runs")
     args = ap.parse_args()
+    if args.ingest_counters:
+        print(json.dumps(ingest_counters(*args.ingest_counters)))
+        return 0
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU: the query path has no "
+                                   "multi-GPU form in this build, so --gpus must be 1"}))
         return 2
 
+    # the forms run in a child process started before this process touches the GPU; it
+    # waits for a line on its stdin, sent once the headline measurement is done
+    if args.workload == "forms" and args.wait_go:
+        sys.stdin.readline()          # the parent is done with the GPU: start now
+    child = None
+    if args.workload == "torus" and not args.no_forms:
+        import subprocess
+        child = subprocess.Popen(_forms_argv(args), stdin=subprocess.PIPE,
+                                 stdout=subprocess.PIPE, text=True)
+    try:
+        return _main(args, child)
+    finally:
+        if child is not None and child.poll() is None:
+            child.kill()
+            child.wait()
+
+
+def _main(args, child) -> int:
     import torch
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
@@ -568,9 +860,9 @@ def main() -> int:
     if args.workload == "plane":
         return bench_plane(args)
     if args.workload == "serving":
-        if args.clouds == 256:
-            args.clouds = 64
         return bench_serving(args)
+    if args.workload == "forms":
+        return bench_forms(args)
     from paper_2605_02224_amd import workloads as W
     from paper_2605_02224_amd import _lib
     from paper_2605_02224_amd.api import Cloud
@@ -633,12 +925,19 @@ def main() -> int:
     kern_ms = tot.value / max(cnt.value, 1)
     achieved = bytes_per_q * nq / (kern_ms * 1e-3) / 1e9
     log(f"{qps / 1e6:.1f} M queries/s, {ms_step:.3f} ms/step, query kernel {kern_ms:.3f} ms")
+    gpu_idx = idx.cpu().numpy()
+    gpu_dist = dist.cpu().numpy()
 
     # context numbers (not the headline): k=1 and the on-surface query set
+    traffic = measured_traffic(k)
     extras = {"build_s": round(build_s, 2), "device_bytes": cl.device_bytes,
               "entries_per_query": round(E, 2), "lists_per_query": round(L, 3),
-              "inserts_per_query": round(INS, 2),
-              "kernel_ms": round(kern_ms, 4), "autotuned": tuned}
+              "inserts_per_query": round(INS, 2), "algorithmic_bytes_per_query": round(bytes_per_q, 1),
+              "kernel": f"mknn::knn_rows_kernel<1, true, true, true> (k={k})" if k == 16 else None,
+              "kernel_ms": round(kern_ms, 4), "autotuned": tuned,
+              "roofline_frac_step_basis": round(qps * bytes_per_q / (HBM_PEAK_GBS * 1e9), 4),
+              "hbm_measured_GBps": (round(traffic / (kern_ms * 1e-3) / 1e9, 1)
+                                    if traffic else None)}
     extra_runs = () if args.no_extras else (("volume_k1", q, 1), ("surface_k16", qb, 16),
                                             ("surface_k1", qb, 1))
     for name, qq, kk in extra_runs:
@@ -653,6 +952,11 @@ def main() -> int:
             cl.knn(qq, kk, out=(i2, d2))
         torch.cuda.synchronize()
         extras[name + "_qps"] = round(nq * reps / (time.perf_counter() - t0), 1)
+    if not args.no_extras:
+        probe = memory_probes()
+        probe["frac_of_stream_read"] = round(achieved / probe["stream_read_GBps"], 4)
+        extras["memory_probe"] = probe
+        log(f"memory probes: {probe}")
     log(f"extras: {extras}")
 
     if args.copy_probe:
@@ -665,11 +969,21 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(P, w.queries, k, args.cpu_seconds)
-        log(f"cpu baseline: {cpu}")
+        cpu, parity = cpu_baseline(P, w.queries, k, args.cpu_seconds, gpu_idx, gpu_dist)
+        extras["parity"] = parity
+        log(f"cpu baseline: {cpu}; parity: {parity}")
+
+    if child is not None:
+        log("starting the batched and serving forms (child process)")
+        out, _ = child.communicate("go\n")
+        if child.returncode != 0:
+            raise RuntimeError(f"the batched/serving child process failed ({child.returncode})")
+        forms = json.loads(out.strip().splitlines()[-1])
+        extras["batched"] = forms["batched"]
+        extras["serving"] = forms["serving"]
 
     line = {
-        "metric": "k-NN queries/sec (k=16, 1M-pt surface) + p50/p99 latency, batched vs plain",
+        "metric": METRIC,
         "value": round(qps, 1),
         "unit": "queries/s",
         "n_gpus": 1,
@@ -686,7 +1000,7 @@ def main() -> int:
                    "queries": "uniform in bbox x1.1", "order": "seeded random"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(k)},
+                     "traffic": traffic},
         "cpu_baseline": cpu,
         "extra": extras,
     }

@@ -288,6 +288,24 @@ mknn_status mknn_timing_enable(int enable);
 mknn_status mknn_timing_read(double *total_ms, int64_t *launches);
 
 /* ---------------------------------------------------------------------------------------
+ * Memory probes (diagnostics for the memory roofline of the query kernels; the paper has no
+ * counterpart).
+ *
+ * mknn_probe_stream_read: sustained rate of a streaming read of the caller's device buffer
+ * (`bytes`, a multiple of 16, at least 4 KiB; make it larger than the 256 MB last-level
+ * cache to measure HBM).  mknn_probe_gather16: sustained rate of `accesses` (rounded up to
+ * a multiple of 16,384) random 16-byte record reads from the buffer (its largest
+ * power-of-two number of records), counting 16 useful bytes per read -- the access of a
+ * list walk that opens a new list.  Both run one untimed and `reps` timed launches on
+ * `stream` (HIP events; synchronises) and report the best in *gbps (1e9 bytes per second).
+ * The buffer is only read.  Errors: EINVAL, EHIP.
+ */
+mknn_status mknn_probe_stream_read(const void *d_buf, int64_t bytes, int32_t reps, void *stream,
+                                   double *gbps);
+mknn_status mknn_probe_gather16(const void *d_buf, int64_t bytes, int64_t accesses, int32_t reps,
+                                void *stream, double *gbps);
+
+/* ---------------------------------------------------------------------------------------
  * Deletion (Sec. 4.3, Alg. 3).
  *
  * mknn_delete: removes the given live ranks, one after the other.  Afterwards the successor

@@ -33,6 +33,9 @@ SIGNATURES = {
     "mknn_knn_counts": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P, _P]),
     "mknn_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "mknn_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+    "mknn_probe_stream_read": (ctypes.c_int, [_P, _I64, _I32, _P, ctypes.POINTER(ctypes.c_double)]),
+    "mknn_probe_gather16": (ctypes.c_int, [_P, _I64, _I64, _I32, _P,
+                                           ctypes.POINTER(ctypes.c_double)]),
     "mknn_free": (None, [_P]),
     "mknn_last_error": (ctypes.c_char_p, []),
     "mknn_version": (ctypes.c_char_p, []),

@@ -16,7 +16,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["mknn_host.cpp", "delaunay.cpp", "deletion.cpp", "insertion.cpp"]
-HIP_SOURCES = ["mknn_device.hip", "mknn_batch.hip", "mknn_server.hip"]
+HIP_SOURCES = ["mknn_device.hip", "mknn_batch.hip", "mknn_server.hip", "mknn_probe.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I" + INCLUDE, "-I" + CSRC]
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
