@@ -177,11 +177,14 @@ def test_256_clouds_paper_scale_sampled(env):
     plan.close()
 
 
-def test_waves_moving_between_clouds_of_very_different_size(env):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_waves_moving_between_clouds_of_very_different_size(env, persistent):
     """Wavefronts take tiles of one request after another; rows idle at a switch still hold
     the descriptor of the previous request's cloud, which must never be used to address the
     next cloud's (much smaller) arena.  Tiny clouds interleaved with a large one, small
-    tiles, and every result checked against the oracle."""
+    tiles, and every result checked against the oracle -- in the default flat launch and in
+    the persistent tile-claiming launch, where a wavefront does change request."""
+    import os
     torch, oracle, A, W, clouds = env
     rng = np.random.default_rng(41)
     big = W.random_cloud(120000, seed=42, shape="torus").by_rank
@@ -198,7 +201,12 @@ def test_waves_moving_between_clouds_of_very_different_size(env):
             items.append((cl, torch.from_numpy(Q).cuda(), k, 0))
             host.append((P, Q, k, 0))
     items = A.alloc_outputs(items)
-    plan = A.BatchPlan(len(items), 20000, tile_queries=4, sort=True, graph=False)
+    if persistent:
+        os.environ["MKNN_BATCH_PERSISTENT"] = "1"
+    try:
+        plan = A.BatchPlan(len(items), 20000, tile_queries=4, sort=True, graph=False)
+    finally:
+        os.environ.pop("MKNN_BATCH_PERSISTENT", None)
     plan.run(items)
     torch.cuda.synchronize()
     assert _check(env, items, host) <= 3
