@@ -251,6 +251,108 @@ struct RowWalker {
       }
     }
   }
+
+  // One slot per lane, descent steps first (S == 1, DESCENT_FIRST): the two kinds of step
+  // below do what step<true> does, each with only the work its rows need.  While some row
+  // of the wavefront is in its descent only those rows advance, and they offer nothing to
+  // N (the transition sites go to the ring); once no row is, every busy row expands.
+
+  // A step while some row is in its descent.
+  __device__ __forceinline__ void step_descent(const QueryArgs &a, const float4 *ent,
+                                               const uint64_t *lst, int l, int g, int32_t uk,
+                                               int32_t um) {
+    static_assert(S == 1, "descent-only steps serve one slot per lane");
+    const int32_t k = EXACTK ? 16 : (UNIFORM ? uk : this->k);
+    const int32_t m = UNIFORM ? um : this->m;
+    const bool desc = phase == kRowDescent;
+    const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
+    const uint32_t e = base + (uint32_t)l;
+    const float4 c = ent[st + e];   // in bounds for every lane: see step()
+    const int32_t r = __float_as_int(c.w);
+    const bool valid = desc && e < len && r < m;
+    const double dx = (double)qx - (double)c.x, dy = (double)qy - (double)c.y,
+                 dz = (double)qz - (double)c.z;
+    const double dv = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    const uint32_t vmask = row_bits(__ballot(valid), g);
+    const uint32_t jm = row_bits(__ballot(valid && dv < dcur), g);
+    if (jm) {
+      // the first strictly closer entry is the next transition site (Alg. 1)
+      const int j = __ffs(jm) - 1;
+      dcur = __shfl(dv, j, 16);
+      cur = __shfl(r, j, 16);
+      if (l == (ntrans & 15)) {
+        ring_d(a)[l] = dcur;
+        ring_r(a)[l] = cur;
+      }
+      ++ntrans;
+      dsc = lst[cur];
+      base = 0;
+    } else if (desc) {
+      if (vmask == 0xffffu && base + 16 < len) {
+        base += 16;   // the next chunk of a long list
+      } else {
+        // the descent ends at p_cur: N starts as the last transition sites, nearest first,
+        // and the final list is scanned again as the expansion of N[0]
+        const int have = ntrans < 16 ? ntrans : 16;
+        const int src = (ntrans - 1 - l) & 15;
+        N.d[0] = l < have ? ring_d(a)[src] : INFINITY;
+        N.r[0] = l < have ? ring_r(a)[src] : kEmpty;
+        N.refresh_threshold(k);
+        od = dcur;
+        orr = cur;
+        if (k == 1) {
+          finish(a, l, k);
+        } else {
+          phase = kRowExpand;
+          it = 0;
+          base = 0;
+        }
+      }
+    }
+  }
+
+  // A step while no row is in its descent: every busy row scans a chunk of the list of N's
+  // slot `it` and offers the entries above that slot's key and not above the k-th key.  The
+  // two tests compare D only: an entry tied in D with the owner but of smaller rank is
+  // already in N, and one tied with the k-th key but of larger rank lands past the last
+  // slot, so offering them changes nothing.
+  __device__ __forceinline__ void step_expand(const QueryArgs &a, const float4 *ent,
+                                              const uint64_t *lst, int merge_min, int l, int g,
+                                              int32_t uk, int32_t um) {
+    static_assert(S == 1, "expansion-only steps serve one slot per lane");
+    const int32_t k = EXACTK ? 16 : (UNIFORM ? uk : this->k);
+    const int32_t m = UNIFORM ? um : this->m;
+    const bool act = phase != kRowIdle;
+    const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
+    const uint32_t e = base + (uint32_t)l;
+    const float4 c = ent[st + e];
+    const int32_t r = __float_as_int(c.w);
+    const bool valid = act && e < len && r < m;
+    const double dx = (double)qx - (double)c.x, dy = (double)qy - (double)c.y,
+                 dz = (double)qz - (double)c.z;
+    const double dv = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    const uint32_t vmask = row_bits(__ballot(valid), g);
+    const bool cand = valid && dv >= od && dv <= N.thr_d;
+    offer_all(N, cand, dv, r, l, g, k, merge_min);
+    if (act) {
+      if (vmask == 0xffffu && base + 16 < len) {
+        base += 16;
+      } else {
+        ++it;
+        int32_t pr = kEmpty;
+        double pd = 0;
+        if (it < k - 1) N.slot(it, pd, pr);
+        if (pr != kEmpty) {
+          od = pd;
+          orr = pr;
+          dsc = lst[pr];
+          base = 0;
+        } else {
+          finish(a, l, k);
+        }
+      }
+    }
+  }
 };
 
 // Plain launch: a wavefront owns `per_wave` consecutive sorted queries; row g takes
@@ -270,8 +372,15 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
   if constexpr (DESCENT_FIRST) {
     // 4 queries per wavefront: each row takes its one query and runs it to the end
     if (begin + g < end) w.begin(a, begin + g, l);
-    while (__ballot(w.phase != kRowIdle) != 0)
-      w.template step<true>(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
+    if constexpr (S == 1) {
+      while (__ballot(w.phase == kRowDescent) != 0)
+        w.step_descent(a, a.ent, a.lst, l, g, a.k, m);
+      while (__ballot(w.phase != kRowIdle) != 0)
+        w.step_expand(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
+    } else {
+      while (__ballot(w.phase != kRowIdle) != 0)
+        w.template step<true>(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
+    }
   } else {
     int64_t next = begin + g;
     for (;;) {
