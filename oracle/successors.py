@@ -1,11 +1,11 @@
 """Brute-force successor lists -- TEST INFRASTRUCTURE ONLY (never used by the product path).
 
-Definition (Sec. 3, successor lists; Fig. 2 caption): for birth-ordered points
-p_0, p_1, ... (0-based ranks), rank j > i belongs to the successor list L_i iff inserting p_j
-prunes the Voronoi cell of p_i in the diagram of the prefix {p_0..p_j}.  Pruning means the
-cell loses a part of positive volume, which happens exactly when, in the diagram of
-{p_0..p_j}, the cells of p_i and p_j share a facet of positive area.  Each list is therefore
-ascending in rank.
+Definition (Sec. 3, successor lists; Fig. 2 caption): for points ordered by birth,
+p_0, p_1, ... (0-based ranks), the list L_i holds the younger ranks j > i whose arrival cut
+away part of the Voronoi cell p_i had among the points born before p_j.  A cell loses a part
+of positive volume to p_j exactly when, in the Voronoi diagram of {p_0..p_j}, the cells of
+p_i and p_j meet in a facet of positive area -- the test implemented below.  Ranks are
+appended in birth order, so each list ascends.
 
 Exact test for one pair: the shared facet lies in the bisector plane of p_i, p_j, and it has
 positive area iff some point x of that plane is strictly closer to p_i (equivalently p_j)

@@ -252,17 +252,19 @@ struct RowWalker {
     }
   }
 
-  // One slot per lane, descent steps first (S == 1, DESCENT_FIRST): the two kinds of step
-  // below do what step<true> does, each with only the work its rows need.  While some row
-  // of the wavefront is in its descent only those rows advance, and they offer nothing to
-  // N (the transition sites go to the ring); once no row is, every busy row expands.
+  // Descent steps first (DESCENT_FIRST): the two kinds of step below do what step<true>
+  // does, each with only the work its rows need.  While some row of the wavefront is in its
+  // descent only those rows advance; once no row is, every busy row expands.  With one slot
+  // per lane the descent offers nothing to N (the transition sites go to the ring); with
+  // more, a jumping row offers its transition site and a row that does not jump offers the
+  // chunk (a long list that jumps later, or the final list, which is then Alg. 2's first
+  // iteration).
 
   // A step while some row is in its descent.
   __device__ __forceinline__ void step_descent(const QueryArgs &a, const float4 *ent,
                                                const uint64_t *lst, int l, int g, int32_t uk,
-                                               int32_t um) {
-    static_assert(S == 1, "descent-only steps serve one slot per lane");
-    const int32_t k = EXACTK ? 16 : (UNIFORM ? uk : this->k);
+                                               int32_t um, int merge_min = 0) {
+    const int32_t k = EXACTK ? 16 * S : (UNIFORM ? uk : this->k);
     const int32_t m = UNIFORM ? um : this->m;
     const bool desc = phase == kRowDescent;
     const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
@@ -275,21 +277,33 @@ struct RowWalker {
     const double dv = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
     const uint32_t vmask = row_bits(__ballot(valid), g);
     const uint32_t jm = row_bits(__ballot(valid && dv < dcur), g);
+    if constexpr (S > 1) {
+      // tested against the k-th key on D only: an entry tied with it but of larger rank
+      // lands past the last slot
+      const int j = jm ? __ffs(jm) - 1 : 0;
+      const bool cand = (jm ? l == j : valid) && dv <= N.thr_d;
+      offer_all(N, cand, dv, r, l, g, k, merge_min);
+    }
     if (jm) {
       // the first strictly closer entry is the next transition site (Alg. 1)
       const int j = __ffs(jm) - 1;
       dcur = __shfl(dv, j, 16);
       cur = __shfl(r, j, 16);
-      if (l == (ntrans & 15)) {
-        ring_d(a)[l] = dcur;
-        ring_r(a)[l] = cur;
+      if constexpr (S == 1) {
+        if (l == (ntrans & 15)) {
+          ring_d(a)[l] = dcur;
+          ring_r(a)[l] = cur;
+        }
+        ++ntrans;
       }
-      ++ntrans;
       dsc = lst[cur];
       base = 0;
     } else if (desc) {
       if (vmask == 0xffffu && base + 16 < len) {
         base += 16;   // the next chunk of a long list
+      } else if constexpr (S > 1) {
+        // the final list has been offered: the expansion continues with N[1]'s list
+        next_list(a, lst, l, k, 1);
       } else {
         // the descent ends at p_cur: N starts as the last transition sites, nearest first,
         // and the final list is scanned again as the expansion of N[0]
@@ -319,8 +333,7 @@ struct RowWalker {
   __device__ __forceinline__ void step_expand(const QueryArgs &a, const float4 *ent,
                                               const uint64_t *lst, int merge_min, int l, int g,
                                               int32_t uk, int32_t um) {
-    static_assert(S == 1, "expansion-only steps serve one slot per lane");
-    const int32_t k = EXACTK ? 16 : (UNIFORM ? uk : this->k);
+    const int32_t k = EXACTK ? 16 * S : (UNIFORM ? uk : this->k);
     const int32_t m = UNIFORM ? um : this->m;
     const bool act = phase != kRowIdle;
     const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
@@ -335,22 +348,28 @@ struct RowWalker {
     const bool cand = valid && dv >= od && dv <= N.thr_d;
     offer_all(N, cand, dv, r, l, g, k, merge_min);
     if (act) {
-      if (vmask == 0xffffu && base + 16 < len) {
+      if (vmask == 0xffffu && base + 16 < len)
         base += 16;
-      } else {
-        ++it;
-        int32_t pr = kEmpty;
-        double pd = 0;
-        if (it < k - 1) N.slot(it, pd, pr);
-        if (pr != kEmpty) {
-          od = pd;
-          orr = pr;
-          dsc = lst[pr];
-          base = 0;
-        } else {
-          finish(a, l, k);
-        }
-      }
+      else
+        next_list(a, lst, l, k, it + 1);
+    }
+  }
+
+  // Expand the list of N's slot `nit` next, or finish the query when there is none.
+  __device__ __forceinline__ void next_list(const QueryArgs &a, const uint64_t *lst, int l,
+                                            int32_t k, int32_t nit) {
+    it = nit;
+    phase = kRowExpand;
+    int32_t pr = kEmpty;
+    double pd = 0;
+    if (it < k - 1) N.slot(it, pd, pr);
+    if (pr != kEmpty) {
+      od = pd;
+      orr = pr;
+      dsc = lst[pr];
+      base = 0;
+    } else {
+      finish(a, l, k);
     }
   }
 };
@@ -372,15 +391,10 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
   if constexpr (DESCENT_FIRST) {
     // 4 queries per wavefront: each row takes its one query and runs it to the end
     if (begin + g < end) w.begin(a, begin + g, l);
-    if constexpr (S == 1) {
-      while (__ballot(w.phase == kRowDescent) != 0)
-        w.step_descent(a, a.ent, a.lst, l, g, a.k, m);
-      while (__ballot(w.phase != kRowIdle) != 0)
-        w.step_expand(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
-    } else {
-      while (__ballot(w.phase != kRowIdle) != 0)
-        w.template step<true>(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
-    }
+    while (__ballot(w.phase == kRowDescent) != 0)
+      w.step_descent(a, a.ent, a.lst, l, g, a.k, m, a.merge_min);
+    while (__ballot(w.phase != kRowIdle) != 0)
+      w.step_expand(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
   } else {
     int64_t next = begin + g;
     for (;;) {

@@ -253,7 +253,10 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
       if (exhausted && preq < 0) return;
       continue;
     }
-    w.template step<true>(reqs[req], ent, lst, merge_min, l, g, rk, rm);
+    if (__ballot(w.phase == kRowDescent) != 0)
+      w.step_descent(reqs[req], ent, lst, l, g, rk, rm, merge_min);
+    else
+      w.step_expand(reqs[req], ent, lst, merge_min, l, g, rk, rm);
   }
 }
 
@@ -293,8 +296,10 @@ void knn_batch_flat_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
   RowWalker<S, false, (S == 1), true> w;
   w.N.init();
   if (begin + g < end) w.begin(a, begin + g, l);
+  while (__ballot(w.phase == kRowDescent) != 0)
+    w.step_descent(a, a.ent, a.lst, l, g, a.k, m, a.merge_min);
   while (__ballot(w.phase != kRowIdle) != 0)
-    w.template step<true>(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
+    w.step_expand(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
 }
 
 // The persistent tile-claiming kernel instead of the flat one (MKNN_BATCH_PERSISTENT=1 in
