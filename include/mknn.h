@@ -60,9 +60,14 @@ typedef enum {
  *   order  host int32 [n] permutation: rank r is the caller's point order[r];
  *          NULL means the identity (rank r = row r).
  *   out    receives a new cloud handle; release it with mknn_free().
+ * Prefixes that span only a line or a plane are handled as the lists define them (Sec. 3):
+ * cells of collinear points are slabs and cells of coplanar points prisms, so a rank joins
+ * the lists of its neighbours on that line or in that plane, and the first rank off the
+ * line (plane) joins the list of every older rank; a cloud may stay planar or collinear
+ * throughout.  Deletion and insertion on such a cloud rebuild local triangulations that
+ * need four affinely independent points and return EUNSUPPORTED where they have none.
  * Errors: EINVAL (n < 1, NULL xyz/out, order not a permutation), ENONFINITE, EDUPLICATE,
- * EUNSUPPORTED (the first four ranks are coplanar, so the prefix diagram starts
- * degenerate), ENOMEM.
+ * EUNSUPPORTED (internal construction failure), ENOMEM.
  */
 mknn_status mknn_build(const float *xyz, int64_t n, const int32_t *order, mknn_cloud **out);
 

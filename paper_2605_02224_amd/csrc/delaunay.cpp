@@ -2,6 +2,7 @@
 #include "delaunay.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "exact.h"
@@ -241,8 +242,9 @@ bool DelaunayBuilder::init_first_tet() {
   }
   for (int i = 0; i < 4; ++i) vtet_[v[i]] = t;
   // lists: with four affinely independent sites every pair is Voronoi-adjacent
-  for (int j = 1; j < 4; ++j)
-    for (int i = 0; i < j; ++i) append(order_[i], order_[j]);
+  if (!quiet_start_)
+    for (int j = 1; j < 4; ++j)
+      for (int i = 0; i < j; ++i) append(order_[i], order_[j]);
   nbrs_.assign(order_.begin(), order_.begin() + 3);
   std::sort(nbrs_.begin(), nbrs_.end());
   ninserted_ = 4;
@@ -380,9 +382,100 @@ BuildStatus DelaunayBuilder::insert_next() {
     }
   }
   std::sort(nbrs_.begin(), nbrs_.end());
-  for (int32_t i : nbrs_) append(i, j);
+  if (nreal_ < 0) {
+    for (int32_t i : nbrs_) append(i, j);
+  } else {
+    // low-dimensional start: the start's later ranks and the spare points are no list owners
+    for (int32_t i : nbrs_)
+      if (i < j) append(i, j);
+  }
   ++ninserted_;
   ++live_;
+  return kBuildOk;
+}
+
+BuildStatus DelaunayBuilder::low_dim_plan(double *pts, int64_t nreal, int32_t *A, int32_t *B,
+                                          int64_t *bad) {
+  const double *p0 = pts, *p1 = pts + 3;
+  if (p0[0] == p1[0] && p0[1] == p1[1] && p0[2] == p1[2]) {
+    *bad = 1;
+    return kBuildDuplicate;
+  }
+  auto collinear = [&](const double *q) {
+    for (int k = 0; k < 3; ++k)
+      if (cross_component_sign(p0, p1, q, k) != 0) return false;
+    return true;
+  };
+  // a length comparable to the cloud, for the spare points
+  double ext = 0;
+  for (int64_t r = 1; r < nreal; ++r)
+    for (int k = 0; k < 3; ++k) ext = std::max(ext, std::fabs(pts[3 * r + k] - p0[k]));
+  if (!(ext > 0)) ext = 1;
+  double *va = pts + 3 * nreal, *vb = pts + 3 * (nreal + 1);
+  *A = -1;
+  for (int64_t j = 2; j < nreal && *A < 0; ++j)
+    if (!collinear(pts + 3 * j)) *A = (int32_t)j;
+  if (*A < 0) {
+    for (int k = 0; k < 3 && *A < 0; ++k) {
+      for (int m = 0; m < 3; ++m) va[m] = p0[m];
+      va[k] += ext;
+      if (!collinear(va)) *A = (int32_t)nreal;
+    }
+    if (*A < 0) return kBuildInternal;
+  }
+  const double *pa = pts + 3 * (int64_t)(*A);
+  *B = -1;
+  for (int64_t j = 2; j < nreal && *B < 0; ++j)
+    if (j != *A && orient3d(p0, p1, pa, pts + 3 * j) != 0) *B = (int32_t)j;
+  if (*B < 0) {
+    for (int k = 0; k < 3 && *B < 0; ++k)
+      for (int sgn = 0; sgn < 2 && *B < 0; ++sgn) {
+        for (int m = 0; m < 3; ++m) vb[m] = p0[m];
+        vb[k] += sgn ? -ext : ext;
+        if (orient3d(p0, p1, pa, vb) != 0) *B = (int32_t)(nreal + 1);
+      }
+    if (*B < 0) return kBuildInternal;
+  }
+  return kBuildOk;
+}
+
+BuildStatus DelaunayBuilder::build_low_dim(int64_t nreal, int32_t A, int32_t B, int64_t *bad_rank) {
+  if (ninserted_ != 0 || n_ != nreal + 2 || nreal < 2) return kBuildInternal;
+  nreal_ = nreal;
+  order_.clear();
+  order_.push_back(0);
+  order_.push_back(1);
+  order_.push_back(A);
+  order_.push_back(B);
+  for (int32_t v = 2; v < (int32_t)nreal; ++v)
+    if (v != A && v != B) order_.push_back(v);
+  ascending_ = false;
+  quiet_start_ = true;
+  if (!init_first_tet()) return kBuildInternal;
+  quiet_start_ = false;
+  append(0, 1);   // two sites: the bisector plane is their common facet
+  // A and B (when they are ranks) take every older rank once the ranks before them are in
+  bool a_done = A >= nreal, b_done = B >= nreal;
+  auto flush = [&](int64_t next) {
+    for (int pass = 0; pass < 2; ++pass) {
+      const int32_t x = pass == 0 ? std::min(A, B) : std::max(A, B);
+      bool &done = (x == A) ? a_done : b_done;
+      if (!done && x < next) {
+        for (int32_t i = 0; i < x; ++i) append(i, x);
+        done = true;
+      }
+    }
+  };
+  while (ninserted_ < (int64_t)order_.size()) {
+    const int32_t j = order_[ninserted_];
+    flush(j);
+    BuildStatus s = insert_next();
+    if (s != kBuildOk) {
+      if (bad_rank) *bad_rank = j;
+      return s;
+    }
+  }
+  flush(nreal);
   return kBuildOk;
 }
 

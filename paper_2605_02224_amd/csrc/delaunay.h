@@ -41,6 +41,24 @@ class DelaunayBuilder {
   // Inserts rank j (j == number inserted so far); used by build() and by incremental use.
   BuildStatus insert_next();
 
+  // Clouds whose first four ranks are coplanar (or collinear): the lists are defined for
+  // every prefix (Sec. 3) -- while the prefix spans a line or a plane, the Voronoi cells are
+  // slabs or prisms over the cells of that line or plane.  low_dim_plan picks the start:
+  // A = the first rank off the line of ranks 0 and 1, B = the first rank off the plane of
+  // ranks 0, 1 and A; when there is none, a spare point (ids nreal, nreal + 1 of pts, which
+  // the caller reserves) is placed off the line or plane instead.  Returns kBuildDuplicate
+  // (*bad = 1) if ranks 0 and 1 coincide.
+  static BuildStatus low_dim_plan(double *pts, int64_t nreal, int32_t *A, int32_t *B,
+                                  int64_t *bad);
+  // Builds the lists of ranks 0 .. nreal-1 (the builder holds nreal + 2 points) starting from
+  // the tetrahedron (0, 1, A, B).  A rank j on the line or in the plane is then inserted
+  // with A and B already present; its neighbours of smaller rank are exactly its neighbours
+  // in the diagram of the prefix (the cone over the line's or plane's triangulation has no
+  // other edges between them), and A and B take their own list entries when their turn
+  // comes: every older rank, since a point off the line (plane) of the older ones is a
+  // Voronoi neighbour of each of them.  Spare points never enter a list.
+  BuildStatus build_low_dim(int64_t nreal, int32_t A, int32_t B, int64_t *bad_rank);
+
   int64_t inserted() const { return ninserted_; }
 
   // Successor lists as CSR (entries ascending within each list).
@@ -135,6 +153,8 @@ class DelaunayBuilder {
   // the perturbation ranks vertices by insertion; with an ascending order that is the id
   int32_t rank_of(int32_t v) const { return v; }
   std::vector<char> done_;
+  int64_t nreal_ = -1;              // build_low_dim: ids >= nreal_ are spare points
+  bool quiet_start_ = false;        // init_first_tet records no list entries
   int32_t nearest_inserted(const double *p, double *dbest) const;
   int32_t locate(int32_t near, const double *p);
   void append(int32_t owner, int32_t rank);

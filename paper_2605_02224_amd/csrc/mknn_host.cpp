@@ -130,18 +130,38 @@ mknn_status mknn_build(const float *xyz, int64_t n, const int32_t *order, mknn_c
                                               std::to_string(c->order[bad]) +
                                               " duplicates an earlier point");
       }
+      Csr succ;
       if (s == kBuildDegenerateStart) {
-        delete c;
-        return set_error(MKNN_EUNSUPPORTED,
-                         "mknn_build: the first four ranks are coplanar; the construction "
-                         "needs an affinely independent start");
+        // the first four ranks are coplanar: start from the first ranks off their line and
+        // plane (or spare points off them) and record the lists of the low-dimensional prefix
+        std::vector<double> P2(P);
+        P2.resize(3 * (size_t)(n + 2));
+        int32_t A = -1, B = -1;
+        s = DelaunayBuilder::low_dim_plan(P2.data(), n, &A, &B, &bad);
+        if (s == kBuildOk) {
+          DelaunayBuilder b2(P2.data(), n + 2);
+          s = b2.build_low_dim(n, A, B, &bad);
+          if (s == kBuildOk) {
+            succ = b2.successors();
+            succ.off.resize(n + 1);   // the spare points own no entries
+            succ.ent.resize(succ.off[n]);
+          }
+        }
+        if (s == kBuildDuplicate) {
+          delete c;
+          return set_error(MKNN_EDUPLICATE, "mknn_build: point " +
+                                                std::to_string(c->order[bad]) +
+                                                " duplicates an earlier point");
+        }
+      } else if (s == kBuildOk) {
+        succ = b.successors();
       }
       if (s != kBuildOk) {
         delete c;
         return set_error(MKNN_EUNSUPPORTED, "mknn_build: internal failure at rank " +
                                                 std::to_string(bad));
       }
-      c->succ = b.successors();
+      c->succ = std::move(succ);
     }
     transpose(c->succ, n, &c->pred);
     c->live.assign(n, 1);

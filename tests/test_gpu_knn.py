@@ -268,3 +268,24 @@ def test_per_query_arguments_rejected(env):
     assert st == -1 and b"query 299 " in L.mknn_last_error()
     torch.cuda.synchronize()
     assert (idx == -7).all()                   # nothing was written
+
+
+def test_low_dimensional_clouds(env):
+    """Clouds that start (or stay) in a line or a plane: a planar cloud of 20,000 points,
+    and a cloud whose first ranks are collinear, then coplanar, then in general position."""
+    torch, oracle, A = env
+    rng = np.random.default_rng(23)
+    P1 = np.zeros((20000, 3), np.float32)
+    P1[:, :2] = rng.uniform(-1, 1, (20000, 2))
+    a = np.zeros((50, 3), np.float32)
+    a[:, 0] = rng.uniform(-1, 1, 50)
+    b = np.zeros((500, 3), np.float32)
+    b[:, :2] = rng.uniform(-1, 1, (500, 2))
+    c = rng.uniform(-1, 1, (10000, 3)).astype(np.float32)
+    P2 = np.concatenate([a, b, c])
+    for P in (P1, P2):
+        cl = A.Cloud.build(P).upload()
+        Q = rng.uniform(-1.2, 1.2, (9000, 3)).astype(np.float32)
+        Q[:3000, 2] = 0.0
+        for k, m in ((1, None), (8, None), (16, 300), (33, None)):
+            assert _run(env, cl, P, Q, k, m) <= 2

@@ -138,10 +138,16 @@ def test_errors(api):
         api.Cloud.build(Q)
     assert e.value.status == ENONFINITE
     Q = P.copy()
-    Q[:4, 2] = 0.0     # first four ranks coplanar
+    Q[:3] = Q[0]       # a duplicate among the first, low-dimensional ranks
     with pytest.raises(MknnError) as e:
         api.Cloud.build(Q)
-    assert e.value.status == EUNSUPPORTED
+    assert e.value.status == EDUPLICATE
+    Q = P.copy()
+    Q[:6, 2] = 0.0     # coplanar start, then a duplicate of rank 0
+    Q[7] = Q[0]
+    with pytest.raises(MknnError) as e:
+        api.Cloud.build(Q)
+    assert e.value.status == EDUPLICATE
     with pytest.raises(MknnError) as e:
         api.Cloud.build(P, np.zeros(50, np.int32))
     assert e.value.status == EINVAL
@@ -200,3 +206,82 @@ def test_confirmed_prefix_property_20k(api):
                         assert c in order[:i], (m, q, i, c)
                         checked += 1
     assert checked > 1000
+
+
+def _low_dim_clouds():
+    """Clouds whose first ranks span only a line or a plane (Sec. 3 defines the lists for
+    every prefix): (name, points, exact) -- exact=False where cocircular ties allow weak
+    adjacencies."""
+    rng = np.random.default_rng(17)
+    out = []
+    # a plane z = 0 in general position, then the whole cloud stays in it
+    P = np.zeros((40, 3), np.float32)
+    P[:, :2] = rng.uniform(-1, 1, (40, 2))
+    out.append(("plane z=0", P, True))
+    # collinear on a tilted line (integer multiples of (1, 2, 3))
+    t = rng.permutation(np.arange(-12, 13))[:20].astype(np.float32)
+    out.append(("tilted line", np.stack([t, 2 * t, 3 * t], 1).astype(np.float32), True))
+    # collinear prefix, then points of a plane through the line, then 3-D points
+    a = np.zeros((5, 3), np.float32)
+    a[:, 0] = rng.uniform(-1, 1, 5)
+    b = np.zeros((10, 3), np.float32)
+    b[:, :2] = rng.uniform(-1, 1, (10, 2))
+    c = rng.uniform(-1, 1, (20, 3)).astype(np.float32)
+    out.append(("line, plane, space", np.concatenate([a, b, c]), True))
+    # a tilted integer plane z = x + 2y: many cocircular quadruples
+    xy = rng.permutation([(x, y) for x in range(-4, 5) for y in range(-4, 5)])[:35]
+    P = np.array([(x, y, x + 2 * y) for x, y in xy], np.float32)
+    out.append(("integer plane z = x + 2y", P, False))
+    # a coplanar start of four ranks, the rest in general position
+    P = rng.uniform(-1, 1, (35, 3)).astype(np.float32)
+    P[:4, 2] = 0.25
+    out.append(("four coplanar first", P, True))
+    return out
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_low_dimensional_starts(api, case):
+    """Clouds whose first four (or all) ranks are coplanar or collinear build, their lists
+    are the exact brute-force lists (between facet and weak adjacency where cocircular ties
+    exist), and walking them answers k-NN exactly."""
+    import oracle
+    name, P, exact = _low_dim_clouds()[case]
+    L = api.Cloud.build(P).lists()
+    strong = S.successor_lists(P)
+    if exact:
+        assert L == strong, name
+    else:
+        weak = S.weakly_adjacent_pairs_at_insertion(P)
+        for i in range(len(L)):
+            assert set(strong[i]) <= set(L[i]), name
+            assert all(i in weak[j] for j in L[i]), name
+            assert L[i] == sorted(L[i])
+    rng = np.random.default_rng(case)
+    lo, hi = P.min(0) - 0.5, P.max(0) + 0.5
+    Q = rng.uniform(lo, hi, (200, 3)).astype(np.float32)
+    Q[:10] = P[:10]
+    for k in (1, 5, 12):
+        ref, _, _ = oracle.knn_bruteforce(P, Q, k)
+        idx, _, _, _ = dpknn.dp_knn_batch(P, L, Q, k)
+        assert (idx == ref).all(), (name, k)
+
+
+def test_low_dimensional_large_planar_cloud(api):
+    """A planar cloud of 20,000 points (the plane z = 0, float32-exact) builds in bounded
+    time and its lists answer k-NN exactly (Theorem 1) against brute force."""
+    import time
+    import oracle
+    rng = np.random.default_rng(5)
+    xy = rng.uniform(-1, 1, (20000, 2)).astype(np.float32)
+    P = np.stack([xy[:, 0], xy[:, 1], np.zeros(20000, np.float32)], 1).astype(np.float32)
+    t0 = time.perf_counter()
+    cl = api.Cloud.build(P)
+    assert time.perf_counter() - t0 < 30
+    L = cl.lists()
+    assert all(L[i] == sorted(L[i]) and (not L[i] or L[i][0] > i) for i in range(len(L)))
+    Q = np.concatenate([rng.uniform(-1.2, 1.2, (300, 3)), P[:20]]).astype(np.float32)
+    Q[:150, 2] = 0.0
+    for k in (1, 8, 20):
+        ref, _, _ = oracle.knn_bruteforce(P, Q, k)
+        idx, _, _, _ = dpknn.dp_knn_batch(P, L, Q, k)
+        assert (idx == ref).all(), k
