@@ -232,21 +232,32 @@ def run_batched(args) -> dict:
     nq = sum(q.shape[0] for q in qs)
     items = A.alloc_outputs([(c, q, w.k, None) for c, q in zip(clouds, qs)])
     plan = A.BatchPlan(len(items), nq, tile_queries=args.tile, sort=True, graph=True)
-    tuned = None
+    os.environ["MKNN_BATCH_PERSISTENT"] = "1"     # read at plan creation
+    try:
+        pplan = A.BatchPlan(len(items), nq, tile_queries=args.tile, sort=True, graph=True)
+    finally:
+        os.environ.pop("MKNN_BATCH_PERSISTENT", None)
+    tuned = ptuned = None
     if not args.no_autotune:
-        tuned = plan.tune(items)   # untimed
-        log(f"batched: autotuner chose {tuned}")
+        tuned = plan.tune(items)     # untimed: merge threshold of the flat launch
+        ptuned = pplan.tune(items)   # untimed: tile length of the persistent launch
+        log(f"batched: autotuner chose merge threshold {tuned} (flat), tile {ptuned} "
+            f"(persistent)")
     torch.cuda.synchronize()
 
     def run_batch():
         plan.run(items)
+
+    def run_persistent():
+        pplan.run(items)
 
     def run_plain():
         for cl, q, k, m, idx, dist in items:
             cl.knn(q, k, out=(idx, dist))
 
     res = {}
-    for name, fn in (("plain", run_plain), ("batched", run_batch)):
+    for name, fn in (("plain", run_plain), ("persistent", run_persistent),
+                     ("batched", run_batch)):
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
@@ -273,14 +284,19 @@ def run_batched(args) -> dict:
         rows += sel.size
     log(f"batched: parity {rows} rows, {ties} near-tie positions")
     plan.close()
+    pplan.close()
     return {"workload": f"batched_{len(items)}_clouds_k{w.k}", "clouds": len(items),
             "points": npts, "queries": int(nq), "k": w.k,
             "batched_qps": round(res["batched"][0], 1),
             "batched_ms": round(res["batched"][1] * 1e3, 3),
             "plain_qps": round(res["plain"][0], 1), "plain_ms": round(res["plain"][1] * 1e3, 3),
             "speedup_vs_plain": round(res["batched"][0] / res["plain"][0], 3),
-            "form": "one flat launch per register class, hipGraph replay",
-            "tile_queries_tuned": tuned, "build_s": round(build_s, 2),
+            "persistent_qps": round(res["persistent"][0], 1),
+            "persistent_ms": round(res["persistent"][1] * 1e3, 3),
+            "form": "one flat launch per register class, hipGraph replay (the persistent "
+                    "work-stealing launch beside it)",
+            "merge_min_tuned": tuned, "persistent_tile_tuned": ptuned,
+            "build_s": round(build_s, 2),
             "parity": {"rows": rows, "near_ties": int(ties), "mismatches": 0}}
 
 

@@ -201,12 +201,16 @@ mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries,
 mknn_status mknn_batch_plan_run(mknn_batch_plan *plan, const mknn_request *reqs, int32_t nreq,
                                 void *stream);
 
-/* Autotuner of the batched form's persistent launch (MKNN_BATCH_PERSISTENT=1): runs the
- * batch with tile lengths 8, 16, 32, 64 and 256 (three timed runs each, HIP events on
- * `stream`), keeps the fastest as the plan's tile length and reports it.  The outputs hold
- * the batch's results afterwards. */
+/* Autotuner of the plan's own launch, on this batch (three timed runs per candidate after a
+ * warm-up, HIP events on `stream`).  Flat launch (the default): the merge threshold of
+ * every register class with work (candidates per chunk from which the merge network
+ * replaces one-by-one insertion: 4, 6, 8 for k <= 16; 5, 8, 11, 14, 17 above), one class
+ * at a time; the plan keeps the fastest per class, and *best receives the threshold of the
+ * class with the most queries.  Persistent launch: the tile length (8, 16, 32, 64, 256);
+ * the plan keeps the fastest and *best receives it.  The outputs hold the batch's results
+ * afterwards. */
 mknn_status mknn_batch_plan_tune(mknn_batch_plan *plan, const mknn_request *reqs, int32_t nreq,
-                                 void *stream, int32_t *best_tile);
+                                 void *stream, int32_t *best);
 
 /* Release a plan (waits for its last run). */
 void mknn_batch_plan_destroy(mknn_batch_plan *plan);

@@ -260,7 +260,9 @@ class BatchPlan:
         check(_lib.lib().mknn_batch_plan_run(self._h, self._keep, len(items), _stream(stream)))
 
     def tune(self, items, stream=None) -> int:
-        """Pick the fastest tile length for batches like this one; returns it."""
+        """Tune the plan's launch on batches like this one: the merge thresholds of the flat
+        launch (returns the threshold of the class with most queries) or the tile length of
+        the persistent launch (returns it)."""
         self._keep = _requests(items)
         t = ctypes.c_int32()
         check(_lib.lib().mknn_batch_plan_tune(self._h, self._keep, len(items), _stream(stream),

@@ -45,7 +45,9 @@ __device__ __forceinline__ void offer_all(RowTopK<S, EXACTK> &N, bool cand, doub
     N.insert_each(cand, dd, rr, l, g, k);
 }
 
-constexpr int32_t kRowDescent = 0, kRowExpand = 1, kRowIdle = 2;
+// kRowSettle (one slot per lane, descent steps first): the descent has ended and N is
+// still to be seeded from the ring (settle()).
+constexpr int32_t kRowDescent = 0, kRowExpand = 1, kRowIdle = 2, kRowSettle = 3;
 
 // Per-row rings of transition sites (k <= 16), 16 entries for each of the 16 rows of a
 // 256-thread workgroup (every launch of these kernels uses 256 threads).  In LDS rather
@@ -305,23 +307,31 @@ struct RowWalker {
         // the final list has been offered: the expansion continues with N[1]'s list
         next_list(a, lst, l, k, 1);
       } else {
-        // the descent ends at p_cur: N starts as the last transition sites, nearest first,
-        // and the final list is scanned again as the expansion of N[0]
-        const int have = ntrans < 16 ? ntrans : 16;
-        const int src = (ntrans - 1 - l) & 15;
-        N.d[0] = l < have ? ring_d(a)[src] : INFINITY;
-        N.r[0] = l < have ? ring_r(a)[src] : kEmpty;
-        N.refresh_threshold(k);
-        od = dcur;
-        orr = cur;
-        if (k == 1) {
-          finish(a, l, k);
-        } else {
-          phase = kRowExpand;
-          it = 0;
-          base = 0;
-        }
+        phase = kRowSettle;   // the descent ends at p_cur; N is seeded by settle()
       }
+    }
+  }
+
+  // One slot per lane: a row whose descent has ended at p_cur starts N as the last
+  // transition sites, nearest first, and scans the final list again as the expansion of
+  // N[0].  Called once no row is in its descent (kept out of the descent steps, whose loop
+  // then carries fewer values).
+  __device__ __forceinline__ void settle(const QueryArgs &a, int l, int32_t uk) {
+    const int32_t k = EXACTK ? 16 : (UNIFORM ? uk : this->k);
+    if (phase != kRowSettle) return;
+    const int have = ntrans < 16 ? ntrans : 16;
+    const int src = (ntrans - 1 - l) & 15;
+    N.d[0] = l < have ? ring_d(a)[src] : INFINITY;
+    N.r[0] = l < have ? ring_r(a)[src] : kEmpty;
+    N.refresh_threshold(k);
+    od = dcur;
+    orr = cur;
+    if (k == 1) {
+      finish(a, l, k);
+    } else {
+      phase = kRowExpand;
+      it = 0;
+      base = 0;
     }
   }
 
@@ -393,6 +403,7 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
     if (begin + g < end) w.begin(a, begin + g, l);
     while (__ballot(w.phase == kRowDescent) != 0)
       w.step_descent(a, a.ent, a.lst, l, g, a.k, m, a.merge_min);
+    if constexpr (S == 1) w.settle(a, l, a.k);
     while (__ballot(w.phase != kRowIdle) != 0)
       w.step_expand(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
   } else {

@@ -253,10 +253,15 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
       if (exhausted && preq < 0) return;
       continue;
     }
-    if (__ballot(w.phase == kRowDescent) != 0)
+    if (__ballot(w.phase == kRowDescent) != 0) {
       w.step_descent(reqs[req], ent, lst, l, g, rk, rm, merge_min);
-    else
-      w.step_expand(reqs[req], ent, lst, merge_min, l, g, rk, rm);
+    } else {
+      if constexpr (S == 1) {
+        if (__ballot(w.phase == kRowSettle) != 0) w.settle(reqs[req], l, rk);
+      }
+      if (__ballot(w.phase != kRowIdle) != 0)
+        w.step_expand(reqs[req], ent, lst, merge_min, l, g, rk, rm);
+    }
   }
 }
 
@@ -298,6 +303,7 @@ void knn_batch_flat_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
   if (begin + g < end) w.begin(a, begin + g, l);
   while (__ballot(w.phase == kRowDescent) != 0)
     w.step_descent(a, a.ent, a.lst, l, g, a.k, m, a.merge_min);
+  if constexpr (S == 1) w.settle(a, l, a.k);
   while (__ballot(w.phase != kRowIdle) != 0)
     w.step_expand(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
 }
@@ -349,6 +355,7 @@ struct mknn_batch_plan {
   uint32_t grid_batch[kClasses] = {1, 1, 1, 1};
   uint32_t grid_flat = 8;           // flat launch: blocks for the capacity (a multiple of 8)
   bool persistent = false;          // the persistent kernel instead of the flat one
+  int32_t merge_min[kClasses] = {0, 0, 0, 0};   // per class (S - 1); 0 = the autotuner's table
   uint32_t classes = 0xF;           // register classes that plan_enqueue launches (bit S-1)
   uint32_t graph_classes = 0;       // the classes the captured graph launches
   uint32_t grid_stream = 1;
@@ -600,7 +607,9 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   for (int32_t r = 0; r < nreq; ++r) {
     const mknn_request &q = reqs[r];
     fill_cloud_args(q.cloud, &args[r]);
-    args[r].merge_min = config_for(q.k, false, q.cloud->dev_n).merge_min;
+    const int cls = (q.k + 15) / 16 - 1;
+    args[r].merge_min = p->merge_min[cls] > 0 ? p->merge_min[cls]
+                                               : config_for(q.k, false, q.cloud->dev_n).merge_min;
     args[r].q = q.d_q;
     args[r].qs = p->sort ? p->d_qs + qoff[r] : nullptr;
     args[r].nq = q.nq;
@@ -652,19 +661,16 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
 }
 
 mknn_status mknn_batch_plan_tune(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
-                                 void *stream, int32_t *best_tile) {
+                                 void *stream, int32_t *best) {
   clear_error();
   if (!p) return set_error(MKNN_EINVAL, "mknn_batch_plan_tune: plan is NULL");
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0), "mknn_batch_plan_tune: event");
   hipError_t e = hipEventCreate(&e1);
-  const int32_t keep = p->tile_q;
-  int32_t best = keep;
-  float best_ms = INFINITY;
   mknn_status st = MKNN_OK;
-  for (int32_t t : {8, 16, 32, 64, 256}) {
-    p->tile_q = t;
+  // best of three timed runs after a warm-up
+  auto time_batch = [&](float *ms) {
     float tm = INFINITY;
     for (int rep = 0; rep < 4 && e == hipSuccess && st == MKNN_OK; ++rep) {
       e = hipEventRecord(e0, s);
@@ -676,18 +682,62 @@ mknn_status mknn_batch_plan_tune(mknn_batch_plan *p, const mknn_request *reqs, i
       if (e == hipSuccess) e = hipEventElapsedTime(&v, e0, e1);
       if (e == hipSuccess && rep > 0) tm = std::min(tm, v);
     }
-    if (st != MKNN_OK || e != hipSuccess) break;
-    if (tm < best_ms) {
-      best_ms = tm;
-      best = t;
+    *ms = tm;
+  };
+  int32_t report = 0;
+  if (p->persistent) {
+    // the persistent launch: the tile length
+    const int32_t keep = p->tile_q;
+    int32_t bt = keep;
+    float best_ms = INFINITY;
+    for (int32_t t : {8, 16, 32, 64, 256}) {
+      p->tile_q = t;
+      float tm;
+      time_batch(&tm);
+      if (st != MKNN_OK || e != hipSuccess) break;
+      if (tm < best_ms) {
+        best_ms = tm;
+        bt = t;
+      }
     }
+    p->tile_q = (st == MKNN_OK && e == hipSuccess) ? bt : keep;
+    report = p->tile_q;
+  } else {
+    // the flat launch: the merge threshold of every register class with work, one class at
+    // a time (the others at their current value); the class with most queries is reported
+    int64_t q_of[kClasses] = {0, 0, 0, 0};
+    for (int32_t r = 0; r < nreq; ++r)
+      if (reqs[r].k >= 1 && reqs[r].k <= MKNN_KMAX) q_of[(reqs[r].k + 15) / 16 - 1] += reqs[r].nq;
+    int top = 0;
+    for (int c = 1; c < kClasses; ++c)
+      if (q_of[c] > q_of[top]) top = c;
+    static const int32_t cand1[] = {4, 6, 8}, candS[] = {5, 8, 11, 14, 17};
+    for (int c = 0; c < kClasses && st == MKNN_OK && e == hipSuccess; ++c) {
+      if (!q_of[c]) continue;
+      const int32_t keep = p->merge_min[c];
+      int32_t bm = keep;
+      float best_ms = INFINITY;
+      const int32_t *cv = c == 0 ? cand1 : candS;
+      const int ncv = c == 0 ? 3 : 5;
+      for (int t = 0; t < ncv; ++t) {
+        p->merge_min[c] = cv[t];
+        float tm;
+        time_batch(&tm);
+        if (st != MKNN_OK || e != hipSuccess) break;
+        if (tm < best_ms) {
+          best_ms = tm;
+          bm = cv[t];
+        }
+      }
+      p->merge_min[c] = (st == MKNN_OK && e == hipSuccess) ? bm : keep;
+    }
+    report = p->merge_min[top];
   }
   (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  p->tile_q = (st == MKNN_OK && e == hipSuccess) ? best : keep;
   if (st != MKNN_OK) return st;
   if (e != hipSuccess) return set_error(MKNN_EHIP, std::string("mknn_batch_plan_tune: ") + hipGetErrorName(e));
-  if (best_tile) *best_tile = best;
+  if (best) *best = report;
   return MKNN_OK;
 }
 

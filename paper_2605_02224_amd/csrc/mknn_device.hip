@@ -533,9 +533,9 @@ static long env_long(const char *name, long dflt) {
 }
 
 // Defaults measured on the 1M torus: scheduled rows, one query per row, and the merge
-// network from 6 / 9 / 11 / 14 candidates per chunk for S = 1..4 slots per lane.
+// network from 6 / 9 / 10 / 11 candidates per chunk for S = 1..4 slots per lane.
 static TuneConfig default_config(int S) {
-  static const int32_t mm[4] = {6, 9, 11, 14};
+  static const int32_t mm[4] = {6, 9, 10, 11};
   return {3, mm[(S < 1 ? 1 : S > 4 ? 4 : S) - 1], 4};
 }
 

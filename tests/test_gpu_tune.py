@@ -57,13 +57,24 @@ def test_batch_plan_tune(env):
         Q = W.uniform_in_box(rng, int(rng.integers(100, 20000)), *W.bbox_expanded(P, 1.1))
         items.append((cl, torch.from_numpy(Q).cuda(), int(rng.choice([3, 10, 16, 33])), None))
     items = A.alloc_outputs(items)
-    plan = A.BatchPlan(len(items), sum(it[1].shape[0] for it in items))
-    tile = plan.tune(items)
-    assert tile in (8, 16, 32, 64, 256)
-    plan.run(items)
-    torch.cuda.synchronize()
-    for cl, q, k, m, idx, dist in items:
-        ri, rd = cl.knn(q, k)
+    import os
+    # the flat launch (default) tunes its merge thresholds, the persistent one its tile length
+    for persistent in (False, True):
+        if persistent:
+            os.environ["MKNN_BATCH_PERSISTENT"] = "1"
+        try:
+            plan = A.BatchPlan(len(items), sum(it[1].shape[0] for it in items))
+        finally:
+            os.environ.pop("MKNN_BATCH_PERSISTENT", None)
+        best = plan.tune(items)
+        if persistent:
+            assert best in (8, 16, 32, 64, 256)
+        else:
+            assert best in (4, 6, 8, 5, 11, 14, 17)
+        plan.run(items)
         torch.cuda.synchronize()
-        assert torch.equal(ri, idx) and torch.equal(rd, dist)
-    plan.close()
+        for cl, q, k, m, idx, dist in items:
+            ri, rd = cl.knn(q, k)
+            torch.cuda.synchronize()
+            assert torch.equal(ri, idx) and torch.equal(rd, dist)
+        plan.close()
