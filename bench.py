@@ -45,18 +45,21 @@ def log(msg: str) -> None:
     print(f"[bench {time.perf_counter() - _T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
+# the translation unit of the plain query path and the headers its kernels are built from
+KERNEL_SOURCES = ("mknn_device.hip", "knn_kernels.h", "knn_group.h", "knn_rows.h",
+                  "device_common.h", "planefit.h")
+
+
 def csrc_digest() -> str:
-    """Hash of the sources the kernels are compiled from (the HIP translation units and
-    every header), to tell whether stored counter readings still apply.  Host-only C++
-    (construction, deletion, insertion) does not enter."""
-    import glob
+    """Hash of the sources the plain query kernels are compiled from, to tell whether stored
+    counter readings still apply (host-only code, the batched and serving translation units
+    and the probes do not enter)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2605_02224_amd", "csrc")
-    files = glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))
-    for f in sorted(files):
-        h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()
 
 
