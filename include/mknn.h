@@ -330,11 +330,17 @@ mknn_status mknn_probe_gather16(const void *d_buf, int64_t bytes, int64_t access
  * the old segments.  When the arena's slack runs out, the lists are packed again.  The
  * call synchronises `stream` before returning.
  *   ranks  host int32 [count]
+ * The batch is reordered into rounds of deletions whose local sets (the rank, its
+ * predecessors and its list) are pairwise disjoint -- they commute, since the result is
+ * defined by the remaining points alone -- and the host work of a round runs on several
+ * threads (at most OMP_NUM_THREADS, else the hardware threads, shared by every call in the
+ * process); the lists are those of the serial order.
  * Errors: ENOTFOUND (unknown, deleted or repeated rank; nothing is changed), EINVAL (the
- * last live point), EUNSUPPORTED (the local set starts with four coplanar points; ranks of
- * the batch before the failing one stay deleted on the host, and the device copy must be
- * uploaded again before the next query), EHIP, ENOMEM.  Not thread-safe per
- * cloud: queries on other streams must be ordered around a deletion by the caller.
+ * last live point), EUNSUPPORTED (the local set starts with four coplanar points; the ranks
+ * applied before the failing one -- earlier rounds, and earlier ranks of its round in batch
+ * order -- stay deleted on the host, and the device copy must be uploaded again before the
+ * next query), EHIP, ENOMEM.  Not thread-safe per cloud: queries on other streams must be
+ * ordered around a deletion by the caller.
  */
 mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void *stream);
 

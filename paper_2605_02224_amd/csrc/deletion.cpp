@@ -22,10 +22,22 @@
 // While Loc_k holds at most three points (only possible for the three oldest ranks), Loc_k is
 // the whole prefix P_{1:k} \ {p_i} and adjacency is decided directly: two or three sites are
 // pairwise adjacent, except that the middle of three collinear sites separates the other two.
+//
+// A batch is reordered into rounds of independent deletions.  The lists after deleting a set
+// are those of the remaining points (Sec. 4.3), whatever the order, and the work for p_i
+// reads only the lists of i and of its local set Loc(i) = pred[i] + L_i and writes only
+// theirs; so deletions whose closed local sets {i} + Loc(i) are pairwise disjoint see the
+// same lists in any order.  Each round takes, in batch order, every remaining deletion whose
+// closed local set meets none already taken; the redistributions of a round run on several
+// threads, and their edits are then applied in batch order.
 #include <algorithm>
+#include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "cloud.h"
 #include "delaunay.h"
@@ -165,6 +177,64 @@ mknn_status redistribute(mknn_cloud *c, int32_t i, std::vector<NewEntry> *adds) 
   return MKNN_OK;
 }
 
+// Helper threads for the redistributions, shared by every deletion in the process: at most
+// the CPU budget (OMP_NUM_THREADS when set, else the hardware threads) minus one per caller.
+std::atomic<int> g_helpers{-1};
+
+int cpu_budget() {
+  const char *e = std::getenv("OMP_NUM_THREADS");
+  int v = e ? std::atoi(e) : 0;
+  if (v <= 0) v = (int)std::thread::hardware_concurrency();
+  return std::max(1, v);
+}
+
+int take_helpers(int want) {
+  int cur = g_helpers.load();
+  if (cur < 0) {
+    int init = -1;
+    g_helpers.compare_exchange_strong(init, cpu_budget() - 1);
+    cur = g_helpers.load();
+  }
+  while (want > 0 && cur > 0) {
+    const int got = std::min(want, cur);
+    if (g_helpers.compare_exchange_weak(cur, cur - got)) return got;
+  }
+  return 0;
+}
+
+void give_helpers(int n) { if (n > 0) g_helpers.fetch_add(n); }
+
+struct RoundItem {
+  int32_t rank;
+  std::vector<NewEntry> adds;
+  mknn_status st = MKNN_OK;
+  std::string err;
+};
+
+// Redistributions of one round, on the calling thread and up to `helpers` more.
+void run_round(mknn_cloud *c, std::vector<RoundItem> &items, int helpers) {
+  std::atomic<size_t> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const size_t t = next.fetch_add(1);
+      if (t >= items.size()) return;
+      RoundItem &it = items[t];
+      try {
+        it.st = redistribute(c, it.rank, &it.adds);
+        if (it.st != MKNN_OK) it.err = mknn_last_error();
+      } catch (const std::bad_alloc &) {
+        it.st = MKNN_ENOMEM;
+        it.err = "mknn_delete: out of host memory";
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  const int nh = std::min<int>(helpers, (int)items.size() - 1);
+  for (int h = 0; h < nh; ++h) th.emplace_back(work);
+  work();
+  for (std::thread &t : th) t.join();
+}
+
 }  // namespace
 
 mknn_status delete_ranks_host(mknn_cloud *c, const int32_t *ranks, int64_t count,
@@ -191,42 +261,73 @@ mknn_status delete_ranks_host(mknn_cloud *c, const int32_t *ranks, int64_t count
       c->editable = true;
     }
     std::vector<char> mark(c->n, 0);
-    std::vector<NewEntry> adds;
-    for (int32_t i : del) {
-      adds.clear();
-      mknn_status st = redistribute(c, i, &adds);
-      if (st != MKNN_OK) {
-        c->ins.reset();
-        if (i != del.front()) {
-          // earlier ranks of the batch are already applied: the host lists have moved on,
-          // and a device copy stays stale until the next upload
-          c->csr_dirty = true;
-          ++c->version;
+    std::vector<uint32_t> claim(c->n, 0);   // round stamp of the ranks a round's work touches
+    uint32_t round = 0;
+    bool applied_any = false;
+    std::vector<int32_t> rest = del, later;
+    std::vector<RoundItem> items;
+    while (!rest.empty()) {
+      // ---- one round: every remaining deletion whose closed local set is still free
+      ++round;
+      items.clear();
+      later.clear();
+      for (int32_t i : rest) {
+        const int32_t *pb = c->dpred.begin(i), *sb = c->dsucc.begin(i);
+        const int32_t np = c->dpred.size(i), ns = c->dsucc.size(i);
+        bool free = claim[i] != round;
+        for (int32_t t = 0; free && t < np; ++t) free = claim[pb[t]] != round;
+        for (int32_t t = 0; free && t < ns; ++t) free = claim[sb[t]] != round;
+        if (!free) {
+          later.push_back(i);
+          continue;
         }
-        return st;
+        claim[i] = round;
+        for (int32_t t = 0; t < np; ++t) claim[pb[t]] = round;
+        for (int32_t t = 0; t < ns; ++t) claim[sb[t]] = round;
+        items.emplace_back();
+        items.back().rank = i;
       }
-      for (const NewEntry &e : adds) {
-        c->dsucc.insert_sorted(e.owner, e.rank);
-        c->dpred.insert_sorted(e.rank, e.owner);
-        if (!mark[e.owner]) { mark[e.owner] = 1; changed->push_back(e.owner); }
+      const int helpers = items.size() > 1 ? take_helpers((int)items.size() - 1) : 0;
+      run_round(c, items, helpers);
+      give_helpers(helpers);
+      // ---- apply the round's edits in batch order
+      for (RoundItem &it : items) {
+        const int32_t i = it.rank;
+        if (it.st != MKNN_OK) {
+          c->ins.reset();
+          if (applied_any) {
+            // ranks applied before this one stay deleted: the host lists have moved on,
+            // and a device copy stays stale until the next upload
+            c->csr_dirty = true;
+            ++c->version;
+          }
+          return set_error(it.st, it.err);
+        }
+        for (const NewEntry &e : it.adds) {
+          c->dsucc.insert_sorted(e.owner, e.rank);
+          c->dpred.insert_sorted(e.rank, e.owner);
+          if (!mark[e.owner]) { mark[e.owner] = 1; changed->push_back(e.owner); }
+        }
+        // pruning
+        for (int32_t t = 0; t < c->dpred.size(i); ++t) {
+          const int32_t j = c->dpred.begin(i)[t];
+          c->dsucc.erase(j, i);
+          if (!mark[j]) { mark[j] = 1; changed->push_back(j); }
+        }
+        for (int32_t t = 0; t < c->dsucc.size(i); ++t) c->dpred.erase(c->dsucc.begin(i)[t], i);
+        c->dsucc.clear(i);
+        c->dpred.clear(i);
+        if (!mark[i]) { mark[i] = 1; changed->push_back(i); }
+        c->live[i] = 0;
+        --c->nlive;
+        if (i == c->head) {
+          int32_t h = i + 1;
+          while (h < c->n && !c->live[h]) ++h;
+          c->head = h;
+        }
+        applied_any = true;
       }
-      // pruning
-      for (int32_t t = 0; t < c->dpred.size(i); ++t) {
-        const int32_t j = c->dpred.begin(i)[t];
-        c->dsucc.erase(j, i);
-        if (!mark[j]) { mark[j] = 1; changed->push_back(j); }
-      }
-      for (int32_t t = 0; t < c->dsucc.size(i); ++t) c->dpred.erase(c->dsucc.begin(i)[t], i);
-      c->dsucc.clear(i);
-      c->dpred.clear(i);
-      if (!mark[i]) { mark[i] = 1; changed->push_back(i); }
-      c->live[i] = 0;
-      --c->nlive;
-      if (i == c->head) {
-        int32_t h = i + 1;
-        while (h < c->n && !c->live[h]) ++h;
-        c->head = h;
-      }
+      rest.swap(later);
     }
     c->csr_dirty = true;
     if (c->ins) {

@@ -108,3 +108,27 @@ def test_delete_one_at_a_time_random(api, seed):
         cl.delete([int(r)])
         alive[r] = False
         assert cl.lists() == _expected_lists(P, np.flatnonzero(alive)), int(r)
+
+
+@pytest.mark.parametrize("frac", [0.05, 0.4])
+def test_batch_in_rounds_equals_build_of_remaining(api, frac):
+    """One large batch is reordered into rounds of independent deletions, each round's
+    redistributions on several threads; the lists equal a build of the remaining points
+    (Sec. 4.3), also when many deleted ranks are neighbours of each other (40% deleted,
+    many rounds) and when the head and the oldest ranks are in the batch."""
+    from paper_2605_02224_amd import workloads as W
+    n = 6000
+    P = W.random_cloud(n, seed=9, shape="sphere").by_rank
+    cl = api.Cloud.build(P)
+    rng = np.random.default_rng(3)
+    dead = rng.choice(n, int(frac * n), replace=False)
+    dead = np.unique(np.concatenate([dead, [0, 1, 2, 7]]))
+    rng.shuffle(dead)
+    cl.delete(dead)
+    keep = np.setdiff1d(np.arange(n), dead)
+    ref = api.Cloud.build(P[keep]).lists()
+    mapped = [[] for _ in range(n)]
+    for a, lst in enumerate(ref):
+        mapped[keep[a]] = [int(keep[x]) for x in lst]
+    assert cl.lists() == mapped
+    assert cl.live_count == keep.size and cl.head == int(keep[0])
