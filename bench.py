@@ -105,13 +105,39 @@ def ingest_counters(fetch_dir: str, write_dir: str, out_path: str) -> dict:
         key = "fetch" if counter == "FETCH_SIZE" else "write"
         rec[f"{key}_kib_per_dispatch"] = round(sum(kern) / len(kern), 1)
         rec[f"{key}_dispatches"] = len(kern)
-        rec[f"{key}_scale"] = round((1 << 20) / (sum(copy) / len(copy)), 4)
+        # the probe is the largest elementwise pass of the run (1 GiB in, 1 GiB out); the
+        # benchmark's other elementwise kernels are small conversions and reductions
+        rec[f"{key}_probe_kib"] = max(copy)
+        rec[f"{key}_scale"] = round((1 << 20) / max(copy), 4)
     rec["traffic_bytes_per_dispatch"] = 1024.0 * (
         rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] +
         rec["write_kib_per_dispatch"] * rec["write_scale"])
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=2)
     return rec
+
+
+def trace_summary(trace_dir: str) -> dict:
+    """Durations of the headline query kernel in rocprofv3 kernel-trace CSVs of this
+    benchmark (one file per process): every dispatch of knn_rows_kernel<1, true, true, true>
+    over the 1M-query grid, in launch order, and their mean."""
+    import csv
+    import glob
+    out = {}
+    for f in sorted(glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))):
+        durs = []
+        for r in csv.DictReader(open(f)):
+            if "knn_rows_kernel<1, true, true, true>" not in r.get("Kernel_Name", ""):
+                continue
+            grid = int(r.get("Grid_Size") or r.get("Grid_Size_X") or 0)
+            durs.append((grid, (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6))
+        if durs:
+            big = [d for g, d in durs if g >= 16_000_000]
+            out[os.path.basename(f)] = {
+                "dispatches": len(durs), "headline_grid_dispatches": len(big),
+                "headline_grid_mean_ms": round(sum(big) / len(big), 4) if big else None,
+                "headline_grid_ms": [round(d, 4) for d in big]}
+    return out
 
 
 def cpu_info() -> dict:
@@ -852,9 +878,14 @@ def main() -> int:
                     help="also run one plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--ingest-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
                     help="write the HBM traffic reading from two rocprofv3 --pmc runs")
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR",
+                    help="durations of the headline kernel in a rocprofv3 kernel trace")
     args = ap.parse_args()
     if args.ingest_counters:
         print(json.dumps(ingest_counters(*args.ingest_counters)))
+        return 0
+    if args.trace_summary:
+        print(json.dumps(trace_summary(args.trace_summary), indent=1))
         return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU: the query path has no "
