@@ -344,6 +344,35 @@ mknn_status mknn_probe_gather16(const void *d_buf, int64_t bytes, int64_t access
  */
 mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void *stream);
 
+/* mknn_delete_lazy: marks live ranks as deleted without running Alg. 3 yet.  The marks are a
+ * device bitmap (one bit per rank, allocated on the first call and grown by re-allocation)
+ * set by a kernel on `stream`; the call synchronises `stream`.  Until they are applied,
+ * every query on the cloud (mknn_knn, mknn_knn_plane, mknn_knn_var, mknn_batch_plan_run)
+ * walks the un-updated lists for min(MKNN_KMAX, k + 16) neighbours and keeps the first k
+ * unmarked ones.  These are the k nearest remaining ranks whenever the walk found at least
+ * k unmarked ones (every site outside the walk's list is farther than all of it); a row with
+ * fewer is exact only if the prefix holds fewer sites than the walk's width.  Otherwise the
+ * call applies the pending deletions (as mknn_delete: host Alg. 3, then the delta; it
+ * synchronises `stream`) and answers again, so every result is exact.  A query call with
+ * marks pending reads one word back from the device and therefore synchronises `stream`.
+ * mknn_delete applies the pending marks together with its own batch; mknn_insert,
+ * mknn_knn_counts, mknn_autotune and a re-upload apply them first; mknn_knn_static returns
+ * EUNSUPPORTED while marks are pending (it must not allocate, and applying them does).
+ * mknn_live_count no longer counts marked ranks.
+ *   ranks  host int32 [count]
+ * Errors: ENOTFOUND (unknown, deleted, already marked or repeated rank; nothing is marked),
+ * EINVAL (not uploaded; the last live point), EHIP, ENOMEM.  Not thread-safe per cloud. */
+mknn_status mknn_delete_lazy(mknn_cloud *c, const int32_t *ranks, int64_t count, void *stream);
+
+/* Applies the pending marks (Alg. 3 on the host, then the delta on `stream`, which is
+ * synchronised).  Errors as mknn_delete; if Alg. 3 fails part way (EUNSUPPORTED) the
+ * pending set is dropped: the ranks applied before the failing one stay deleted, the rest
+ * stay live, and the cloud must be uploaded again.  No pending marks: a no-op. */
+mknn_status mknn_delete_flush(mknn_cloud *c, void *stream);
+
+/* Number of ranks marked by mknn_delete_lazy and not yet applied. */
+int64_t mknn_pending_deletes(const mknn_cloud *c);
+
 /* ---------------------------------------------------------------------------------------
  * Insertion (the construction of Sec. 3, continued).
  *

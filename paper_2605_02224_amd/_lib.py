@@ -66,6 +66,9 @@ SIGNATURES.update({
     "mknn_batch_knn": (ctypes.c_int, [ctypes.POINTER(Request), _I32, _P]),
     "mknn_delete": (ctypes.c_int, [_P, _P, _I64, _P]),
     "mknn_insert": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "mknn_delete_lazy": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "mknn_delete_flush": (ctypes.c_int, [_P, _P]),
+    "mknn_pending_deletes": (_I64, [_P]),
     "mknn_server_create": (ctypes.c_int, [_I64, _I32, _I32, _I32, _PP]),
     "mknn_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(Request), _P, _P,
                                           ctypes.POINTER(ctypes.c_uint64)]),
@@ -105,6 +108,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2605_02224_amd.build`")
+        # torch first: the library then binds to the HIP runtime torch has loaded, so one
+        # runtime (one device context) serves both
+        import torch  # noqa: F401
         h = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(h, name)

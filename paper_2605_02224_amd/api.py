@@ -92,6 +92,20 @@ class Cloud:
             st = _stream(stream)
         check(_lib.lib().mknn_delete(self._h, _ptr(r), r.shape[0], st))
 
+    def delete_lazy(self, ranks, stream=None) -> None:
+        """Mark live ranks as deleted on the device; queries filter them until flush()
+        (or a call that needs the lists current) runs Alg. 3.  Needs an uploaded cloud."""
+        r = np.ascontiguousarray(np.asarray(ranks, dtype=np.int32).reshape(-1))
+        check(_lib.lib().mknn_delete_lazy(self._h, _ptr(r), r.shape[0], _stream(stream)))
+
+    def flush(self, stream=None) -> None:
+        """Apply the deletions marked by delete_lazy (Alg. 3, then the device delta)."""
+        check(_lib.lib().mknn_delete_flush(self._h, _stream(stream)))
+
+    @property
+    def pending_deletes(self) -> int:
+        return int(_lib.lib().mknn_pending_deletes(self._h))
+
     def insert(self, points, stream=None) -> range:
         """Append points (float32 [count, 3]) as the newest ranks; returns their ranks."""
         pts = np.ascontiguousarray(np.asarray(points, dtype=np.float32).reshape(-1, 3))

@@ -118,6 +118,14 @@ inline void fill_cloud_args(const mknn_cloud *c, QueryArgs *a) {
 mknn_status delete_prepare(mknn_cloud *c, const int32_t *ranks, int64_t count, DeviceDelta *d);
 mknn_status insert_prepare(mknn_cloud *c, const float *xyz, int64_t count, DeviceDelta *d);
 mknn_status apply_delta(mknn_cloud *c, DeviceDelta *d, hipStream_t s);
+// Applies a cloud's pending (lazy) deletions, and `more` ranks with them (synchronises s).
+mknn_status flush_pending(mknn_cloud *c, hipStream_t s, const int32_t *more = nullptr,
+                          int64_t nmore = 0);
+// The server's batched run, filtering pending deletions, and the per-request counts of rows
+// it could not certify (pinned; valid once the run completed; NULL if nothing was filtered).
+mknn_status batch_plan_run_pending(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
+                                   hipStream_t s);
+const uint32_t *batch_plan_overflow(const mknn_batch_plan *p);
 // After a re-pack, the replaced arena is freed by the caller once no work reads it.
 void release_old_arena(DeviceDelta *d);
 mknn_status pack_lists(mknn_cloud *c, HostPack *p);

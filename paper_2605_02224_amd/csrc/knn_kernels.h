@@ -36,7 +36,18 @@ struct QueryArgs {
   int32_t *cnt_inserts;               // optional diagnostic: candidates inserted into N
   int32_t merge_min;                  // k <= 16: candidates per chunk from which a merge
                                       // network replaces one-by-one insertion (0 = default)
+  // Pending (lazy) deletions: ranks marked in `dead` are still listed but no longer part of
+  // the cloud.  The walk then runs for more neighbours than asked (k, or per query kq +
+  // kLazyMargin) and a row keeps the first kout (per query: kq) that are not marked; a row
+  // whose walk filled all its slots with fewer than kout unmarked sites cannot be certified
+  // and counts itself in *overflow.  dead == NULL: no pending deletions.
+  const uint32_t *dead;
+  int32_t kout;
+  uint32_t *overflow;
 };
+
+// Extra neighbours a walk collects per query while deletions are pending.
+constexpr int32_t kLazyMargin = 16;
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range
 // of tiles so Morton-adjacent queries share that XCD's L2.

@@ -60,8 +60,10 @@ __device__ __forceinline__ int32_t *ring_r(const QueryArgs &) { return g_ring_r 
 // The state of one row's current query.  Row-uniform values, held by every lane of the row.
 // WIDE_Q: hold the query in float64 (widened once rather than at every chunk), where the
 // registers allow it.  UNIFORM: one k and one m for the whole launch (or, batched, for the
-// request the wavefront is on) -- no per-query arrays, and k and m stay scalars.
-template <int S, bool EXACTK, bool WIDE_Q = (S == 1), bool UNIFORM = EXACTK>
+// request the wavefront is on) -- no per-query arrays, and k and m stay scalars.  LAZY: the
+// launch may filter pending deletions (QueryArgs::dead); kept out of the other launches,
+// whose registers (and so occupancy) the filter would cost.
+template <int S, bool EXACTK, bool WIDE_Q = (S == 1), bool UNIFORM = EXACTK, bool LAZY = false>
 struct RowWalker {
   RowTopK<S, EXACTK> N;
   using QCoord = typename std::conditional<WIDE_Q, double, float>::type;
@@ -99,6 +101,9 @@ struct RowWalker {
       qz = a.q[3 * s + 2];
     }
     k = !UNIFORM && a.kq ? a.kq[qi] : a.k;
+    // pending deletions: walk for more neighbours than the row keeps (at most the class's)
+    if constexpr (LAZY && !UNIFORM)
+      if (a.kq && a.dead) k = k + kLazyMargin < 16 * S ? k + kLazyMargin : 16 * S;
     int64_t mm = !UNIFORM && a.mq ? (int64_t)a.mq[qi] : (int64_t)a.m;
     if (mm > a.n) mm = a.n;
     m = (int32_t)mm;
@@ -137,6 +142,12 @@ struct RowWalker {
   // uk: the launch's (request's) k when UNIFORM, held by the caller in a scalar register
   __device__ __forceinline__ void finish(const QueryArgs &a, int l, int32_t uk) {
     const int32_t k = EXACTK ? 16 * S : (UNIFORM ? uk : this->k);
+    if constexpr (LAZY) {
+      if (a.dead) {
+        finish_live(a, l, k);
+        return;
+      }
+    }
     const int64_t row = !UNIFORM && a.row_off ? a.row_off[qi] : qi * (int64_t)k;
 #pragma unroll
     for (int t = 0; t < S; ++t) {
@@ -146,6 +157,45 @@ struct RowWalker {
         a.out_idx[row + j] = empty ? -1 : N.r[t];
         a.out_dist[row + j] = empty ? INFINITY : (float)sqrt(N.d[t]);
       }
+    }
+    phase = kRowIdle;
+    dsc = 0;
+    base = 0;
+  }
+
+  // Pending deletions: N holds the k nearest listed sites, marked ones included.  The row
+  // keeps the first kout unmarked ones, in order; these are the kout nearest remaining sites
+  // whenever N holds that many (every remaining site not in N is farther than all of N).  A
+  // row with fewer is exact only if N is not full (then N holds every site of the prefix);
+  // otherwise it is padded and counted in *overflow, and its caller answers it again once
+  // the deletions are applied.  Row-uniform control; the row's lanes are all active.
+  __device__ __forceinline__ void finish_live(const QueryArgs &a, int l, int32_t k) {
+    const int g = (int)((threadIdx.x & 63) >> 4);
+    const int32_t ko = !UNIFORM && a.kq ? a.kq[qi] : a.kout;
+    const int64_t row = !UNIFORM && a.row_off ? a.row_off[qi] : qi * (int64_t)ko;
+    int32_t kept = 0;
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int32_t r = N.r[t];
+      const bool listed = 16 * t + l < k && r != kEmpty;
+      const bool live = listed && ((a.dead[(uint32_t)r >> 5] >> (r & 31)) & 1u) == 0;
+      const uint32_t lm = row_bits(__ballot(live), g);
+      const int32_t pos = kept + __popc(lm & ((1u << l) - 1u));
+      if (live && pos < ko) {
+        a.out_idx[row + pos] = r;
+        a.out_dist[row + pos] = (float)sqrt(N.d[t]);
+      }
+      kept += __popc(lm);
+    }
+    for (int32_t j = kept + l; j < ko; j += 16) {
+      a.out_idx[row + j] = -1;
+      a.out_dist[row + j] = INFINITY;
+    }
+    if (kept < ko) {
+      double ld;
+      int32_t lr;
+      N.slot(k - 1, ld, lr);
+      if (lr != kEmpty && l == 0) atomicAdd(a.overflow, 1u);
     }
     phase = kRowIdle;
     dsc = 0;
@@ -386,7 +436,7 @@ struct RowWalker {
 
 // Plain launch: a wavefront owns `per_wave` consecutive sorted queries; row g takes
 // positions g, g + 4, g + 8, ... of them, so the rows stay on Morton neighbours.
-template <int S, bool EXACTK, bool DESCENT_FIRST, bool UNIFORM>
+template <int S, bool EXACTK, bool DESCENT_FIRST, bool UNIFORM, bool LAZY = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
 void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
   const int lane = threadIdx.x & 63;
@@ -395,7 +445,7 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
       ((int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t begin = wave * per_wave;
   const int64_t end = begin + per_wave < a.nq ? begin + per_wave : a.nq;
-  RowWalker<S, EXACTK, (S == 1), UNIFORM> w;
+  RowWalker<S, EXACTK, (S == 1), UNIFORM, LAZY> w;
   w.N.init();
   const int32_t m = (int32_t)(a.m < a.n ? (int64_t)a.m : a.n);
   if constexpr (DESCENT_FIRST) {

@@ -186,7 +186,7 @@ __device__ __forceinline__ void claim_tile(const BatchHeader *h, const BatchEntr
 // serves one request at a time: a claimed tile of another request is held until every row
 // has finished the current one.  For k <= 16 the tile and request bookkeeping would spill
 // about 18 registers at 8 waves per SIMD; 7 waves with almost no spills measure faster.
-template <int S>
+template <int S, bool LAZY = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 7 : 1, 8)))
 void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const BatchEntry *ents,
                            uint32_t *counters, int cls) {
@@ -202,7 +202,7 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
   int merge_min = 1;
   // the query in float32 (the bookkeeping needs the registers); a request has one k and one
   // m, held below in scalar registers with its lists
-  RowWalker<S, false, false, true> w;
+  RowWalker<S, false, false, true, LAZY> w;
   int32_t rk = 0, rm = 0;
   w.N.init();
   for (;;) {
@@ -274,7 +274,7 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
 // graph replays any batch) and laid XCD-contiguously over the workgroups the batch needs:
 // block 8 i + x runs on XCD x and takes workgroup x * per + i, per = ceil(needed / 8);
 // blocks past that leave at once.
-template <int S>
+template <int S, bool LAZY = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
 void knn_batch_flat_kernel(const BatchHeader *h, const QueryArgs *reqs, const BatchEntry *ents,
                            const int64_t *woff, int cls) {
@@ -298,7 +298,7 @@ void knn_batch_flat_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
   const int64_t end = begin + 4 < a.nq ? begin + 4 : a.nq;
   const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4;
   const int32_t m = (int32_t)(a.m < a.n ? (int64_t)a.m : a.n);
-  RowWalker<S, false, (S == 1), true> w;
+  RowWalker<S, false, (S == 1), true, LAZY> w;
   w.N.init();
   if (begin + g < end) w.begin(a, begin + g, l);
   while (__ballot(w.phase == kRowDescent) != 0)
@@ -348,16 +348,19 @@ struct mknn_batch_plan {
   float4 *d_qs = nullptr;
   char *h_stage = nullptr;          // pinned
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // captured graphs: [0] the plain kernels, [1] the variants that filter pending deletions
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   hipEvent_t done = nullptr;
   bool pending = false;
   uint32_t grid_batch[kClasses] = {1, 1, 1, 1};
   uint32_t grid_flat = 8;           // flat launch: blocks for the capacity (a multiple of 8)
   bool persistent = false;          // the persistent kernel instead of the flat one
+  uint32_t *h_overflow = nullptr;   // pinned: per request, rows a run could not certify
+  bool lazy_run = false;            // the last run filtered pending deletions
   int32_t merge_min[kClasses] = {0, 0, 0, 0};   // per class (S - 1); 0 = the autotuner's table
   uint32_t classes = 0xF;           // register classes that plan_enqueue launches (bit S-1)
-  uint32_t graph_classes = 0;       // the classes the captured graph launches
+  uint32_t graph_classes[2] = {0, 0};   // the classes each captured graph launches
   uint32_t grid_stream = 1;
 };
 
@@ -365,17 +368,55 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 static void plan_release(mknn_batch_plan *p) {
   if (p->pending && p->done) (void)hipEventSynchronize(p->done);
-  if (p->exec) (void)hipGraphExecDestroy(p->exec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (int v = 0; v < 2; ++v) {
+    if (p->exec[v]) (void)hipGraphExecDestroy(p->exec[v]);
+    if (p->graph[v]) (void)hipGraphDestroy(p->graph[v]);
+  }
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->done) (void)hipEventDestroy(p->done);
   if (p->d_base) (void)hipFree(p->d_base);
   if (p->h_stage) (void)hipHostFree(p->h_stage);
+  if (p->h_overflow) (void)hipHostFree(p->h_overflow);
   delete p;
 }
 
-// Enqueue the whole batch sequence on stream s (captured into the graph or run eagerly).
-static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s) {
+// The query launches of plan_enqueue, one per register class in p->classes.
+template <bool LAZY>
+static void launch_batch_kernels(const mknn_batch_plan *p, hipStream_t s, const BatchHeader *hdr,
+                                 const QueryArgs *reqs, const BatchEntry *ents,
+                                 const int64_t *woff) {
+  // only the classes in p->classes: an empty class's launch still dispatches its whole grid
+  const bool c1 = p->classes & 1u, c2 = p->classes & 2u, c3 = p->classes & 4u,
+             c4 = p->classes & 8u;
+  if (p->persistent) {
+    if (c1)
+      hipLaunchKernelGGL((knn_batch_rows_kernel<1, LAZY>), dim3(p->grid_batch[0]), dim3(256), 0, s,
+                         hdr, reqs, ents, p->d_counters, 0);
+    if (c2)
+      hipLaunchKernelGGL((knn_batch_rows_kernel<2, LAZY>), dim3(p->grid_batch[1]), dim3(256), 0, s,
+                         hdr, reqs, ents, p->d_counters, 1);
+    if (c3)
+      hipLaunchKernelGGL((knn_batch_rows_kernel<3, LAZY>), dim3(p->grid_batch[2]), dim3(256), 0, s,
+                         hdr, reqs, ents, p->d_counters, 2);
+    if (c4)
+      hipLaunchKernelGGL((knn_batch_rows_kernel<4, LAZY>), dim3(p->grid_batch[3]), dim3(256), 0, s,
+                         hdr, reqs, ents, p->d_counters, 3);
+  } else {
+    const dim3 gf(p->grid_flat);
+    if (c1)
+      hipLaunchKernelGGL((knn_batch_flat_kernel<1, LAZY>), gf, dim3(256), 0, s, hdr, reqs, ents, woff, 0);
+    if (c2)
+      hipLaunchKernelGGL((knn_batch_flat_kernel<2, LAZY>), gf, dim3(256), 0, s, hdr, reqs, ents, woff, 1);
+    if (c3)
+      hipLaunchKernelGGL((knn_batch_flat_kernel<3, LAZY>), gf, dim3(256), 0, s, hdr, reqs, ents, woff, 2);
+    if (c4)
+      hipLaunchKernelGGL((knn_batch_flat_kernel<4, LAZY>), gf, dim3(256), 0, s, hdr, reqs, ents, woff, 3);
+  }
+}
+
+// Enqueue the whole batch sequence on stream s (captured into a graph or run eagerly); lazy:
+// the query kernels that filter pending deletions.
+static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s, bool lazy) {
   const BatchHeader *hdr = (const BatchHeader *)(p->d_base + p->off_hdr);
   const QueryArgs *reqs = (const QueryArgs *)(p->d_base + p->off_reqs);
   const BatchEntry *ents = (const BatchEntry *)(p->d_base + p->off_ents);
@@ -384,8 +425,8 @@ static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s) {
   const int64_t *woff = (const int64_t *)(p->d_base + p->off_woff);
   hipError_t e = hipMemcpyAsync(p->d_base, p->h_stage, p->stage_bytes, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(1), dim3(64), 0, s, p->d_counters,
-                     (int64_t)(kClasses * kQueues), 0u);
+  hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(64), dim3(256), 0, s, p->d_counters,
+                     (int64_t)(kClasses * kQueues) + p->max_req, 0u);
   if (p->sort) {
     const int64_t nb = p->max_req * kSegBins;
     const uint32_t gb = (uint32_t)std::min<int64_t>(4096, (nb + 255) / 256);
@@ -402,120 +443,25 @@ static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = timing_mark(s, true);
   if (e != hipSuccess) return e;
-  // only the classes in p->classes: an empty class's launch still dispatches its whole grid
-  const bool c1 = p->classes & 1u, c2 = p->classes & 2u, c3 = p->classes & 4u,
-             c4 = p->classes & 8u;
-  if (p->persistent) {
-    if (c1)
-      hipLaunchKernelGGL(knn_batch_rows_kernel<1>, dim3(p->grid_batch[0]), dim3(256), 0, s, hdr,
-                         reqs, ents, p->d_counters, 0);
-    if (c2)
-      hipLaunchKernelGGL(knn_batch_rows_kernel<2>, dim3(p->grid_batch[1]), dim3(256), 0, s, hdr,
-                         reqs, ents, p->d_counters, 1);
-    if (c3)
-      hipLaunchKernelGGL(knn_batch_rows_kernel<3>, dim3(p->grid_batch[2]), dim3(256), 0, s, hdr,
-                         reqs, ents, p->d_counters, 2);
-    if (c4)
-      hipLaunchKernelGGL(knn_batch_rows_kernel<4>, dim3(p->grid_batch[3]), dim3(256), 0, s, hdr,
-                         reqs, ents, p->d_counters, 3);
-  } else {
-    const dim3 gf(p->grid_flat);
-    if (c1)
-      hipLaunchKernelGGL(knn_batch_flat_kernel<1>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 0);
-    if (c2)
-      hipLaunchKernelGGL(knn_batch_flat_kernel<2>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 1);
-    if (c3)
-      hipLaunchKernelGGL(knn_batch_flat_kernel<3>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 2);
-    if (c4)
-      hipLaunchKernelGGL(knn_batch_flat_kernel<4>, gf, dim3(256), 0, s, hdr, reqs, ents, woff, 3);
-  }
+  if (lazy)
+    launch_batch_kernels<true>(p, s, hdr, reqs, ents, woff);
+  else
+    launch_batch_kernels<false>(p, s, hdr, reqs, ents, woff);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return timing_mark(s, false);
 }
 
-extern "C" {
+namespace mknn {
+static mknn_status plan_run(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
+                            hipStream_t s, bool filter_pending);
 
-mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, int32_t tile_queries,
-                                   int32_t flags, mknn_batch_plan **out) {
-  clear_error();
-  if (!out) return set_error(MKNN_EINVAL, "mknn_batch_plan_create: out is NULL");
-  *out = nullptr;
-  if (max_requests < 1 || max_requests > (1 << 20) || max_queries < 1 ||
-      max_queries > (int64_t)0x7fffffff)
-    return set_error(MKNN_EINVAL, "mknn_batch_plan_create: capacity out of range");
-  if (tile_queries < 4 || tile_queries > (1 << 20))
-    return set_error(MKNN_EINVAL, "mknn_batch_plan_create: tile_queries out of range [4, 2^20]");
-  mknn_batch_plan *p = new (std::nothrow) mknn_batch_plan();
-  if (!p) return set_error(MKNN_ENOMEM, "mknn_batch_plan_create: out of host memory");
-  p->max_req = max_requests;
-  p->max_q = max_queries;
-  p->tile_q = tile_queries;
-  p->sort = !(flags & MKNN_BATCH_NO_SORT);
-  p->persistent = batch_persistent();
-  p->use_graph = !(flags & MKNN_BATCH_NO_GRAPH);
-  hipError_t e = hipGetDevice(&p->device);
-  size_t o = 0;
-  p->off_hdr = o;
-  o = align256(o + sizeof(BatchHeader));
-  p->off_reqs = o;
-  o = align256(o + sizeof(QueryArgs) * (size_t)p->max_req);
-  p->off_ents = o;
-  o = align256(o + sizeof(BatchEntry) * (size_t)p->max_req);
-  p->off_boxes = o;
-  o = align256(o + sizeof(BoxArgs) * (size_t)p->max_req);
-  p->off_qoff = o;
-  o = align256(o + sizeof(int64_t) * (size_t)(p->max_req + 1));
-  p->off_woff = o;
-  o = align256(o + sizeof(int64_t) * (size_t)p->max_req);
-  p->stage_bytes = o;
-  const size_t counters_at = o;
-  o = align256(o + sizeof(uint32_t) * kClasses * kQueues);
-  const size_t bins_at = o;
-  if (p->sort) o = align256(o + sizeof(uint32_t) * (size_t)p->max_req * kSegBins);
-  const size_t qs_at = o;
-  if (p->sort) o = align256(o + sizeof(float4) * (size_t)p->max_q);
-  if (e == hipSuccess) e = hipMalloc((void **)&p->d_base, o);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_stage, p->stage_bytes, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
-  if (e == hipSuccess && p->use_graph) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    const std::string msg = std::string("mknn_batch_plan_create: ") + hipGetErrorName(e);
-    plan_release(p);
-    return set_error(e == hipErrorOutOfMemory ? MKNN_ENOMEM : MKNN_EHIP, msg);
-  }
-  std::memset(p->h_stage, 0, p->stage_bytes);
-  const uint32_t cus = (uint32_t)device_cus();
-  p->grid_batch[0] = cus * resident_batch_blocks<1>();
-  p->grid_batch[1] = cus * resident_batch_blocks<2>();
-  p->grid_batch[2] = cus * resident_batch_blocks<3>();
-  p->grid_batch[3] = cus * resident_batch_blocks<4>();
-  p->grid_stream = cus * 8;
-  {
-    // a class holds at most max_q / 4 + max_req wavefronts of work (a partial one per request)
-    const int64_t waves = (p->max_q + 3) / 4 + p->max_req;
-    const int64_t wgs = (waves + 3) / 4;
-    const int64_t blocks = 8 * ((wgs + 7) / 8);
-    if (blocks > (int64_t)0x7fffffff) {
-      plan_release(p);
-      return set_error(MKNN_EINVAL, "mknn_batch_plan_create: capacity too large for one launch");
-    }
-    p->grid_flat = (uint32_t)blocks;
-  }
-  p->d_counters = (uint32_t *)(p->d_base + counters_at);
-  p->d_bins = p->sort ? (uint32_t *)(p->d_base + bins_at) : nullptr;
-  p->d_qs = p->sort ? (float4 *)(p->d_base + qs_at) : nullptr;
-  *out = p;
-  return MKNN_OK;
-}
-
-void mknn_batch_plan_destroy(mknn_batch_plan *p) {
-  if (p) plan_release(p);
-}
-
-mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
-                                void *stream) {
-  clear_error();
+// The server's form of a run: requests on clouds with pending deletions over-fetch and
+// filter (QueryArgs::dead) instead of applying the deletions first; the rows each request
+// could not certify are copied to the plan's pinned counters (batch_plan_overflow) behind
+// the run.
+static mknn_status plan_run(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
+                            hipStream_t s, bool filter_pending) {
   if (!p) return set_error(MKNN_EINVAL, "mknn_batch_plan_run: plan is NULL");
   if (nreq < 0 || (nreq > 0 && !reqs))
     return set_error(MKNN_EINVAL, "mknn_batch_plan_run: bad request array");
@@ -527,6 +473,9 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   // ---- validate and describe every request
   std::vector<int64_t> qoff((size_t)nreq + 1, 0);
   std::vector<int> cls((size_t)nreq, 0);
+  std::vector<char> lazy((size_t)nreq, 0);   // the request filters pending deletions
+  std::vector<int32_t> kwalk((size_t)nreq, 0);
+  bool any_lazy = false;
   for (int32_t r = 0; r < nreq; ++r) {
     const mknn_request &q = reqs[r];
     const std::string who = "mknn_batch_plan_run: request " + std::to_string(r);
@@ -538,8 +487,19 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
     if (q.nq < 0) return set_error(MKNN_EINVAL, who + ": nq < 0");
     if (q.nq > 0 && (!q.d_q || !q.d_idx || !q.d_dist))
       return set_error(MKNN_EINVAL, who + ": NULL buffer");
+    if (q.cloud->dev_lazy.load() != 0) {
+      if (filter_pending && q.cloud->d_dead) {
+        lazy[r] = 1;
+        any_lazy = true;
+      } else {
+        // the public batched call applies pending deletions first (synchronously)
+        st = flush_pending(const_cast<mknn_cloud *>(q.cloud), s);
+        if (st != MKNN_OK) return st;
+      }
+    }
+    kwalk[r] = lazy[r] ? std::min<int32_t>(MKNN_KMAX, q.k + kLazyMargin) : q.k;
     qoff[r + 1] = qoff[r] + q.nq;
-    cls[r] = (q.k + 15) / 16 - 1;
+    cls[r] = (kwalk[r] + 15) / 16 - 1;
   }
   if (qoff[nreq] > p->max_q)
     return set_error(MKNN_EINVAL, "mknn_batch_plan_run: more queries than the plan holds");
@@ -607,13 +567,18 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   for (int32_t r = 0; r < nreq; ++r) {
     const mknn_request &q = reqs[r];
     fill_cloud_args(q.cloud, &args[r]);
-    const int cls = (q.k + 15) / 16 - 1;
-    args[r].merge_min = p->merge_min[cls] > 0 ? p->merge_min[cls]
-                                               : config_for(q.k, false, q.cloud->dev_n).merge_min;
+    const int cl = cls[r];
+    args[r].merge_min = p->merge_min[cl] > 0 ? p->merge_min[cl]
+                                             : config_for(kwalk[r], false, q.cloud->dev_n).merge_min;
     args[r].q = q.d_q;
     args[r].qs = p->sort ? p->d_qs + qoff[r] : nullptr;
     args[r].nq = q.nq;
-    args[r].k = q.k;
+    args[r].k = kwalk[r];
+    if (lazy[r]) {
+      args[r].dead = q.cloud->d_dead;
+      args[r].kout = q.k;
+      args[r].overflow = p->d_counters + kClasses * kQueues + r;
+    }
     args[r].m = q.m == 0 ? (int32_t)q.cloud->dev_n : q.m;
     args[r].out_idx = q.d_idx;
     args[r].out_dist = q.d_dist;
@@ -624,21 +589,21 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
   uint32_t need = 0;   // the classes with work in this batch
   for (int c = 0; c < kClasses; ++c)
     if (class_q[c] > 0) need |= 1u << c;
-  hipStream_t s = (hipStream_t)stream;
   if (p->use_graph && !timing_enabled()) {
-    if (p->exec && (need & ~p->graph_classes)) {
+    const int v = any_lazy ? 1 : 0;
+    if (p->exec[v] && (need & ~p->graph_classes[v])) {
       // a class the graph does not launch: capture again with it (the previous run is done)
-      (void)hipGraphExecDestroy(p->exec);
-      (void)hipGraphDestroy(p->graph);
-      p->exec = nullptr;
-      p->graph = nullptr;
+      (void)hipGraphExecDestroy(p->exec[v]);
+      (void)hipGraphDestroy(p->graph[v]);
+      p->exec[v] = nullptr;
+      p->graph[v] = nullptr;
     }
-    if (!p->exec) {
-      p->classes = p->graph_classes | need;
-      p->graph_classes = p->classes;
+    if (!p->exec[v]) {
+      p->classes = p->graph_classes[v] | need;
+      p->graph_classes[v] = p->classes;
       HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal),
               "mknn_batch_plan_run: begin capture");
-      hipError_t e = plan_enqueue(p, p->cap_stream);
+      hipError_t e = plan_enqueue(p, p->cap_stream, any_lazy);
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
       if (e != hipSuccess || e2 != hipSuccess) {
@@ -646,19 +611,124 @@ mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, in
         return set_error(MKNN_EHIP, std::string("mknn_batch_plan_run: capture failed: ") +
                                         hipGetErrorName(e != hipSuccess ? e : e2));
       }
-      p->graph = g;
-      HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0),
+      p->graph[v] = g;
+      HIP_TRY(hipGraphInstantiate(&p->exec[v], p->graph[v], nullptr, nullptr, 0),
               "mknn_batch_plan_run: instantiate");
     }
-    HIP_TRY(hipGraphLaunch(p->exec, s), "mknn_batch_plan_run: graph launch");
+    HIP_TRY(hipGraphLaunch(p->exec[v], s), "mknn_batch_plan_run: graph launch");
   } else {
     p->classes = need;
-    HIP_TRY(plan_enqueue(p, s), "mknn_batch_plan_run: launch");
+    HIP_TRY(plan_enqueue(p, s, any_lazy), "mknn_batch_plan_run: launch");
   }
+  p->lazy_run = any_lazy;
+  if (any_lazy)
+    HIP_TRY(hipMemcpyAsync(p->h_overflow, p->d_counters + kClasses * kQueues,
+                           sizeof(uint32_t) * (size_t)std::max<int32_t>(1, nreq),
+                           hipMemcpyDeviceToHost, s),
+            "mknn_batch_plan_run: overflow counters");
   HIP_TRY(hipEventRecord(p->done, s), "mknn_batch_plan_run: record");
   p->pending = true;
   return MKNN_OK;
 }
+
+mknn_status batch_plan_run_pending(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
+                                   hipStream_t s) {
+  return plan_run(p, reqs, nreq, s, true);
+}
+const uint32_t *batch_plan_overflow(const mknn_batch_plan *p) {
+  return p->lazy_run ? p->h_overflow : nullptr;
+}
+}  // namespace mknn
+
+
+extern "C" {
+
+mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, int32_t tile_queries,
+                                   int32_t flags, mknn_batch_plan **out) {
+  clear_error();
+  if (!out) return set_error(MKNN_EINVAL, "mknn_batch_plan_create: out is NULL");
+  *out = nullptr;
+  if (max_requests < 1 || max_requests > (1 << 20) || max_queries < 1 ||
+      max_queries > (int64_t)0x7fffffff)
+    return set_error(MKNN_EINVAL, "mknn_batch_plan_create: capacity out of range");
+  if (tile_queries < 4 || tile_queries > (1 << 20))
+    return set_error(MKNN_EINVAL, "mknn_batch_plan_create: tile_queries out of range [4, 2^20]");
+  mknn_batch_plan *p = new (std::nothrow) mknn_batch_plan();
+  if (!p) return set_error(MKNN_ENOMEM, "mknn_batch_plan_create: out of host memory");
+  p->max_req = max_requests;
+  p->max_q = max_queries;
+  p->tile_q = tile_queries;
+  p->sort = !(flags & MKNN_BATCH_NO_SORT);
+  p->persistent = batch_persistent();
+  p->use_graph = !(flags & MKNN_BATCH_NO_GRAPH);
+  hipError_t e = hipGetDevice(&p->device);
+  size_t o = 0;
+  p->off_hdr = o;
+  o = align256(o + sizeof(BatchHeader));
+  p->off_reqs = o;
+  o = align256(o + sizeof(QueryArgs) * (size_t)p->max_req);
+  p->off_ents = o;
+  o = align256(o + sizeof(BatchEntry) * (size_t)p->max_req);
+  p->off_boxes = o;
+  o = align256(o + sizeof(BoxArgs) * (size_t)p->max_req);
+  p->off_qoff = o;
+  o = align256(o + sizeof(int64_t) * (size_t)(p->max_req + 1));
+  p->off_woff = o;
+  o = align256(o + sizeof(int64_t) * (size_t)p->max_req);
+  p->stage_bytes = o;
+  const size_t counters_at = o;
+  // tile counters, then one overflow counter per request (pending deletions)
+  o = align256(o + sizeof(uint32_t) * (kClasses * kQueues + (size_t)p->max_req));
+  const size_t bins_at = o;
+  if (p->sort) o = align256(o + sizeof(uint32_t) * (size_t)p->max_req * kSegBins);
+  const size_t qs_at = o;
+  if (p->sort) o = align256(o + sizeof(float4) * (size_t)p->max_q);
+  if (e == hipSuccess) e = hipMalloc((void **)&p->d_base, o);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_stage, p->stage_bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void **)&p->h_overflow, sizeof(uint32_t) * (size_t)std::max<int64_t>(1, p->max_req));
+  if (e == hipSuccess && p->use_graph) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    const std::string msg = std::string("mknn_batch_plan_create: ") + hipGetErrorName(e);
+    plan_release(p);
+    return set_error(e == hipErrorOutOfMemory ? MKNN_ENOMEM : MKNN_EHIP, msg);
+  }
+  std::memset(p->h_stage, 0, p->stage_bytes);
+  const uint32_t cus = (uint32_t)device_cus();
+  p->grid_batch[0] = cus * resident_batch_blocks<1>();
+  p->grid_batch[1] = cus * resident_batch_blocks<2>();
+  p->grid_batch[2] = cus * resident_batch_blocks<3>();
+  p->grid_batch[3] = cus * resident_batch_blocks<4>();
+  p->grid_stream = cus * 8;
+  {
+    // a class holds at most max_q / 4 + max_req wavefronts of work (a partial one per request)
+    const int64_t waves = (p->max_q + 3) / 4 + p->max_req;
+    const int64_t wgs = (waves + 3) / 4;
+    const int64_t blocks = 8 * ((wgs + 7) / 8);
+    if (blocks > (int64_t)0x7fffffff) {
+      plan_release(p);
+      return set_error(MKNN_EINVAL, "mknn_batch_plan_create: capacity too large for one launch");
+    }
+    p->grid_flat = (uint32_t)blocks;
+  }
+  p->d_counters = (uint32_t *)(p->d_base + counters_at);
+  p->d_bins = p->sort ? (uint32_t *)(p->d_base + bins_at) : nullptr;
+  p->d_qs = p->sort ? (float4 *)(p->d_base + qs_at) : nullptr;
+  *out = p;
+  return MKNN_OK;
+}
+
+void mknn_batch_plan_destroy(mknn_batch_plan *p) {
+  if (p) plan_release(p);
+}
+
+mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
+                                void *stream) {
+  clear_error();
+  return plan_run(p, reqs, nreq, (hipStream_t)stream, false);
+}
+
 
 mknn_status mknn_batch_plan_tune(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
                                  void *stream, int32_t *best) {

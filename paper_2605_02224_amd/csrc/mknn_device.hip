@@ -260,9 +260,14 @@ static void free_device(mknn_cloud *c) {
   if (c->d_ent) (void)hipFree(c->d_ent);
   if (c->d_lst) (void)hipFree(c->d_lst);
   if (c->d_pts) (void)hipFree(c->d_pts);
+  if (c->d_dead) (void)hipFree(c->d_dead);
+  if (c->d_overflow) (void)hipFree(c->d_overflow);
   c->d_ent = nullptr;
   c->d_lst = nullptr;
   c->d_pts = nullptr;
+  c->d_dead = nullptr;
+  c->d_overflow = nullptr;
+  c->dead_words = 0;
   c->dev_bytes = 0;
   c->dev_version = ~0ull;
 }
@@ -639,7 +644,14 @@ static hipError_t launch_rows(const QueryArgs &a, int32_t per_wave, hipStream_t 
   // descent steps first only when every row keeps its one query for the whole launch;
   // k and m as scalars when there are no per-query arrays (always so for exact k)
   const bool uniform = !a.kq && !a.mq;
-  if (EXACTK || uniform) {
+  if (a.dead) {
+    // pending deletions: the filtering variants (descent first, one query per row)
+    if (per_wave != 4) return hipErrorInvalidValue;
+    if (EXACTK || uniform)
+      hipLaunchKernelGGL((knn_rows_kernel<S, EXACTK, true, true, true>), dim3(blocks), dim3(256), 0, s, a, per_wave);
+    else if constexpr (!EXACTK)
+      hipLaunchKernelGGL((knn_rows_kernel<S, false, true, false, true>), dim3(blocks), dim3(256), 0, s, a, per_wave);
+  } else if (EXACTK || uniform) {
     if (per_wave == 4)
       hipLaunchKernelGGL((knn_rows_kernel<S, EXACTK, true, true>), dim3(blocks), dim3(256), 0, s, a, per_wave);
     else
@@ -700,14 +712,26 @@ static mknn_status prepare_queries(const mknn_cloud *c, const float *d_q, int64_
   return MKNN_OK;
 }
 
+// Pending deletions on a launch: the walk collects kout + kLazyMargin neighbours (at most
+// MKNN_KMAX) and the rows keep the first kout unmarked ones (QueryArgs::dead).
+struct LazyLaunch {
+  int32_t kout;
+};
+
 static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
                              int32_t m, const int32_t *d_k, const int32_t *d_m,
                              const int64_t *d_row_off, int32_t kmax, int32_t *d_idx,
                              float *d_dist, int32_t *d_ce, int32_t *d_cl, int32_t *d_ci,
                              hipStream_t s, const char *who, const TuneConfig *force = nullptr,
-                             float *d_plane = nullptr, void *fixed_scratch = nullptr) {
+                             float *d_plane = nullptr, void *fixed_scratch = nullptr,
+                             const LazyLaunch *lazy = nullptr) {
   QueryArgs a;
   fill_cloud_args(c, &a);
+  if (lazy) {
+    a.dead = c->d_dead;
+    a.kout = lazy->kout;
+    a.overflow = c->d_overflow;
+  }
   a.q = d_q;
   a.nq = nq;
   a.k = k;
@@ -726,7 +750,11 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
   if (st != MKNN_OK) return st;
   a.qs = qs;
   const bool exact = (d_k == nullptr);
-  const TuneConfig cfg = force ? *force : config_for(kmax, exact, c->dev_n);
+  TuneConfig cfg = force ? *force : config_for(kmax, exact, c->dev_n);
+  if (lazy) {
+    cfg.family = 3;   // only the row kernels filter marked ranks
+    cfg.per_wave = 4;
+  }
   a.merge_min = cfg.merge_min;
   // the allocation-free entry point records no timing events (they are created on demand)
   hipError_t e = fixed_scratch ? hipSuccess : timing_mark(s, true);
@@ -741,7 +769,7 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
   if (e == hipSuccess && !fixed_scratch) e = timing_mark(s, false);
   // the plane fit reads the rows just written (and the sorted queries, for their order)
   if (e == hipSuccess && d_plane)
-    e = launch_plane_fit((const float4 *)c->d_pts, d_idx, qs, nq, k, d_plane, s);
+    e = launch_plane_fit((const float4 *)c->d_pts, d_idx, qs, nq, lazy ? lazy->kout : k, d_plane, s);
   if (scratch) (void)hipFreeAsync(scratch, s);
   if (e != hipSuccess)
     return set_error(MKNN_EHIP, std::string(who) + ": launch failed: " + hipGetErrorName(e));
@@ -823,6 +851,59 @@ static mknn_status static_scratch(void **out) {
   return MKNN_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// Pending (lazy) deletions
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mark_dead_kernel(uint32_t *bits, const int32_t *r,
+                                                        int64_t cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) atomicOr(&bits[(uint32_t)r[i] >> 5], 1u << (r[i] & 31));
+}
+
+// Applies the pending deletions (Alg. 3 on the host, the delta on s); synchronises s.
+mknn_status flush_pending(mknn_cloud *c, hipStream_t s, const int32_t *more, int64_t nmore) {
+  std::vector<int32_t> all(c->lazy);
+  if (more) all.insert(all.end(), more, more + nmore);
+  if (all.empty()) return MKNN_OK;
+  DeviceDelta d;
+  const uint64_t version = c->version;
+  mknn_status st = delete_prepare(c, all.data(), (int64_t)all.size(), &d);
+  // a batch that changed nothing keeps the pending set; one applied (even in part) ends it
+  if (st != MKNN_OK && c->version == version) return st;
+  for (int32_t r : c->lazy) c->lazy_mark[r] = 0;
+  c->lazy.clear();
+  c->dev_lazy = 0;
+  if (st != MKNN_OK) return st;
+  if (!d.on_device) return MKNN_OK;
+  st = apply_delta(c, &d, s);
+  if (st != MKNN_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s), "apply pending deletions: synchronize");
+  release_old_arena(&d);
+  return MKNN_OK;
+}
+
+// A query call on the device lists.  With pending deletions the launch over-fetches and
+// filters (LazyLaunch), then the overflow counter is read back (s is synchronised) and, if
+// some row could not be certified, the pending deletions are applied and the call runs
+// again on the new lists.  launch(const LazyLaunch *) enqueues the call.
+template <typename Launch>
+static mknn_status run_with_pending(const mknn_cloud *cc, int32_t kout, hipStream_t s,
+                                    const char *who, Launch launch) {
+  mknn_cloud *c = const_cast<mknn_cloud *>(cc);
+  if (c->dev_lazy.load() == 0 || !c->d_dead) return launch(nullptr);
+  const LazyLaunch lz{kout};
+  hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(1), dim3(64), 0, s, c->d_overflow, (int64_t)1, 0u);
+  mknn_status st = launch(&lz);
+  if (st != MKNN_OK) return st;
+  uint32_t ovf = 0;
+  HIP_TRY(hipMemcpyAsync(&ovf, c->d_overflow, sizeof(ovf), hipMemcpyDeviceToHost, s), who);
+  HIP_TRY(hipStreamSynchronize(s), who);
+  if (ovf == 0) return MKNN_OK;
+  st = flush_pending(c, s);
+  if (st != MKNN_OK) return st;
+  return launch(nullptr);
+}
+
 }  // namespace mknn
 
 using namespace mknn;
@@ -836,8 +917,15 @@ mknn_status mknn_upload(mknn_cloud *c, void *stream) {
   HIP_TRY(hipGetDevice(&dev), "mknn_upload: hipGetDevice");
   if (c->d_ent && c->dev_version == c->version && c->device == dev) return MKNN_OK;
   hipStream_t s = (hipStream_t)stream;
+  mknn_status st = MKNN_OK;
+  if (!c->lazy.empty()) {
+    // pending deletions are applied to the host lists only; the new copy then holds them
+    free_device(c);
+    st = flush_pending(c, s);
+    if (st != MKNN_OK) return st;
+  }
   HostPack pack;
-  mknn_status st = pack_lists(c, &pack);
+  st = pack_lists(c, &pack);
   if (st != MKNN_OK) return st;
   free_device(c);
   c->device = dev;
@@ -880,8 +968,12 @@ mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t 
   if (m < 1 || m > c->dev_n) return set_error(MKNN_EINVAL, "mknn_knn: m must be in [1, n]");
   if (nq == 0) return MKNN_OK;
   if (!d_q || !d_idx || !d_dist) return set_error(MKNN_EINVAL, "mknn_knn: NULL buffer");
-  return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, d_idx, d_dist, nullptr,
-                   nullptr, nullptr, (hipStream_t)stream, "mknn_knn");
+  hipStream_t s = (hipStream_t)stream;
+  return run_with_pending(c, k, s, "mknn_knn", [&](const LazyLaunch *lz) {
+    const int32_t kw = lz ? std::min<int32_t>(MKNN_KMAX, k + kLazyMargin) : k;
+    return run_query(c, d_q, nq, kw, m, nullptr, nullptr, nullptr, kw, d_idx, d_dist, nullptr,
+                     nullptr, nullptr, s, "mknn_knn", nullptr, nullptr, nullptr, lz);
+  });
 }
 
 mknn_status mknn_knn_static(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
@@ -898,6 +990,9 @@ mknn_status mknn_knn_static(const mknn_cloud *c, const float *d_q, int64_t nq, i
   if (m < 1 || m > c->dev_n) return set_error(MKNN_EINVAL, "mknn_knn_static: m must be in [1, n]");
   if (nq == 0) return MKNN_OK;
   if (!d_q || !d_idx || !d_dist) return set_error(MKNN_EINVAL, "mknn_knn_static: NULL buffer");
+  if (c->dev_lazy.load() != 0)
+    return set_error(MKNN_EUNSUPPORTED, "mknn_knn_static: the cloud has pending deletions "
+                                        "(apply them with mknn_delete_flush first)");
   void *buf = nullptr;
   st = static_scratch(&buf);
   if (st != MKNN_OK) return st;
@@ -921,8 +1016,12 @@ mknn_status mknn_knn_plane(const mknn_cloud *c, const float *d_q, int64_t nq, in
   if (nq == 0) return MKNN_OK;
   if (!d_q || !d_idx || !d_dist || !d_plane)
     return set_error(MKNN_EINVAL, "mknn_knn_plane: NULL buffer");
-  return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, d_idx, d_dist, nullptr,
-                   nullptr, nullptr, (hipStream_t)stream, "mknn_knn_plane", nullptr, d_plane);
+  hipStream_t s = (hipStream_t)stream;
+  return run_with_pending(c, k, s, "mknn_knn_plane", [&](const LazyLaunch *lz) {
+    const int32_t kw = lz ? std::min<int32_t>(MKNN_KMAX, k + kLazyMargin) : k;
+    return run_query(c, d_q, nq, kw, m, nullptr, nullptr, nullptr, kw, d_idx, d_dist, nullptr,
+                     nullptr, nullptr, s, "mknn_knn_plane", nullptr, d_plane, nullptr, lz);
+  });
 }
 
 mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, const int32_t *d_k,
@@ -937,10 +1036,14 @@ mknn_status mknn_knn_var(const mknn_cloud *c, const float *d_q, int64_t nq, cons
   if (nq == 0) return MKNN_OK;
   if (!d_q || !d_k || !d_m || !d_row_off || !d_idx || !d_dist)
     return set_error(MKNN_EINVAL, "mknn_knn_var: NULL buffer");
-  st = check_per_query(d_k, d_m, d_row_off, nq, kmax, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  st = check_per_query(d_k, d_m, d_row_off, nq, kmax, s);
   if (st != MKNN_OK) return st;
-  return run_query(c, d_q, nq, 0, 0, d_k, d_m, d_row_off, kmax, d_idx, d_dist, nullptr, nullptr,
-                   nullptr, (hipStream_t)stream, "mknn_knn_var");
+  return run_with_pending(c, 0, s, "mknn_knn_var", [&](const LazyLaunch *lz) {
+    const int32_t kw = lz ? std::min<int32_t>(MKNN_KMAX, kmax + kLazyMargin) : kmax;
+    return run_query(c, d_q, nq, 0, 0, d_k, d_m, d_row_off, kw, d_idx, d_dist, nullptr, nullptr,
+                     nullptr, s, "mknn_knn_var", nullptr, nullptr, nullptr, lz);
+  });
 }
 
 mknn_status mknn_knn_counts(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
@@ -955,6 +1058,10 @@ mknn_status mknn_knn_counts(const mknn_cloud *c, const float *d_q, int64_t nq, i
   if (m < 1 || m > c->dev_n) return set_error(MKNN_EINVAL, "mknn_knn_counts: m must be in [1, n]");
   if (nq == 0) return MKNN_OK;
   if (!d_q || !d_entries || !d_lists) return set_error(MKNN_EINVAL, "mknn_knn_counts: NULL buffer");
+  if (c->dev_lazy.load() != 0) {
+    st = flush_pending(const_cast<mknn_cloud *>(c), (hipStream_t)stream);
+    if (st != MKNN_OK) return st;
+  }
   return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, nullptr, nullptr, d_entries,
                    d_lists, d_inserts, (hipStream_t)stream, "mknn_knn_counts");
 }
@@ -971,6 +1078,10 @@ mknn_status mknn_autotune(const mknn_cloud *c, const float *d_q, int64_t nq, int
   if (st != MKNN_OK) return st;
   if (m == 0) m = (int32_t)c->dev_n;
   if (m < 1 || m > c->dev_n) return set_error(MKNN_EINVAL, "mknn_autotune: m must be in [0, n]");
+  if (c->dev_lazy.load() != 0) {
+    st = flush_pending(const_cast<mknn_cloud *>(c), (hipStream_t)stream);
+    if (st != MKNN_OK) return st;
+  }
   const int S = (k + 15) / 16;
   std::vector<TuneConfig> cand;
   for (int pw : {4, 8}) {
@@ -1105,11 +1216,19 @@ mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void
   if (!c) return set_error(MKNN_EINVAL, "mknn_delete: cloud is NULL");
   if (count < 0 || (count > 0 && !ranks)) return set_error(MKNN_EINVAL, "mknn_delete: bad ranks");
   if (count == 0) return MKNN_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (!c->lazy.empty()) {
+    // pending deletions go with this batch
+    for (int64_t t = 0; t < count; ++t)
+      if (ranks[t] >= 0 && ranks[t] < (int32_t)c->lazy_mark.size() && c->lazy_mark[ranks[t]])
+        return set_error(MKNN_ENOTFOUND, "mknn_delete: rank " + std::to_string(ranks[t]) +
+                                             " is already deleted (pending)");
+    return flush_pending(c, s, ranks, count);
+  }
   DeviceDelta d;
   mknn_status st = delete_prepare(c, ranks, count, &d);
   if (st != MKNN_OK) return st;
   if (!d.on_device) return MKNN_OK;
-  hipStream_t s = (hipStream_t)stream;
   st = apply_delta(c, &d, s);
   if (st != MKNN_OK) return st;
   HIP_TRY(hipStreamSynchronize(s), "mknn_delete: synchronize");
@@ -1117,11 +1236,78 @@ mknn_status mknn_delete(mknn_cloud *c, const int32_t *ranks, int64_t count, void
   return MKNN_OK;
 }
 
+mknn_status mknn_delete_lazy(mknn_cloud *c, const int32_t *ranks, int64_t count, void *stream) {
+  clear_error();
+  if (!c) return set_error(MKNN_EINVAL, "mknn_delete_lazy: cloud is NULL");
+  if (count < 0 || (count > 0 && !ranks)) return set_error(MKNN_EINVAL, "mknn_delete_lazy: bad ranks");
+  if (count == 0) return MKNN_OK;
+  mknn_status st = check_uploaded(c, "mknn_delete_lazy");
+  if (st != MKNN_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = c->n;
+  if ((int64_t)c->lazy_mark.size() < n) c->lazy_mark.resize(n, 0);
+  std::vector<int32_t> sorted(ranks, ranks + count);
+  std::sort(sorted.begin(), sorted.end());
+  for (size_t t = 0; t < sorted.size(); ++t) {
+    const int32_t r = sorted[t];
+    if (r < 0 || r >= n || !c->live[r] || c->lazy_mark[r] || (t && sorted[t - 1] == r))
+      return set_error(MKNN_ENOTFOUND, "mknn_delete_lazy: rank " + std::to_string(r) +
+                                           " is unknown, deleted, pending or repeated");
+  }
+  if (c->nlive - (int64_t)c->lazy.size() - count < 1)
+    return set_error(MKNN_EINVAL, "mknn_delete_lazy: a cloud must keep at least one point");
+  const int64_t words = (n + 31) / 32;
+  if (!c->d_dead || c->dead_words < words) {
+    // a larger bitmap: apply what is pending (its bits then no longer matter) and start anew
+    st = flush_pending(c, s);
+    if (st != MKNN_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s), "mknn_delete_lazy: synchronize");
+    if (c->d_dead) (void)hipFree(c->d_dead);
+    c->d_dead = nullptr;
+    const int64_t cap = std::max<int64_t>(2 * words, 1024);
+    HIP_TRY(hipMalloc((void **)&c->d_dead, sizeof(uint32_t) * (size_t)cap), "mknn_delete_lazy: bitmap");
+    c->dead_words = cap;
+    if (!c->d_overflow)
+      HIP_TRY(hipMalloc((void **)&c->d_overflow, sizeof(uint32_t)), "mknn_delete_lazy: counter");
+    hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(256), dim3(256), 0, s, c->d_dead, cap, 0u);
+  }
+  int32_t *d_r = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&d_r, sizeof(int32_t) * (size_t)count, s), "mknn_delete_lazy: scratch");
+  hipError_t e = hipMemcpyAsync(d_r, ranks, sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(mark_dead_kernel, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, s,
+                       c->d_dead, d_r, count);
+    e = hipGetLastError();
+  }
+  (void)hipFreeAsync(d_r, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess)
+    return set_error(MKNN_EHIP, std::string("mknn_delete_lazy: ") + hipGetErrorName(e));
+  for (int64_t t = 0; t < count; ++t) {
+    c->lazy_mark[ranks[t]] = 1;
+    c->lazy.push_back(ranks[t]);
+  }
+  c->dev_lazy = (int64_t)c->lazy.size();
+  return MKNN_OK;
+}
+
+mknn_status mknn_delete_flush(mknn_cloud *c, void *stream) {
+  clear_error();
+  if (!c) return set_error(MKNN_EINVAL, "mknn_delete_flush: cloud is NULL");
+  return flush_pending(c, (hipStream_t)stream);
+}
+
+int64_t mknn_pending_deletes(const mknn_cloud *c) { return c ? (int64_t)c->lazy.size() : 0; }
+
 mknn_status mknn_insert(mknn_cloud *c, const float *xyz, int64_t count, void *stream) {
   clear_error();
   if (!c) return set_error(MKNN_EINVAL, "mknn_insert: cloud is NULL");
   if (count < 0 || (count > 0 && !xyz)) return set_error(MKNN_EINVAL, "mknn_insert: bad points");
   if (count == 0) return MKNN_OK;
+  if (!c->lazy.empty()) {
+    mknn_status st = flush_pending(c, (hipStream_t)stream);
+    if (st != MKNN_OK) return st;
+  }
   DeviceDelta d;
   mknn_status st = insert_prepare(c, xyz, count, &d);
   if (st != MKNN_OK) return st;
@@ -1134,7 +1320,7 @@ mknn_status mknn_insert(mknn_cloud *c, const float *xyz, int64_t count, void *st
   return MKNN_OK;
 }
 
-int64_t mknn_live_count(const mknn_cloud *c) { return c ? c->nlive : 0; }
+int64_t mknn_live_count(const mknn_cloud *c) { return c ? c->nlive - (int64_t)c->lazy.size() : 0; }
 
 int32_t mknn_head(const mknn_cloud *c) { return c ? c->head : -1; }
 
