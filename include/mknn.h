@@ -416,6 +416,17 @@ int32_t mknn_head(const mknn_cloud *c);
  * launched, and later requests on that cloud wait for the deletion).  With
  * MKNN_SERVER_BIND_AT_ADMISSION a request answers on the lists current when its wave is
  * launched, and never waits for a deletion's host part.
+ * MKNN_SERVER_LAZY_DELETE keeps that strict order without making requests wait for the
+ * host part of a deletion.  A deletion batch takes the next epoch of its cloud and is
+ * checked (as mknn_delete checks it; a bad batch fails whole) and marked in the cloud's
+ * device epoch array at once, on a marking stream, after any insertion queued before it
+ * has been applied.  A request over-fetches and filters the marks of the epochs submitted
+ * before it (mknn_delete_lazy describes the filter), so later deletions never touch its
+ * answer.  An update's device delta is applied only once every request submitted before
+ * it has completed, and a request with a row the filter could not certify is queued again
+ * and answered once the deletions it saw are applied.  Insertions are handled as in the
+ * strict order.  Not with MKNN_SERVER_PLAIN or MKNN_SERVER_BIND_AT_ADMISSION (EINVAL), and
+ * not on a cloud with deletions pending from mknn_delete_lazy (EINVAL at submission).
  * With MKNN_SERVER_PLAIN (the per-request baseline) every request is its own mknn_knn
  * launch, back to back in arrival order on one stream, at most 64 in flight and together
  * at most pool_queries queries; nstreams and max_wave_requests are then ignored.
@@ -427,6 +438,7 @@ typedef struct mknn_server mknn_server;
 
 #define MKNN_SERVER_PLAIN 1
 #define MKNN_SERVER_BIND_AT_ADMISSION 2
+#define MKNN_SERVER_LAZY_DELETE 4
 
 mknn_status mknn_server_create(int64_t pool_queries, int32_t nstreams, int32_t max_wave_requests,
                                int32_t flags, mknn_server **out);
@@ -451,7 +463,8 @@ mknn_status mknn_server_poll(mknn_server *s, uint64_t ticket, int32_t *done);
  * was launched; a deletion's device delta was enqueued), [2] completion observed (after the
  * copies to host memory).  updates_seen (may be NULL) receives, for a request, the number
  * of update batches (deletions and insertions) of this server applied to its cloud when it
- * was launched.  Returns the operation's own status. */
+ * was launched (with MKNN_SERVER_LAZY_DELETE: submitted on its cloud before it and not
+ * failed -- the ones its answer reflects).  Returns the operation's own status. */
 mknn_status mknn_server_wait(mknn_server *s, uint64_t ticket, double *times,
                              int64_t *updates_seen);
 /* Waves launched so far and the requests they held. */

@@ -56,6 +56,7 @@ class Request(ctypes.Structure):
 
 SERVER_PLAIN = 1
 SERVER_BIND_AT_ADMISSION = 2
+SERVER_LAZY_DELETE = 4
 BATCH_NO_SORT = 1
 BATCH_NO_GRAPH = 2
 

@@ -304,9 +304,10 @@ class Server:
 
     def __init__(self, pool_queries: int = 1 << 21, nstreams: int = 2,
                  max_wave_requests: int = 256, plain: bool = False,
-                 bind_at_admission: bool = False):
+                 bind_at_admission: bool = False, lazy_delete: bool = False):
         flags = ((_lib.SERVER_PLAIN if plain else 0) |
-                 (_lib.SERVER_BIND_AT_ADMISSION if bind_at_admission else 0))
+                 (_lib.SERVER_BIND_AT_ADMISSION if bind_at_admission else 0) |
+                 (_lib.SERVER_LAZY_DELETE if lazy_delete else 0))
         h = ctypes.c_void_p()
         check(_lib.lib().mknn_server_create(int(pool_queries), int(nstreams),
                                             int(max_wave_requests), flags, ctypes.byref(h)))

@@ -104,13 +104,16 @@ struct mknn_cloud {
   int64_t dev_n = 0;               // ranks the device lists cover
   float dev_lo[3] = {0, 0, 0}, dev_hi[3] = {0, 0, 0};   // bounding box (for query bucketing)
 
-  // Pending (lazy) deletions (mknn_delete_lazy): ranks marked as deleted that the lists
-  // still hold until mknn_delete_flush applies Alg. 3 to them.  The device bitmap has one
-  // bit per rank (1 = marked); a rank's bit stays set after its deletion is applied.
-  std::vector<int32_t> lazy;       // pending ranks, in arrival order
+  // Pending (lazy) deletions: ranks marked as deleted that the device lists still hold
+  // until Alg. 3 is applied to them.  The device array holds, per rank, the epoch of the
+  // batch that marked it (0: never marked); an entry keeps its epoch after its deletion is
+  // applied (the rank is then in no list).  mknn_delete_lazy marks in epochs
+  // lazy_epoch + 1, ...; a server marks in epochs of its own.
+  std::vector<int32_t> lazy;       // mknn_delete_lazy: pending ranks, in arrival order
   std::vector<uint8_t> lazy_mark;  // per rank: 1 = pending
-  uint32_t *d_dead = nullptr;      // device bitmap, dead_words words
-  int64_t dead_words = 0;
+  uint32_t lazy_epoch = 0;         // the last epoch mknn_delete_lazy marked in
+  uint32_t *d_dead = nullptr;      // device epochs, dead_cap entries
+  int64_t dead_cap = 0;
   uint32_t *d_overflow = nullptr;  // device counter of rows a lazy launch could not certify
   std::atomic<int64_t> dev_lazy{0};   // marked ranks that launches must filter (0: none)
 };

@@ -121,10 +121,19 @@ mknn_status apply_delta(mknn_cloud *c, DeviceDelta *d, hipStream_t s);
 // Applies a cloud's pending (lazy) deletions, and `more` ranks with them (synchronises s).
 mknn_status flush_pending(mknn_cloud *c, hipStream_t s, const int32_t *more = nullptr,
                           int64_t nmore = 0);
-// The server's batched run, filtering pending deletions, and the per-request counts of rows
-// it could not certify (pinned; valid once the run completed; NULL if nothing was filtered).
+// The server's batched run: request r filters the marks of epochs 1 .. epochs[r] of its
+// cloud's epoch array (none if 0).  batch_plan_overflow: the per-request counts of rows the
+// last run could not certify (pinned; valid once the run completed; NULL if nothing was
+// filtered).
 mknn_status batch_plan_run_pending(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
-                                   hipStream_t s);
+                                   hipStream_t s, const uint32_t *epochs);
+// Marks ranks[0 .. count) (host) with `epoch` in the cloud's epoch array on stream s
+// (asynchronous; the ranks are staged in a stream-ordered allocation).
+mknn_status mark_deleted_async(mknn_cloud *c, const int32_t *ranks, int64_t count,
+                               uint32_t epoch, hipStream_t s);
+// Makes the cloud's epoch array hold at least `need` entries (new entries 0), enqueued on s.
+// A replaced array is returned in *old for the caller to free once no work reads it.
+mknn_status ensure_epochs_async(mknn_cloud *c, int64_t need, hipStream_t s, uint32_t **old);
 const uint32_t *batch_plan_overflow(const mknn_batch_plan *p);
 // After a re-pack, the replaced arena is freed by the caller once no work reads it.
 void release_old_arena(DeviceDelta *d);

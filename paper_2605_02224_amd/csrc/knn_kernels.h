@@ -36,12 +36,15 @@ struct QueryArgs {
   int32_t *cnt_inserts;               // optional diagnostic: candidates inserted into N
   int32_t merge_min;                  // k <= 16: candidates per chunk from which a merge
                                       // network replaces one-by-one insertion (0 = default)
-  // Pending (lazy) deletions: ranks marked in `dead` are still listed but no longer part of
-  // the cloud.  The walk then runs for more neighbours than asked (k, or per query kq +
-  // kLazyMargin) and a row keeps the first kout (per query: kq) that are not marked; a row
-  // whose walk filled all its slots with fewer than kout unmarked sites cannot be certified
-  // and counts itself in *overflow.  dead == NULL: no pending deletions.
+  // Pending (lazy) deletions: dead[r] is the epoch (1, 2, ...) of the deletion batch that
+  // marked rank r, 0 if none.  The ranks marked in epochs 1 .. epoch are still listed but no
+  // longer part of this call's cloud (later epochs are deletions it must not see).  The walk
+  // then runs for more neighbours than asked (k, or per query kq + kLazyMargin) and a row
+  // keeps the first kout (per query: kq) not so marked; a row whose walk filled all its
+  // slots with fewer than kout such sites cannot be certified and counts itself in
+  // *overflow.  dead == NULL: no pending deletions.
   const uint32_t *dead;
+  uint32_t epoch;
   int32_t kout;
   uint32_t *overflow;
 };

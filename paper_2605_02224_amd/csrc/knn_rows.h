@@ -178,7 +178,9 @@ struct RowWalker {
     for (int t = 0; t < S; ++t) {
       const int32_t r = N.r[t];
       const bool listed = 16 * t + l < k && r != kEmpty;
-      const bool live = listed && ((a.dead[(uint32_t)r >> 5] >> (r & 31)) & 1u) == 0;
+      uint32_t e = 0;
+      if (listed) e = a.dead[r];
+      const bool live = listed && (e == 0 || e > a.epoch);
       const uint32_t lm = row_bits(__ballot(live), g);
       const int32_t pos = kept + __popc(lm & ((1u << l) - 1u));
       if (live && pos < ko) {

@@ -454,14 +454,15 @@ static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s, bool lazy) {
 
 namespace mknn {
 static mknn_status plan_run(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
-                            hipStream_t s, bool filter_pending);
+                            hipStream_t s, const uint32_t *epochs);
 
-// The server's form of a run: requests on clouds with pending deletions over-fetch and
-// filter (QueryArgs::dead) instead of applying the deletions first; the rows each request
-// could not certify are copied to the plan's pinned counters (batch_plan_overflow) behind
-// the run.
+// epochs == NULL: the public run; requests on clouds with deletions pending from
+// mknn_delete_lazy apply them first.  Otherwise (the server's run) request r with
+// epochs[r] > 0 over-fetches and filters the marks of epochs 1 .. epochs[r]
+// (QueryArgs::dead) of its cloud's epoch array; the rows each request could not certify are
+// copied to the plan's pinned counters (batch_plan_overflow) behind the run.
 static mknn_status plan_run(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
-                            hipStream_t s, bool filter_pending) {
+                            hipStream_t s, const uint32_t *epochs) {
   if (!p) return set_error(MKNN_EINVAL, "mknn_batch_plan_run: plan is NULL");
   if (nreq < 0 || (nreq > 0 && !reqs))
     return set_error(MKNN_EINVAL, "mknn_batch_plan_run: bad request array");
@@ -487,15 +488,16 @@ static mknn_status plan_run(mknn_batch_plan *p, const mknn_request *reqs, int32_
     if (q.nq < 0) return set_error(MKNN_EINVAL, who + ": nq < 0");
     if (q.nq > 0 && (!q.d_q || !q.d_idx || !q.d_dist))
       return set_error(MKNN_EINVAL, who + ": NULL buffer");
-    if (q.cloud->dev_lazy.load() != 0) {
-      if (filter_pending && q.cloud->d_dead) {
+    if (epochs) {
+      if (epochs[r] != 0) {
+        if (!q.cloud->d_dead) return set_error(MKNN_EINVAL, who + ": no marks to filter");
         lazy[r] = 1;
         any_lazy = true;
-      } else {
-        // the public batched call applies pending deletions first (synchronously)
-        st = flush_pending(const_cast<mknn_cloud *>(q.cloud), s);
-        if (st != MKNN_OK) return st;
       }
+    } else if (q.cloud->dev_lazy.load() != 0) {
+      // the public batched call applies pending deletions first (synchronously)
+      st = flush_pending(const_cast<mknn_cloud *>(q.cloud), s);
+      if (st != MKNN_OK) return st;
     }
     kwalk[r] = lazy[r] ? std::min<int32_t>(MKNN_KMAX, q.k + kLazyMargin) : q.k;
     qoff[r + 1] = qoff[r] + q.nq;
@@ -576,6 +578,7 @@ static mknn_status plan_run(mknn_batch_plan *p, const mknn_request *reqs, int32_
     args[r].k = kwalk[r];
     if (lazy[r]) {
       args[r].dead = q.cloud->d_dead;
+      args[r].epoch = epochs[r];
       args[r].kout = q.k;
       args[r].overflow = p->d_counters + kClasses * kQueues + r;
     }
@@ -632,8 +635,8 @@ static mknn_status plan_run(mknn_batch_plan *p, const mknn_request *reqs, int32_
 }
 
 mknn_status batch_plan_run_pending(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
-                                   hipStream_t s) {
-  return plan_run(p, reqs, nreq, s, true);
+                                   hipStream_t s, const uint32_t *epochs) {
+  return plan_run(p, reqs, nreq, s, epochs);
 }
 const uint32_t *batch_plan_overflow(const mknn_batch_plan *p) {
   return p->lazy_run ? p->h_overflow : nullptr;
@@ -726,7 +729,7 @@ void mknn_batch_plan_destroy(mknn_batch_plan *p) {
 mknn_status mknn_batch_plan_run(mknn_batch_plan *p, const mknn_request *reqs, int32_t nreq,
                                 void *stream) {
   clear_error();
-  return plan_run(p, reqs, nreq, (hipStream_t)stream, false);
+  return plan_run(p, reqs, nreq, (hipStream_t)stream, nullptr);
 }
 
 

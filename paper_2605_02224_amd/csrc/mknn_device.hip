@@ -267,7 +267,7 @@ static void free_device(mknn_cloud *c) {
   c->d_pts = nullptr;
   c->d_dead = nullptr;
   c->d_overflow = nullptr;
-  c->dead_words = 0;
+  c->dead_cap = 0;
   c->dev_bytes = 0;
   c->dev_version = ~0ull;
 }
@@ -464,6 +464,12 @@ mknn_status apply_delta(mknn_cloud *c, DeviceDelta *d, hipStream_t s) {
     d->old_ent = old_ent;
     d->old_lst = old_lst;
     d->old_pts = old_pts;
+    return MKNN_OK;
+  }
+  if (d->ranks.empty() && need == 0 && d->new_pts.empty()) {
+    // nothing changed (an empty batch)
+    note_device_state(c);
+    c->dev_version = c->version.load();
     return MKNN_OK;
   }
   d->desc.resize(d->ranks.size());
@@ -716,6 +722,7 @@ static mknn_status prepare_queries(const mknn_cloud *c, const float *d_q, int64_
 // MKNN_KMAX) and the rows keep the first kout unmarked ones (QueryArgs::dead).
 struct LazyLaunch {
   int32_t kout;
+  uint32_t epoch;   // filter the marks of epochs 1 .. epoch
 };
 
 static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
@@ -730,6 +737,7 @@ static mknn_status run_query(const mknn_cloud *c, const float *d_q, int64_t nq, 
   if (lazy) {
     a.dead = c->d_dead;
     a.kout = lazy->kout;
+    a.epoch = lazy->epoch;
     a.overflow = c->d_overflow;
   }
   a.q = d_q;
@@ -854,10 +862,48 @@ static mknn_status static_scratch(void **out) {
 // ---------------------------------------------------------------------------------------
 // Pending (lazy) deletions
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void mark_dead_kernel(uint32_t *bits, const int32_t *r,
-                                                        int64_t cnt) {
+__global__ __launch_bounds__(256) void mark_dead_kernel(uint32_t *dead, const int32_t *r,
+                                                        int64_t cnt, uint32_t epoch) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) atomicOr(&bits[(uint32_t)r[i] >> 5], 1u << (r[i] & 31));
+  if (i < cnt) dead[r[i]] = epoch;
+}
+
+mknn_status ensure_epochs_async(mknn_cloud *c, int64_t need, hipStream_t s, uint32_t **old) {
+  *old = nullptr;
+  if (c->d_dead && c->dead_cap >= need) return MKNN_OK;
+  const int64_t cap = std::max<int64_t>(2 * need, 4096);
+  uint32_t *nd = nullptr;
+  HIP_TRY(hipMalloc((void **)&nd, sizeof(uint32_t) * (size_t)cap), "deletion epochs");
+  hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(256), dim3(256), 0, s, nd, cap, 0u);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && c->d_dead)
+    e = hipMemcpyAsync(nd, c->d_dead, sizeof(uint32_t) * (size_t)c->dead_cap,
+                       hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(nd);
+    return set_error(MKNN_EHIP, std::string("deletion epochs: ") + hipGetErrorName(e));
+  }
+  *old = c->d_dead;
+  c->d_dead = nd;
+  c->dead_cap = cap;
+  return MKNN_OK;
+}
+
+mknn_status mark_deleted_async(mknn_cloud *c, const int32_t *ranks, int64_t count,
+                               uint32_t epoch, hipStream_t s) {
+  if (count == 0) return MKNN_OK;
+  int32_t *d_r = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&d_r, sizeof(int32_t) * (size_t)count, s), "mark deletions");
+  hipError_t e = hipMemcpyAsync(d_r, ranks, sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(mark_dead_kernel, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, s,
+                       c->d_dead, d_r, count, epoch);
+    e = hipGetLastError();
+  }
+  (void)hipFreeAsync(d_r, s);
+  if (e != hipSuccess) return set_error(MKNN_EHIP, std::string("mark deletions: ") + hipGetErrorName(e));
+  return MKNN_OK;
 }
 
 // Applies the pending deletions (Alg. 3 on the host, the delta on s); synchronises s.
@@ -891,7 +937,7 @@ static mknn_status run_with_pending(const mknn_cloud *cc, int32_t kout, hipStrea
                                     const char *who, Launch launch) {
   mknn_cloud *c = const_cast<mknn_cloud *>(cc);
   if (c->dev_lazy.load() == 0 || !c->d_dead) return launch(nullptr);
-  const LazyLaunch lz{kout};
+  const LazyLaunch lz{kout, c->lazy_epoch};
   hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(1), dim3(64), 0, s, c->d_overflow, (int64_t)1, 0u);
   mknn_status st = launch(&lz);
   if (st != MKNN_OK) return st;
@@ -1256,37 +1302,28 @@ mknn_status mknn_delete_lazy(mknn_cloud *c, const int32_t *ranks, int64_t count,
   }
   if (c->nlive - (int64_t)c->lazy.size() - count < 1)
     return set_error(MKNN_EINVAL, "mknn_delete_lazy: a cloud must keep at least one point");
-  const int64_t words = (n + 31) / 32;
-  if (!c->d_dead || c->dead_words < words) {
-    // a larger bitmap: apply what is pending (its bits then no longer matter) and start anew
+  if (!c->d_dead || c->dead_cap < n) {
+    // a larger array: apply what is pending (its marks then no longer matter) and start anew
     st = flush_pending(c, s);
     if (st != MKNN_OK) return st;
     HIP_TRY(hipStreamSynchronize(s), "mknn_delete_lazy: synchronize");
     if (c->d_dead) (void)hipFree(c->d_dead);
     c->d_dead = nullptr;
-    const int64_t cap = std::max<int64_t>(2 * words, 1024);
-    HIP_TRY(hipMalloc((void **)&c->d_dead, sizeof(uint32_t) * (size_t)cap), "mknn_delete_lazy: bitmap");
-    c->dead_words = cap;
-    if (!c->d_overflow)
-      HIP_TRY(hipMalloc((void **)&c->d_overflow, sizeof(uint32_t)), "mknn_delete_lazy: counter");
-    hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(256), dim3(256), 0, s, c->d_dead, cap, 0u);
+    c->dead_cap = 0;
+    uint32_t *old = nullptr;
+    st = ensure_epochs_async(c, n, s, &old);
+    if (st != MKNN_OK) return st;
   }
-  int32_t *d_r = nullptr;
-  HIP_TRY(hipMallocAsync((void **)&d_r, sizeof(int32_t) * (size_t)count, s), "mknn_delete_lazy: scratch");
-  hipError_t e = hipMemcpyAsync(d_r, ranks, sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(mark_dead_kernel, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, s,
-                       c->d_dead, d_r, count);
-    e = hipGetLastError();
-  }
-  (void)hipFreeAsync(d_r, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess)
-    return set_error(MKNN_EHIP, std::string("mknn_delete_lazy: ") + hipGetErrorName(e));
+  if (!c->d_overflow)
+    HIP_TRY(hipMalloc((void **)&c->d_overflow, sizeof(uint32_t)), "mknn_delete_lazy: counter");
+  st = mark_deleted_async(c, ranks, count, c->lazy_epoch + 1, s);
+  if (st != MKNN_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s), "mknn_delete_lazy: synchronize");
   for (int64_t t = 0; t < count; ++t) {
     c->lazy_mark[ranks[t]] = 1;
     c->lazy.push_back(ranks[t]);
   }
+  ++c->lazy_epoch;
   c->dev_lazy = (int64_t)c->lazy.size();
   return MKNN_OK;
 }

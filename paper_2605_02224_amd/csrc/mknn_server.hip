@@ -22,6 +22,16 @@
 // MKNN_SERVER_BIND_AT_ADMISSION a request binds to the lists current when its wave is
 // launched, so requests never wait for the host part of a deletion.
 //
+// With MKNN_SERVER_LAZY_DELETE the order is the strict one, but no request waits for the
+// host part of a deletion.  A deletion batch gets the next epoch of its cloud and is marked
+// at once in the cloud's device epoch array (a kernel on a marking stream; later waves on
+// the cloud wait for it).  A request filters the marks of the epochs submitted before it:
+// it walks k + 16 neighbours on the lists it finds and keeps the first k unmarked ones,
+// exact whenever the walk holds k of them (Sec. 4.3's lists are not needed for that).  The
+// device delta of a deletion (or insertion) is applied once every request submitted before
+// it has completed, so those requests never see its lists.  A request with a row the walk
+// could not certify is queued again and answered once the deletions it saw are applied.
+//
 // Insertion batches (points appended as new ranks) are update batches of the same kind:
 // they share the per-cloud order, the worker threads, the delta path and the counts of
 // update batches a request saw.  Below, "deletion" stands for either kind.
@@ -39,7 +49,9 @@
 #include <condition_variable>
 #include <deque>
 #include <list>
+#include <map>
 #include <memory>
+#include <set>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -69,6 +81,14 @@ struct ServerOp {
   DeviceDelta delta;
   double t_submit = 0, t_launch = 0, t_done = 0;
   int64_t seen = 0;                 // update batches applied to the cloud at launch
+  // lazy deletion: an update's sequence number on its cloud, or for a request the number of
+  // update batches submitted on its cloud before it; a deletion's epoch, or for a request
+  // the number of deletion epochs before it
+  int64_t seq = 0;
+  uint32_t epoch = 0;
+  bool marked = false;              // a deletion's marks are enqueued
+  bool rerun = false;               // a request answered again after an uncertified row
+  uint32_t *old_dead = nullptr;     // an insertion's replaced epoch array
   mknn_status status = MKNN_OK;
   std::string err;
   bool done = false;
@@ -93,6 +113,20 @@ struct Applying {   // a deletion whose device delta is on the deletion stream
   hipEvent_t ev;
 };
 
+// Lazy deletion: the order of one cloud's updates and requests.
+struct CloudView {
+  int64_t updates = 0;              // update batches submitted so far
+  uint32_t epochs = 0;              // deletion epochs handed out so far
+  std::set<uint32_t> marked_epochs; // deletions marked, delta not yet enqueued
+  int64_t live = 0;                 // live points once the marked deletions are applied
+  int64_t inserting = -1;           // sequence number of an insertion in progress
+  bool grown = false;               // an insertion replaced the epoch array since the last mark
+  std::unordered_set<int32_t> marked;        // ranks marked, not yet applied
+  std::map<int64_t, int64_t> outstanding;    // requests waiting or in flight, by `seq`
+  std::vector<int64_t> failed;               // sequence numbers of failed update batches
+  std::deque<OpPtr> gated;          // host part done; the delta waits for earlier requests
+};
+
 }  // namespace mknn
 
 using namespace mknn;
@@ -101,6 +135,11 @@ struct mknn_server {
   int device = 0;
   bool plain = false;
   bool strict = true;               // requests see exactly the deletions submitted before them
+  bool lazy = false;                // strict order by marking deletions (MKNN_SERVER_LAZY_DELETE)
+  hipStream_t mark_stream = nullptr;
+  std::unordered_map<mknn_cloud *, CloudView> views;
+  std::unordered_map<mknn_cloud *, hipEvent_t> mark_ev;   // after the cloud's last marks
+  int64_t reruns = 0;
   int64_t slot_queries = 0;         // largest wave (queries) one slot takes
   int64_t pool_queries = 0;
   int64_t inflight_queries = 0;     // plain mode: queries of the requests in flight
@@ -157,6 +196,28 @@ static void finish_op(mknn_server *s, const OpPtr &op, mknn_status st, const std
   s->cv_done.notify_all();
 }
 
+// Lazy deletion: whether a request whose view holds the deletion epochs 1 .. epoch still
+// finds some of them marked and not yet applied on the device lists.
+static bool needs_filter(const CloudView &v, uint32_t epoch) {
+  return !v.marked_epochs.empty() && *v.marked_epochs.begin() <= epoch;
+}
+
+// Lazy deletion: a request no longer holds back the deltas of later updates on its cloud.
+static void release_outstanding(mknn_server *s, const OpPtr &op) {
+  auto &o = s->views[op->cloud].outstanding;
+  auto it = o.find(op->seq);
+  if (it != o.end() && --it->second == 0) o.erase(it);
+}
+
+// Lazy deletion: queue a request again, at its place in arrival order (mu held).
+static void requeue(mknn_server *s, const OpPtr &op) {
+  op->rerun = true;
+  ++s->reruns;
+  auto it = s->pending.begin();
+  while (it != s->pending.end() && (*it)->ticket < op->ticket) ++it;
+  s->pending.insert(it, op);
+}
+
 // Launch one wave of requests on slot x (mu held).
 static void launch_wave(mknn_server *s, int x, std::vector<OpPtr> &wave) {
   Slot &sl = s->slots[x];
@@ -166,8 +227,15 @@ static void launch_wave(mknn_server *s, int x, std::vector<OpPtr> &wave) {
   for (const OpPtr &op : wave) {
     op->t_launch = t_launch;
     sl.clouds.insert(op->cloud);
-    auto it = s->applied.find(op->cloud);
-    op->seen = it == s->applied.end() ? 0 : it->second;
+    if (s->lazy) {
+      // every update batch before the request is in its view, the failed ones aside
+      const CloudView &v = s->views[op->cloud];
+      op->seen = op->seq - (int64_t)std::count_if(v.failed.begin(), v.failed.end(),
+                                                  [&](int64_t u) { return u < op->seq; });
+    } else {
+      auto it = s->applied.find(op->cloud);
+      op->seen = it == s->applied.end() ? 0 : it->second;
+    }
     // a prefix beyond the lists the request runs on (possible when bound at admission
     // while an insertion of its submitter was pending) covers them all
     if (op->req.m > op->cloud->dev_n) op->req.m = 0;
@@ -175,6 +243,8 @@ static void launch_wave(mknn_server *s, int x, std::vector<OpPtr> &wave) {
   for (mknn_cloud *c : sl.clouds) {
     auto it = s->ready_ev.find(c);
     if (it != s->ready_ev.end()) (void)hipStreamWaitEvent(sl.stream, it->second, 0);
+    auto im = s->mark_ev.find(c);
+    if (im != s->mark_ev.end()) (void)hipStreamWaitEvent(sl.stream, im->second, 0);
   }
   mknn_status st = MKNN_OK;
   if (s->plain) {
@@ -185,7 +255,16 @@ static void launch_wave(mknn_server *s, int x, std::vector<OpPtr> &wave) {
     std::vector<mknn_request> reqs;
     reqs.reserve(wave.size());
     for (const OpPtr &op : wave) reqs.push_back(op->req);
-    st = mknn_batch_plan_run(sl.plan, reqs.data(), (int32_t)reqs.size(), sl.stream);
+    if (s->lazy) {
+      // filter the marks of the deletions before each request, unless all are applied
+      std::vector<uint32_t> ep;
+      ep.reserve(wave.size());
+      for (const OpPtr &op : wave)
+        ep.push_back(needs_filter(s->views[op->cloud], op->epoch) ? op->epoch : 0u);
+      st = batch_plan_run_pending(sl.plan, reqs.data(), (int32_t)reqs.size(), sl.stream, ep.data());
+    } else {
+      st = mknn_batch_plan_run(sl.plan, reqs.data(), (int32_t)reqs.size(), sl.stream);
+    }
   }
   const std::string err = st == MKNN_OK ? "" : mknn_last_error();
   for (const OpPtr &op : wave) {
@@ -198,7 +277,10 @@ static void launch_wave(mknn_server *s, int x, std::vector<OpPtr> &wave) {
       (void)hipMemcpyAsync(op->h_dist, r.d_dist, cnt * sizeof(float), hipMemcpyDeviceToHost, sl.stream);
   }
   if (st != MKNN_OK) {
-    for (const OpPtr &op : wave) finish_op(s, op, st, err);
+    for (const OpPtr &op : wave) {
+      if (s->lazy) release_outstanding(s, op);
+      finish_op(s, op, st, err);
+    }
     sl.ops.clear();
     return;
   }
@@ -241,6 +323,150 @@ static bool server_idle(const mknn_server *s) {
   bool idle = s->pending.empty() && s->blocked.empty() && s->applying.empty();
   for (const Slot &sl : s->slots) idle &= !sl.busy;
   return idle;
+}
+
+// Enqueue the device delta of an update whose host part finished (mu held): ordered after
+// the in-flight waves that read the cloud (and before a replaced arena is freed, when the
+// applied event completes); then the cloud's next update may start.
+static void enqueue_delta(mknn_server *s, const OpPtr &op) {
+  mknn_cloud *c = op->cloud;
+  if (op->status == MKNN_OK && op->delta.on_device) {
+    for (Slot &sl : s->slots)
+      if (sl.busy && sl.clouds.count(c)) (void)hipStreamWaitEvent(s->del_stream, sl.ev, 0);
+    const double t0 = now_s();
+    op->t_launch = t0;
+    s->repacks += op->delta.repack ? 1 : 0;
+    mknn_status st = apply_delta(c, &op->delta, s->del_stream);
+    if (st == MKNN_OK && s->lazy && op->is_insert && c->d_dead && c->dead_cap < c->n) {
+      // the epoch array grows with the cloud (the old one is freed with the old arena)
+      st = ensure_epochs_async(c, c->n, s->del_stream, &op->old_dead);
+      s->views[c].grown = true;
+    }
+    s->t_apply += now_s() - t0;
+    if (st != MKNN_OK) {
+      op->status = st;
+      op->err = mknn_last_error();
+    }
+  }
+  s->blocked.erase(c);
+  if (s->lazy) {
+    CloudView &v = s->views[c];
+    if (op->is_insert) {
+      v.inserting = -1;
+    } else {
+      v.marked_epochs.erase(op->epoch);
+      for (int32_t r : op->ranks) v.marked.erase(r);
+    }
+    if (op->status != MKNN_OK) {
+      v.failed.push_back(op->seq);
+      v.live = c->nlive - (int64_t)v.marked.size();
+    } else if (op->is_insert) {
+      v.live += (int64_t)op->xyz.size() / 3;
+    }
+  }
+  if (op->status != MKNN_OK) {
+    finish_op(s, op, op->status, op->err);
+    return;
+  }
+  ++s->applied[c];
+  hipEvent_t &rev = s->ready_ev[c];
+  if (!rev) rev = take_event(s);
+  hipEvent_t done_ev = take_event(s);
+  (void)hipEventRecord(rev, s->del_stream);
+  (void)hipEventRecord(done_ev, s->del_stream);
+  s->applying.push_back({op, done_ev});
+}
+
+// Lazy deletion: the deltas whose earlier requests have all completed, in order (mu held).
+static void apply_gated(mknn_server *s) {
+  for (auto &kv : s->views) {
+    CloudView &v = kv.second;
+    while (!v.gated.empty()) {
+      const OpPtr op = v.gated.front();
+      // a request with seq <= op->seq was submitted before the update
+      if (!v.outstanding.empty() && v.outstanding.begin()->first <= op->seq) break;
+      v.gated.pop_front();
+      enqueue_delta(s, op);
+    }
+  }
+}
+
+// Lazy deletion: mark the waiting deletion batches, in arrival order per cloud, once no
+// insertion before them is still to be applied (mu held).  A batch is checked as
+// mknn_delete checks it; a bad one fails whole and marks nothing.
+static void mark_deletions(mknn_server *s) {
+  std::unordered_set<mknn_cloud *> ins_held;
+  for (auto it = s->pending.begin(); it != s->pending.end();) {
+    const OpPtr op = *it;
+    mknn_cloud *c = op->cloud;
+    if (!op->is_update || op->marked) {
+      ++it;
+      continue;
+    }
+    if (op->is_insert) {
+      ins_held.insert(c);
+      ++it;
+      continue;
+    }
+    CloudView &v = s->views[c];
+    if (ins_held.count(c) || v.inserting >= 0) {
+      ++it;
+      continue;
+    }
+    // no insertion runs on the cloud now, so its size and live flags hold still; the
+    // ranks of earlier marked batches are in v.marked (their live flags may be changing)
+    mknn_status st = MKNN_OK;
+    std::string err;
+    std::vector<int32_t> sorted(op->ranks);
+    std::sort(sorted.begin(), sorted.end());
+    for (size_t t = 0; t < sorted.size() && st == MKNN_OK; ++t) {
+      const int32_t r = sorted[t];
+      if (r < 0 || r >= c->n || v.marked.count(r) || !c->live[r] || (t && sorted[t - 1] == r)) {
+        st = MKNN_ENOTFOUND;
+        err = "mknn_server_delete: rank " + std::to_string(r) +
+              " is unknown, deleted, pending or repeated";
+      }
+    }
+    if (st == MKNN_OK && v.live - (int64_t)sorted.size() < 1) {
+      st = MKNN_EINVAL;
+      err = "mknn_server_delete: a cloud must keep at least one point";
+    }
+    if (st == MKNN_OK && !sorted.empty()) {
+      if (v.grown) {
+        // an insertion replaced the array on the deletion stream
+        auto ie = s->ready_ev.find(c);
+        if (ie != s->ready_ev.end()) (void)hipStreamWaitEvent(s->mark_stream, ie->second, 0);
+        v.grown = false;
+      }
+      uint32_t *old = nullptr;
+      st = ensure_epochs_async(c, c->n, s->mark_stream, &old);
+      if (st == MKNN_OK && old) {
+        // only before the first marks of this server can the array be too small: no wave
+        // reads the old one
+        (void)hipStreamSynchronize(s->mark_stream);
+        (void)hipFree(old);
+      }
+      if (st == MKNN_OK) st = mark_deleted_async(c, op->ranks.data(), (int64_t)op->ranks.size(),
+                                                 op->epoch, s->mark_stream);
+      if (st != MKNN_OK) err = mknn_last_error();
+    }
+    if (st != MKNN_OK) {
+      v.failed.push_back(op->seq);
+      --s->pending_updates;
+      it = s->pending.erase(it);
+      finish_op(s, op, st, err);
+      continue;
+    }
+    v.live -= (int64_t)sorted.size();
+    v.marked.insert(sorted.begin(), sorted.end());
+    if (!sorted.empty()) v.marked_epochs.insert(op->epoch);
+    hipEvent_t &mev = s->mark_ev[c];
+    if (!mev) mev = take_event(s);
+    (void)hipEventRecord(mev, s->mark_stream);
+    op->marked = true;
+    op->t_launch = now_s();
+    ++it;
+  }
 }
 
 // The scheduler thread owns the slots and the list of deltas being applied; it polls their
@@ -286,7 +512,16 @@ static void scheduler_loop(mknn_server *s) {
     // ---- completions of waves
     for (int x : done_slots) {
       Slot &sl = s->slots[x];
-      for (const OpPtr &op : sl.ops) finish_op(s, op, MKNN_OK, "");
+      const uint32_t *ovf = s->lazy && sl.plan ? batch_plan_overflow(sl.plan) : nullptr;
+      for (size_t i = 0; i < sl.ops.size(); ++i) {
+        const OpPtr &op = sl.ops[i];
+        if (ovf && ovf[i] != 0) {
+          requeue(s, op);   // a row could not be certified: answer again on applied lists
+          continue;
+        }
+        if (s->lazy) release_outstanding(s, op);
+        finish_op(s, op, MKNN_OK, "");
+      }
       sl.ops.clear();
       sl.clouds.clear();
       s->inflight_queries -= sl.queries;
@@ -302,6 +537,10 @@ static void scheduler_loop(mknn_server *s) {
         release_old_arena(&ap.op->delta);
         s->t_release += now_s() - t0;
       }
+      if (ap.op->old_dead) {
+        (void)hipFree(ap.op->old_dead);
+        ap.op->old_dead = nullptr;
+      }
       finish_op(s, ap.op, MKNN_OK, "");
       s->free_events.push_back(ap.ev);
       s->applying.erase(s->applying.begin() + (std::ptrdiff_t)done_apps[t]);
@@ -311,34 +550,14 @@ static void scheduler_loop(mknn_server *s) {
     while (!s->del_done.empty()) {
       OpPtr op = s->del_done.front();
       s->del_done.pop_front();
-      mknn_cloud *c = op->cloud;
-      if (op->status == MKNN_OK && op->delta.on_device) {
-        // the in-flight waves on this cloud finish before the switch (and before a replaced
-        // arena is freed, when the applied event completes)
-        for (Slot &sl : s->slots)
-          if (sl.busy && sl.clouds.count(c)) (void)hipStreamWaitEvent(s->del_stream, sl.ev, 0);
-        const double t0 = now_s();
-        op->t_launch = t0;
-        s->repacks += op->delta.repack ? 1 : 0;
-        mknn_status st = apply_delta(c, &op->delta, s->del_stream);
-        s->t_apply += now_s() - t0;
-        if (st != MKNN_OK) {
-          op->status = st;
-          op->err = mknn_last_error();
-        }
-      }
-      s->blocked.erase(c);
-      if (op->status != MKNN_OK) {
-        finish_op(s, op, op->status, op->err);
-        continue;
-      }
-      ++s->applied[c];
-      hipEvent_t &rev = s->ready_ev[c];
-      if (!rev) rev = take_event(s);
-      hipEvent_t done_ev = take_event(s);
-      (void)hipEventRecord(rev, s->del_stream);
-      (void)hipEventRecord(done_ev, s->del_stream);
-      s->applying.push_back({op, done_ev});
+      if (s->lazy)
+        s->views[op->cloud].gated.push_back(op);   // after the requests submitted before it
+      else
+        enqueue_delta(s, op);
+    }
+    if (s->lazy) {
+      apply_gated(s);
+      mark_deletions(s);
     }
     // ---- form waves on the free slots, in arrival order
     for (int x = 0; x < (int)s->slots.size(); ++x) {
@@ -349,7 +568,21 @@ static void scheduler_loop(mknn_server *s) {
       for (auto it = s->pending.begin(); it != s->pending.end();) {
         const OpPtr &op = *it;
         mknn_cloud *c = op->cloud;
-        if (op->is_update || (s->strict && (s->blocked.count(c) || held.count(c)))) {
+        if (s->lazy) {
+          // held: behind a deletion not yet marked or an insertion not yet applied, or
+          // (answered again) until the deletions in its view are applied
+          if (op->is_update) {
+            if (op->is_insert || !op->marked) held.insert(c);
+            ++it;
+            continue;
+          }
+          const CloudView &v = s->views[c];
+          if (held.count(c) || (v.inserting >= 0 && op->seq > v.inserting) ||
+              (op->rerun && needs_filter(v, op->epoch))) {
+            ++it;
+            continue;
+          }
+        } else if (op->is_update || (s->strict && (s->blocked.count(c) || held.count(c)))) {
           if (s->strict) held.insert(c);
           ++it;
           continue;
@@ -379,7 +612,13 @@ static void scheduler_loop(mknn_server *s) {
           ++it;
           continue;
         }
-        if (!s->blocked.count(c) && !del_held.count(c) && !(s->strict && held.count(c))) {
+        bool start = !s->blocked.count(c) && !del_held.count(c);
+        if (s->lazy)   // a deletion once marked; an insertion once no earlier request waits
+          start = start && (op->is_insert ? !held.count(c) : op->marked);
+        else
+          start = start && !(s->strict && held.count(c));
+        if (start) {
+          if (s->lazy && op->is_insert) s->views[c].inserting = op->seq;
           s->blocked.insert(c);
           s->del_queue.push_back(op);
           --s->pending_updates;
@@ -395,6 +634,19 @@ static void scheduler_loop(mknn_server *s) {
   }
 }
 
+// Lazy deletion: the view of a cloud, made at the cloud's first operation (mu held).  The
+// cloud must have no deletions pending from mknn_delete_lazy.
+static mknn_status take_view(mknn_server *s, mknn_cloud *c, const char *who) {
+  if (s->views.count(c)) return MKNN_OK;
+  if (!c->lazy.empty())
+    return set_error(MKNN_EINVAL, std::string(who) + ": the cloud has deletions pending from "
+                                                     "mknn_delete_lazy (apply them first)");
+  CloudView &v = s->views[c];
+  v.live = c->nlive;
+  v.epochs = c->lazy_epoch;          // above the epochs already in the cloud's array
+  return MKNN_OK;
+}
+
 }  // namespace mknn
 
 extern "C" {
@@ -408,12 +660,17 @@ mknn_status mknn_server_create(int64_t pool_queries, int32_t nstreams, int32_t m
   *out = nullptr;
   const bool plain = (flags & MKNN_SERVER_PLAIN) != 0;
   const bool strict = (flags & MKNN_SERVER_BIND_AT_ADMISSION) == 0;
+  const bool lazy = (flags & MKNN_SERVER_LAZY_DELETE) != 0;
   if (nstreams < 1 || nstreams > 8 || pool_queries < 1 || max_wave_requests < 1)
     return set_error(MKNN_EINVAL, "mknn_server_create: bad capacity");
+  if (lazy && (plain || !strict))
+    return set_error(MKNN_EINVAL, "mknn_server_create: MKNN_SERVER_LAZY_DELETE is a form of the "
+                                  "strict order of the batched server");
   mknn_server *s = new (std::nothrow) mknn_server();
   if (!s) return set_error(MKNN_ENOMEM, "mknn_server_create: out of host memory");
   s->plain = plain;
   s->strict = strict;
+  s->lazy = lazy;
   s->pool_queries = pool_queries;
   s->slot_queries = plain ? pool_queries : std::max<int64_t>(1, pool_queries / nstreams);
   s->max_wave = plain ? 1 : max_wave_requests;
@@ -436,6 +693,7 @@ mknn_status mknn_server_create(int64_t pool_queries, int32_t nstreams, int32_t m
     }
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->del_stream, hipStreamNonBlocking);
+  if (e == hipSuccess && lazy) e = hipStreamCreateWithFlags(&s->mark_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     mknn_server_destroy(s);
     return set_error(MKNN_EHIP, std::string("mknn_server_create: ") + hipGetErrorName(e));
@@ -470,12 +728,22 @@ mknn_status mknn_server_submit(mknn_server *s, const mknn_request *req, int32_t 
   op->t_submit = now_s();
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return set_error(MKNN_EINVAL, "mknn_server_submit: server is stopping");
+  if (s->lazy) {
+    mknn_status st = take_view(s, op->cloud, "mknn_server_submit");
+    if (st != MKNN_OK) return st;
+  }
   op->ticket = s->next_ticket++;
   *ticket = op->ticket;
   s->ops[op->ticket] = op;
   if (r.nq == 0) {
     finish_op(s, op, MKNN_OK, "");
     return MKNN_OK;
+  }
+  if (s->lazy) {
+    CloudView &v = s->views[op->cloud];
+    op->seq = v.updates;
+    op->epoch = v.epochs;
+    ++v.outstanding[op->seq];
   }
   s->pending.push_back(op);
   wake_scheduler(s);
@@ -494,6 +762,13 @@ mknn_status mknn_server_delete(mknn_server *s, mknn_cloud *c, const int32_t *ran
   op->t_submit = now_s();
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return set_error(MKNN_EINVAL, "mknn_server_delete: server is stopping");
+  if (s->lazy) {
+    mknn_status st = take_view(s, c, "mknn_server_delete");
+    if (st != MKNN_OK) return st;
+    CloudView &v = s->views[c];
+    op->seq = v.updates++;
+    op->epoch = ++v.epochs;
+  }
   op->ticket = s->next_ticket++;
   *ticket = op->ticket;
   s->ops[op->ticket] = op;
@@ -516,6 +791,11 @@ mknn_status mknn_server_insert(mknn_server *s, mknn_cloud *c, const float *xyz, 
   op->t_submit = now_s();
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return set_error(MKNN_EINVAL, "mknn_server_insert: server is stopping");
+  if (s->lazy) {
+    mknn_status st = take_view(s, c, "mknn_server_insert");
+    if (st != MKNN_OK) return st;
+    op->seq = s->views[c].updates++;
+  }
   op->ticket = s->next_ticket++;
   *ticket = op->ticket;
   s->ops[op->ticket] = op;
@@ -575,9 +855,10 @@ void mknn_server_destroy(mknn_server *s) {
   if (std::getenv("MKNN_SERVER_TRACE"))
     std::fprintf(stderr,
                  "[mknn server] waves %lld (requests %lld): launch %.3f s, apply %.3f s "
-                 "(%lld re-packs), arena release %.3f s, deletion host work %.3f s\n",
+                 "(%lld re-packs), arena release %.3f s, deletion host work %.3f s, "
+                 "requests answered again %lld\n",
                  (long long)s->waves, (long long)s->wave_requests, s->t_launch, s->t_apply,
-                 (long long)s->repacks, s->t_release, s->t_prepare);
+                 (long long)s->repacks, s->t_release, s->t_prepare, (long long)s->reruns);
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->cv_work.notify_all();
@@ -596,6 +877,12 @@ void mknn_server_destroy(mknn_server *s) {
     (void)hipStreamSynchronize(s->del_stream);
     (void)hipStreamDestroy(s->del_stream);
   }
+  if (s->mark_stream) {
+    (void)hipStreamSynchronize(s->mark_stream);
+    (void)hipStreamDestroy(s->mark_stream);
+  }
+  for (auto &kv : s->mark_ev)
+    if (kv.second) (void)hipEventDestroy(kv.second);
   for (auto &kv : s->ready_ev)
     if (kv.second) (void)hipEventDestroy(kv.second);
   for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);

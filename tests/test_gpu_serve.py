@@ -98,13 +98,15 @@ def test_host_outputs_match_device_outputs(env):
     srv.close()
 
 
-@pytest.mark.parametrize("bind_at_admission", [False, True])
-def test_deletions_between_batches(env, bind_at_admission):
+@pytest.mark.parametrize("order", ["strict", "bind_at_admission", "lazy_delete"])
+def test_deletions_between_batches(env, order):
     """Requests and deletion batches interleaved on several clouds.  Each request reports how
     many deletion batches of its cloud it saw and must equal the oracle on the live set after
-    exactly those.  In the default order that number is the count of deletions submitted
+    exactly those.  In the strict orders (the default, and its form that filters marked
+    deletions instead of waiting for them) that number is the count of deletions submitted
     before the request.  Enough deletions are made on the small cloud to run out of arena
     slack, which forces a full re-pack while other waves are in flight."""
+    bind_at_admission = order == "bind_at_admission"
     torch, oracle, A, W = env
     clouds = _clouds(env, 4, seed=6, nmax=20000)
     P0 = W.random_cloud(3000, seed=77, shape="sphere").by_rank
@@ -113,7 +115,7 @@ def test_deletions_between_batches(env, bind_at_admission):
     masks = [[np.ones(P.shape[0], np.uint8)] for P, _ in clouds]   # live set after v deletions
     rng = np.random.default_rng(7)
     srv = A.Server(pool_queries=1 << 15, nstreams=2, max_wave_requests=16,
-                   bind_at_admission=bind_at_admission)
+                   bind_at_admission=bind_at_admission, lazy_delete=order == "lazy_delete")
     log = []
     for step in range(70):
         c = int(rng.integers(len(clouds)))
@@ -189,8 +191,8 @@ def test_errors_and_empty_requests(env):
     srv.close()
 
 
-@pytest.mark.parametrize("plain", [False, True])
-def test_insertions_and_deletions_between_batches(env, plain):
+@pytest.mark.parametrize("mode", ["batched", "plain", "lazy_delete"])
+def test_insertions_and_deletions_between_batches(env, mode):
     """Insertion batches go through the same ordered update path as deletions: every
     request sees exactly the update batches submitted before it on its cloud, and equals
     the oracle on the points present after those (new points take the next ranks)."""
@@ -204,7 +206,8 @@ def test_insertions_and_deletions_between_batches(env, plain):
     states = [[(n, np.concatenate([np.ones(n, np.uint8), np.zeros(P.shape[0] - n, np.uint8)]))]
               for (P, _), n in zip(clouds, n0)]
     rng = np.random.default_rng(12)
-    srv = A.Server(pool_queries=1 << 15, nstreams=2, max_wave_requests=16, plain=plain)
+    srv = A.Server(pool_queries=1 << 15, nstreams=2, max_wave_requests=16, plain=mode == "plain",
+                   lazy_delete=mode == "lazy_delete")
     log = []
     for step in range(60):
         c = int(rng.integers(2))
@@ -249,3 +252,84 @@ def test_insertions_and_deletions_between_batches(env, plain):
     for c, (P, cl) in enumerate(clouds):
         n, live = states[c][-1]
         assert cl.n == n and cl.live_count == int(live.sum())
+
+
+def test_lazy_delete_answers_uncertified_rows_again(env):
+    """Deleting the 80 nearest sites of some queries leaves their k + 16 walks on the
+    un-updated lists without k unmarked sites; those requests are answered again once the
+    deletions in their view are applied.  Requests submitted before each deletion still see
+    its sites, and the ones after it do not."""
+    torch, oracle, A, W = env
+    P = W.random_cloud(30000, seed=95, shape="torus").by_rank
+    cl = A.Cloud.build(P).upload()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(96)
+    centres = P[rng.choice(P.shape[0], 6, replace=False)]
+    masks = [np.ones(P.shape[0], np.uint8)]
+    srv = A.Server(pool_queries=1 << 15, nstreams=2, max_wave_requests=16, lazy_delete=True)
+    log = []
+    for i, c0 in enumerate(centres):
+        live = masks[-1]
+        ri, _, rD = oracle.knn_bruteforce(P, c0[None, :], 80, live=live)
+        # queries well inside the disc of the 80 sites about to be deleted
+        sd = float(np.sqrt(rD[0, -1])) / 20
+        Q = (c0[None, :] + rng.normal(0, sd, (300, 3))).astype(np.float32)
+        log.append(("knn", srv.submit(cl, torch.from_numpy(Q).cuda(), 16), Q, len(masks) - 1))
+        dead = ri[0]
+        nxt = live.copy()
+        nxt[dead] = 0
+        masks.append(nxt)
+        log.append(("del", srv.delete(cl, dead), None, None))
+        log.append(("knn", srv.submit(cl, torch.from_numpy(Q).cuda(), 16), Q, len(masks) - 1))
+    res = {t: srv.wait(t, with_seen=True) for _, t, *_ in log}
+    srv.close()
+    ex = 0
+    for kind, t, Q, before in log:
+        if kind != "knn":
+            continue
+        _, _, (_, idx, dist, *_), seen = res[t]
+        assert seen == before
+        ri, _, rD = oracle.knn_bruteforce(P, Q, 16, live=masks[seen])
+        ex += compare_rows(idx.cpu().numpy(), dist.cpu().numpy(), ri, rD, P=P, Q=Q,
+                           live=masks[seen])
+    assert ex <= 2
+    assert cl.live_count == int(masks[-1].sum())
+
+
+def test_lazy_delete_errors(env):
+    torch, oracle, A, W = env
+    from paper_2605_02224_amd._lib import MknnError, ENOTFOUND, EINVAL
+    for kw in ({"plain": True}, {"bind_at_admission": True}):
+        with pytest.raises(MknnError) as e:
+            A.Server(pool_queries=1000, lazy_delete=True, **kw)
+        assert e.value.status == EINVAL
+    (P, cl), = _clouds(env, 1, seed=97, nmax=3000)
+    n = P.shape[0]
+    srv = A.Server(pool_queries=1 << 14, nstreams=2, max_wave_requests=4, lazy_delete=True)
+    bad = [srv.delete(cl, [n]), srv.delete(cl, [3, 3]), srv.delete(cl, np.arange(n))]
+    good = srv.delete(cl, [5])
+    again = srv.delete(cl, [5])                   # already deleted (marked) before it
+    q = torch.from_numpy(P[:8]).cuda()
+    t = srv.submit(cl, q, 2)
+    for b, st in zip(bad, (ENOTFOUND, ENOTFOUND, EINVAL)):
+        with pytest.raises(MknnError) as e:
+            srv.wait(b)
+        assert e.value.status == st
+    srv.wait(good)
+    with pytest.raises(MknnError) as e:
+        srv.wait(again)
+    assert e.value.status == ENOTFOUND
+    _, _, (_, idx, dist, *_), seen = srv.wait(t, with_seen=True)
+    assert seen == 1                              # the one good deletion
+    idx = idx.cpu().numpy()
+    assert idx[:, 0].tolist() == [0, 1, 2, 3, 4, int(idx[5, 0]), 6, 7]
+    assert idx[5, 0] != 5
+    srv.close()
+    # a cloud with deletions pending from the plain call cannot be served lazily
+    cl.delete_lazy([7])
+    srv = A.Server(pool_queries=1 << 14, nstreams=2, max_wave_requests=4, lazy_delete=True)
+    with pytest.raises(MknnError) as e:
+        srv.submit(cl, q, 2)
+    assert e.value.status == EINVAL
+    srv.close()
+    cl.flush()
