@@ -539,9 +539,9 @@ def run_serving(args) -> dict:
     nq_of = np.diff(qoff)
     pool = 1 << 22
 
-    def server(plain, bind=True, max_wave=256):
+    def server(plain, bind=True, max_wave=256, lazy=False):
         return A.Server(pool_queries=pool, nstreams=args.slots, max_wave_requests=max_wave,
-                        plain=plain, bind_at_admission=bind)
+                        plain=plain, bind_at_admission=bind, lazy_delete=lazy)
 
     # saturation: the first nsat requests as fast as the ring allows, no deletions
     sat = {}
@@ -557,20 +557,21 @@ def run_serving(args) -> dict:
             f"({nsat / span:.0f} requests/s, {r_ / max(w_, 1):.2f} requests per wave)")
 
     # deletion plans over disjoint rank sets: delete_frac per main run (ten parts each), a
-    # tenth of it per sweep run -- the sweep's 16 runs then stay within the arena slack
-    # (about 2% of the points) left after one re-pack, so no run re-packs a cloud
-    nsweep_runs = 4 * len(loads)
+    # tenth of it per sweep run; the lists are re-packed before each load of the sweep, so
+    # its five runs stay well within the arena slack and no run re-packs a cloud
+    nsweep_runs = 5 * len(loads)
     tenth = w.deletion_plan(frac=args.delete_frac / 10, batch=1000, parts=20 + nsweep_runs)
     main_plans = [_merge_plans(tenth[0:10]), _merge_plans(tenth[10:20])]
     rng = np.random.default_rng(11)
 
-    def open_loop(name, lo, hi, warm, load, plan, plain, bind=True, max_wave=256, capture=()):
+    def open_loop(name, lo, hi, warm, load, plan, plain, bind=True, max_wave=256, capture=(),
+                  lazy=False):
         mean_nq = float(nq_of[lo:hi].mean())
         rate = load * sat["plain"] / mean_nq
         arrivals = np.cumsum(rng.exponential(1.0 / rate, hi - lo))
         pos = np.sort(rng.integers(lo + warm, hi, len(plan)))
         dels = [(int(pos[t]), ci, r) for t, (ci, r) in enumerate(plan)]
-        srv = server(plain, bind, max_wave)
+        srv = server(plain, bind, max_wave, lazy)
         t0 = time.perf_counter()
         lat, t_done, t_first = run.run(srv, lo, hi, arrivals=arrivals, deletions=dels,
                                        clouds=clouds, label=name, capture=capture)
@@ -645,25 +646,26 @@ def run_serving(args) -> dict:
     for _, ci, r in batched_dels:
         live[ci][r] = False
 
-    # sweep of offered loads: plain, batched (bind at admission / strict order) and batched
-    # without coalescing (one request per wave, the same two stream slots)
+    # sweep of offered loads: plain, batched (bind at admission; strict order waiting for
+    # deletions; strict order filtering marked deletions) and batched without coalescing
+    # (one request per wave, the same two stream slots)
     sweep = []
     lo2, hi2 = hi, hi + nsw_warm + nsw
     k = 20
-    t0 = time.perf_counter()
-    for cl in clouds:
-        cl.compact()
-    torch.cuda.synchronize()
-    if loads:
-        log(f"serving: lists re-packed for the sweep in {time.perf_counter() - t0:.1f} s")
     for load in loads:
+        t0 = time.perf_counter()
+        for cl in clouds:
+            cl.compact()
+        torch.cuda.synchronize()
+        log(f"serving: lists re-packed for the sweep in {time.perf_counter() - t0:.1f} s")
         row = {"load": load}
-        for name, plain, bind, mw in (("plain", True, True, 256),
-                                      ("batched_bind", False, True, 256),
-                                      ("batched_strict", False, False, 256),
-                                      ("batched_one_per_wave", False, True, 1)):
+        for name, plain, bind, mw, lazy in (("plain", True, True, 256, False),
+                                            ("batched_bind", False, True, 256, False),
+                                            ("batched_strict", False, False, 256, False),
+                                            ("batched_strict_lazy", False, False, 256, True),
+                                            ("batched_one_per_wave", False, True, 1, False)):
             out, dels = open_loop(f"sweep {load}x {name}", lo2, hi2, nsw_warm, load,
-                                  tenth[k], plain, bind, mw)
+                                  tenth[k], plain, bind, mw, lazy=lazy)
             k += 1
             row[name] = {x: out[x] for x in ("p50_ms", "p99_ms", "served_qps",
                                              "requests_per_wave", "mean_queue_wait_ms")}
