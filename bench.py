@@ -45,6 +45,10 @@ def log(msg: str) -> None:
     print(f"[bench {time.perf_counter() - _T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
+# the query kernel of the headline workload: one slot per lane (k <= 16), k == 16 exactly,
+# descent steps first, one k and m per launch, no pending-deletion filter
+HEADLINE_KERNEL = "knn_rows_kernel<1, true, true, true, false>"
+
 # the translation unit of the plain query path and the headers its kernels are built from
 KERNEL_SOURCES = ("mknn_device.hip", "knn_kernels.h", "knn_group.h", "knn_rows.h",
                   "device_common.h", "planefit.h")
@@ -76,32 +80,34 @@ def measured_traffic(k: int):
     return rec.get("traffic_bytes_per_dispatch")
 
 
-def ingest_counters(fetch_dir: str, write_dir: str, out_path: str) -> dict:
+def ingest_counters(fetch_dir: str, write_dir: str, out_path: str, last: int) -> dict:
     """Write the HBM byte reading of the headline query kernel from two rocprofv3 --pmc runs
     of this benchmark with --copy-probe (FETCH_SIZE in one, WRITE_SIZE in the other):
-    KiB per dispatch of the kernel, each scaled by what the same counter reads for the
-    copy probe (an elementwise pass reading and writing 1 GiB), stamped with the hash of
-    the kernel sources the counters were taken from."""
+    KiB per dispatch over the last `last` dispatches of the kernel (the timed steps; the
+    autotuner's and the warm-up's launches come before them), each scaled by what the same
+    counter reads for the copy probe (an elementwise pass reading and writing 1 GiB),
+    stamped with the hash of the kernel sources the counters were taken from."""
     import csv
     import glob
-    kname = "knn_rows_kernel<1, true, true, true>"
+    kname = HEADLINE_KERNEL
     probe = "elementwise_kernel"
     rec = {"kernel": "mknn::" + kname, "workload": "torus 1M points, 1M volume queries, k=16, m=n",
            "csrc_sha256": csrc_digest()}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         kern, copy = [], []
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-            for row in csv.DictReader(open(f)):
+            for i, row in enumerate(csv.DictReader(open(f))):
                 if row.get("Counter_Name") != counter:
                     continue
                 name = row.get("Kernel_Name", "")
                 if kname in name:
-                    kern.append(float(row["Counter_Value"]))
+                    kern.append((int(row.get("Dispatch_Id") or 0), i, float(row["Counter_Value"])))
                 elif probe in name:
                     copy.append(float(row["Counter_Value"]))
         if not kern or not copy:
             raise RuntimeError(f"{counter}: no dispatch of the query kernel or the copy probe "
                                f"under {d}")
+        kern = [v for _, _, v in sorted(kern)][-last:]
         key = "fetch" if counter == "FETCH_SIZE" else "write"
         rec[f"{key}_kib_per_dispatch"] = round(sum(kern) / len(kern), 1)
         rec[f"{key}_dispatches"] = len(kern)
@@ -117,26 +123,30 @@ def ingest_counters(fetch_dir: str, write_dir: str, out_path: str) -> dict:
     return rec
 
 
-def trace_summary(trace_dir: str) -> dict:
+def trace_summary(trace_dir: str, last: int) -> dict:
     """Durations of the headline query kernel in rocprofv3 kernel-trace CSVs of this
-    benchmark (one file per process): every dispatch of knn_rows_kernel<1, true, true, true>
-    over the 1M-query grid, in launch order, and their mean."""
+    benchmark (one file per process): the dispatches of the headline kernel
+    over the 1M-query grid in launch order, and the mean of the last `last` of them (the
+    timed steps of a run with --no-extras)."""
     import csv
     import glob
     out = {}
-    for f in sorted(glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))):
+    for f in sorted(glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)):
         durs = []
         for r in csv.DictReader(open(f)):
-            if "knn_rows_kernel<1, true, true, true>" not in r.get("Kernel_Name", ""):
+            if HEADLINE_KERNEL not in r.get("Kernel_Name", ""):
                 continue
             grid = int(r.get("Grid_Size") or r.get("Grid_Size_X") or 0)
-            durs.append((grid, (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6))
-        if durs:
-            big = [d for g, d in durs if g >= 16_000_000]
+            durs.append((int(r["Start_Timestamp"]), grid,
+                         (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6))
+        big = [d for _, g, d in sorted(durs) if g >= 16_000_000]
+        if big:
+            tail = big[-last:]
             out[os.path.basename(f)] = {
                 "dispatches": len(durs), "headline_grid_dispatches": len(big),
-                "headline_grid_mean_ms": round(sum(big) / len(big), 4) if big else None,
-                "headline_grid_ms": [round(d, 4) for d in big]}
+                "timed_dispatches": len(tail),
+                "timed_mean_ms": round(sum(tail) / len(tail), 4),
+                "timed_ms": [round(d, 4) for d in tail]}
     return out
 
 
@@ -884,10 +894,10 @@ def main() -> int:
                     help="durations of the headline kernel in a rocprofv3 kernel trace")
     args = ap.parse_args()
     if args.ingest_counters:
-        print(json.dumps(ingest_counters(*args.ingest_counters)))
+        print(json.dumps(ingest_counters(*args.ingest_counters, last=args.steps)))
         return 0
     if args.trace_summary:
-        print(json.dumps(trace_summary(args.trace_summary), indent=1))
+        print(json.dumps(trace_summary(args.trace_summary, last=args.steps), indent=1))
         return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU: the query path has no "
@@ -996,7 +1006,7 @@ def _main(args, child) -> int:
     extras = {"build_s": round(build_s, 2), "device_bytes": cl.device_bytes,
               "entries_per_query": round(E, 2), "lists_per_query": round(L, 3),
               "inserts_per_query": round(INS, 2), "algorithmic_bytes_per_query": round(bytes_per_q, 1),
-              "kernel": f"mknn::knn_rows_kernel<1, true, true, true> (k={k})" if k == 16 else None,
+              "kernel": f"mknn::{HEADLINE_KERNEL} (k={k})" if k == 16 else None,
               "kernel_ms": round(kern_ms, 4), "autotuned": tuned,
               "roofline_frac_step_basis": round(qps * bytes_per_q / (HBM_PEAK_GBS * 1e9), 4),
               "hbm_measured_GBps": (round(traffic / (kern_ms * 1e-3) / 1e9, 1)
