@@ -71,6 +71,31 @@ typedef enum {
  */
 mknn_status mknn_build(const float *xyz, int64_t n, const int32_t *order, mknn_cloud **out);
 
+/* mknn_build_device: the lists of mknn_build (Sec. 3), computed on the GPU; the result is
+ * the same cloud, list for list and entry for entry, as mknn_build's.  Every tetrahedron the
+ * incremental construction creates is generated from pairs of tetrahedra sharing a
+ * triangle, in rounds (a tetrahedron exists from its newest vertex's insertion until the
+ * oldest site in its circumsphere), with the construction's own predicates: the device
+ * certifies a sign with a float64 error bound and defers the rest to exact host arithmetic.
+ *   xyz, order, out  as for mknn_build (host memory; copied).
+ *   stream   hipStream_t as void* (NULL: the legacy default stream) for the device work;
+ *            the call synchronises it and returns when the lists are on the host.
+ * Device memory: about 150 bytes per point for the created tetrahedra, their ridge table
+ * and the sorted entries, plus 4 bytes per conflict record (a few hundred per point);
+ * freed before the call returns.  Clouds of fewer than five points, and clouds whose first
+ * four ranks are coplanar, are built by mknn_build (same lists, same errors).
+ * Errors: as mknn_build; EUNSUPPORTED for n above 2^21 - 2 (ridge keys pack three 21-bit
+ * site ids); EHIP when a HIP call fails (device memory included); EDUPLICATE names the
+ * first rank that repeats an older point, as mknn_build does. */
+mknn_status mknn_build_device(const float *xyz, int64_t n, const int32_t *order, void *stream,
+                              mknn_cloud **out);
+
+/* Counters of the calling thread's last mknn_build_device: counts[0] rounds, [1]
+ * tetrahedra created (ghosts included), [2] conflict records written, [3] candidate tests,
+ * [4] tests decided exactly on the host, [5] list entries; *ms (may be NULL) the call's
+ * wall time in milliseconds.  Errors: EINVAL (counts NULL). */
+mknn_status mknn_build_device_stats(int64_t counts[6], double *ms);
+
 /* Number of points n of the cloud (including deleted ranks). */
 int64_t mknn_size(const mknn_cloud *c);
 

@@ -21,6 +21,8 @@ _I64 = ctypes.c_int64
 _PP = ctypes.POINTER(ctypes.c_void_p)
 SIGNATURES = {
     "mknn_build": (ctypes.c_int, [_P, _I64, _P, _PP]),
+    "mknn_build_device": (ctypes.c_int, [_P, _I64, _P, _P, _PP]),
+    "mknn_build_device_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
     "mknn_size": (_I64, [_P]),
     "mknn_successors": (ctypes.c_int, [_P, _PP, _PP, ctypes.POINTER(_I64)]),
     "mknn_points_by_rank": (ctypes.c_int, [_P, _PP]),

@@ -31,14 +31,21 @@ class Cloud:
         self._h = handle
 
     @classmethod
-    def build(cls, points: np.ndarray, order: Optional[np.ndarray] = None) -> "Cloud":
-        """points: float32 [n,3] in caller order; order[r] = caller index of rank r."""
+    def build(cls, points: np.ndarray, order: Optional[np.ndarray] = None,
+              device: bool = False, stream=None) -> "Cloud":
+        """points: float32 [n,3] in caller order; order[r] = caller index of rank r.
+        device=True builds the same lists on the GPU (mknn_build_device) on `stream`
+        (a torch.cuda.Stream, default: torch's current stream)."""
         pts = np.ascontiguousarray(points, dtype=np.float32).reshape(-1, 3)
         o = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
         if o is not None and o.shape[0] != pts.shape[0]:
             raise ValueError("order must have one entry per point")
         h = ctypes.c_void_p()
-        check(_lib.lib().mknn_build(_ptr(pts), pts.shape[0], _ptr(o), ctypes.byref(h)))
+        if device:
+            check(_lib.lib().mknn_build_device(_ptr(pts), pts.shape[0], _ptr(o),
+                                               _stream(stream), ctypes.byref(h)))
+        else:
+            check(_lib.lib().mknn_build(_ptr(pts), pts.shape[0], _ptr(o), ctypes.byref(h)))
         return cls(h)
 
     def __del__(self):
@@ -378,3 +385,12 @@ class Server:
 
     def __del__(self):
         self.close()
+
+
+def build_device_stats() -> dict:
+    """Counters of this thread's last Cloud.build(device=True)."""
+    c = (ctypes.c_int64 * 6)()
+    ms = ctypes.c_double()
+    check(_lib.lib().mknn_build_device_stats(c, ctypes.byref(ms)))
+    return {"rounds": c[0], "tets": c[1], "conflicts": c[2], "tests": c[3], "deferred": c[4],
+            "entries": c[5], "ms": ms.value}

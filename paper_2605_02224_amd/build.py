@@ -16,7 +16,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["mknn_host.cpp", "delaunay.cpp", "deletion.cpp", "insertion.cpp"]
-HIP_SOURCES = ["mknn_device.hip", "mknn_batch.hip", "mknn_server.hip", "mknn_probe.hip"]
+HIP_SOURCES = ["mknn_device.hip", "mknn_batch.hip", "mknn_server.hip", "mknn_probe.hip",
+               "mknn_build_gpu.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I" + INCLUDE, "-I" + CSRC]
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",

@@ -1,0 +1,124 @@
+"""Successor lists built on the GPU (mknn_build_device) against the host construction
+(mknn_build): the same lists, entry for entry (Sec. 3: the lists are a function of the
+point sequence, not of how the construction is scheduled).  The host construction is
+itself pinned against the oracle's exact lists (tests/test_host_build.py)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_02224_amd import api as A
+    from paper_2605_02224_amd import workloads as W
+    from paper_2605_02224_amd import _lib
+    return torch, A, W, _lib
+
+
+def _same_lists(A, pts, order=None):
+    print(f"device build: n={pts.shape[0]}", flush=True)
+    host = A.Cloud.build(pts, order)
+    dev = A.Cloud.build(pts, order, device=True)
+    st = A.build_device_stats()
+    ho, he = host.successors()
+    do, de = dev.successors()
+    assert np.array_equal(ho, do), "list offsets differ"
+    assert np.array_equal(he, de), "list entries differ"
+    assert np.array_equal(host.points_by_rank(), dev.points_by_rank())
+    return st, dev
+
+
+@pytest.mark.parametrize("n,shape,seed", [(5, "sphere", 1), (64, "sphere", 2),
+                                          (20_000, "sphere", 0), (50_000, "torus", 3),
+                                          (100_000, "ellipsoid", 4)])
+def test_device_lists_equal_host(env, n, shape, seed):
+    torch, A, W, _ = env
+    c = W.random_cloud(n, seed, shape)
+    st, _ = _same_lists(A, c.points, c.order)
+    if n >= 5 and st["rounds"]:
+        assert st["entries"] == int(A.Cloud.build(c.points, c.order).successors()[0][-1])
+
+
+def test_device_lists_lattice(env):
+    """Integer lattice in random order: exact cospherical and coplanar sites everywhere, so
+    many signs are decided on the host; the lists must still be the same."""
+    torch, A, W, _ = env
+    c = W.lattice_cloud(18, seed=5)
+    st, _ = _same_lists(A, c.points, c.order)
+    assert st["deferred"] > 0
+
+
+def test_device_lists_planar_bulk(env):
+    """Mostly coplanar cloud (a flat grid patch with a few sites off the plane first): hull
+    facets in the plane take the in-plane circumcircle rule."""
+    torch, A, W, _ = env
+    rng = np.random.default_rng(7)
+    g = np.arange(40, dtype=np.float32)
+    grid = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    flat = np.concatenate([grid, np.zeros((grid.shape[0], 1), np.float32)], 1)
+    off = np.array([[3.5, 7.25, 5.0], [20.0, 1.0, -4.0], [31.0, 30.5, 6.0], [9.0, 33.0, -2.5]],
+                   np.float32)
+    pts = np.concatenate([off, flat[rng.permutation(flat.shape[0])]], 0)
+    st, _ = _same_lists(A, pts)
+    assert st["deferred"] > 0
+
+
+def test_device_lists_heightfield(env):
+    torch, A, W, _ = env
+    w = W.heightfield_prefix(n=200_000, nq=10)
+    _same_lists(A, w.cloud.points, w.cloud.order)
+
+
+def test_device_lists_torus_1m(env):
+    """The headline cloud (1M torus points, seeded random order)."""
+    torch, A, W, _ = env
+    w = W.torus_paper_scale(n=1_000_000, nq=10)
+    st, dev = _same_lists(A, w.cloud.points, w.cloud.order)
+    print(f"device build of 1M torus: {st}", flush=True)
+
+
+def test_device_build_coplanar_start(env):
+    """First four ranks coplanar: the device call takes the host construction."""
+    torch, A, W, _ = env
+    c = W.random_cloud(3000, 9, "sphere")
+    pts = c.by_rank.copy()
+    pts[3] = pts[0] + 0.5 * (pts[1] - pts[0]) + 0.25 * (pts[2] - pts[0])
+    pts[3] = pts[0] + np.float32(0.5) * (pts[1] - pts[0])   # on the line of ranks 0 and 1
+    _same_lists(A, pts)
+
+
+@pytest.mark.parametrize("where", ["late", "start"])
+def test_device_build_duplicate(env, where):
+    torch, A, W, _lib = env
+    c = W.random_cloud(20_000, 11, "torus")
+    pts = c.by_rank.copy()
+    if where == "late":
+        pts[15_000] = pts[9_000]
+        pts[17_000] = pts[2_000]
+    else:
+        pts[12_000] = pts[2]
+    msgs = []
+    for dev in (False, True):
+        with pytest.raises(RuntimeError) as e:
+            A.Cloud.build(pts, device=dev)
+        msgs.append(str(e.value))
+    assert "EDUPLICATE" in msgs[1]
+    first = 15_000 if where == "late" else 12_000
+    assert f"point {first} " in msgs[0] and f"point {first} " in msgs[1]
+
+
+def test_device_built_cloud_answers_queries(env):
+    """A device-built cloud uploads and answers queries like a host-built one."""
+    torch, A, W, _ = env
+    w = W.sphere_small(n=10_000, nq=4_000, k=8)
+    ch = A.Cloud.build(w.cloud.points, w.cloud.order).upload()
+    cd = A.Cloud.build(w.cloud.points, w.cloud.order, device=True).upload()
+    q = torch.from_numpy(w.queries).cuda()
+    ih, dh = ch.knn(q, 8)
+    idv, dd = cd.knn(q, 8)
+    torch.cuda.synchronize()
+    assert torch.equal(ih, idv) and torch.equal(dh, dd)
