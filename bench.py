@@ -240,12 +240,10 @@ def memory_probes() -> dict:
 
 
 def build_clouds(clouds, threads: int = 16):
-    """Build and upload many clouds; host construction runs on a thread pool (the C call
-    releases the GIL)."""
-    import concurrent.futures as cf
+    """Build and upload many clouds: the lists are built on the GPU one cloud after the
+    other (the same lists as the host construction, which the GPU tests check)."""
     from paper_2605_02224_amd.api import Cloud
-    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-        built = list(ex.map(lambda c: Cloud.build(c.by_rank), clouds))
+    built = [Cloud.build(c.by_rank, device=True) for c in clouds]
     for c in built:
         c.upload()
     return built
@@ -944,10 +942,24 @@ def _main(args, child) -> int:
     w = W.torus_paper_scale(n=args.n, nq=args.nq, k=args.k)
     P = w.cloud.by_rank
     log(f"workload generated in {time.perf_counter() - t0:.1f} s")
+    # the lists, built on the GPU (timed), and by the host construction for comparison
+    from paper_2605_02224_amd import api as A
+    Cloud.build(P[:1000], device=True)   # first use of the device path (code objects load)
     t0 = time.perf_counter()
-    cl = Cloud.build(P)
+    cl = Cloud.build(P, device=True)
+    build_dev_s = time.perf_counter() - t0
+    build_stats = A.build_device_stats()
+    t0 = time.perf_counter()
+    cl_host = Cloud.build(P)
     build_s = time.perf_counter() - t0
-    log(f"lists built in {build_s:.1f} s")
+    ho, he = cl_host.successors()
+    do, de = cl.successors()
+    lists_equal = bool(np.array_equal(ho, do) and np.array_equal(he, de))
+    del cl_host, ho, he, do, de
+    log(f"lists built on the GPU in {build_dev_s:.2f} s ({build_stats}), on the host in "
+        f"{build_s:.1f} s; equal: {lists_equal}")
+    if not lists_equal:
+        raise RuntimeError("device-built lists differ from the host construction's")
     cl.upload()
     q = torch.from_numpy(w.queries).cuda()
     qb = torch.from_numpy(w.queries_b).cuda()
@@ -1003,7 +1015,10 @@ def _main(args, child) -> int:
 
     # context numbers (not the headline): k=1 and the on-surface query set
     traffic = measured_traffic(k)
-    extras = {"build_s": round(build_s, 2), "device_bytes": cl.device_bytes,
+    extras = {"build_s": round(build_s, 2), "build_device_s": round(build_dev_s, 3),
+              "build_device": {k: (round(v, 1) if isinstance(v, float) else v)
+                               for k, v in build_stats.items()},
+              "build_lists_equal": lists_equal, "device_bytes": cl.device_bytes,
               "entries_per_query": round(E, 2), "lists_per_query": round(L, 3),
               "inserts_per_query": round(INS, 2), "algorithmic_bytes_per_query": round(bytes_per_q, 1),
               "kernel": f"mknn::{HEADLINE_KERNEL} (k={k})" if k == 16 else None,

@@ -79,6 +79,8 @@ struct Deferred {      // a candidate test whose sign the device could not certi
   int32_t q;
   int32_t from_td;
   int64_t idx;         // candidate index
+  int32_t tnew;        // the new tetrahedron's id (its min conflict takes q if accepted)
+  int32_t pad;
 };
 
 __device__ __forceinline__ double3 site(const float4 *P, int32_t v) {
@@ -252,18 +254,19 @@ __global__ void make_kernel(const Item *__restrict__ items, int64_t w,
 // One thread per candidate test: finds its job (the last job starting at or before it),
 // takes the candidate from td's list, then ts's, and writes 1 (in the new conflict list),
 // 0, or 2 (deferred to the host).  A candidate at the creating site's own coordinates is a
-// duplicate point.
-__global__ void test_kernel(const Job *__restrict__ jobs, const uint64_t *__restrict__ jobstart,
-                            int64_t njobs, uint64_t c0, uint64_t ncand,
-                            const int4 *__restrict__ tv,
-                            const int64_t *__restrict__ coff, const int32_t *__restrict__ pool,
-                            const float4 *__restrict__ P, uint8_t *__restrict__ flag,
-                            int32_t *__restrict__ candq, Deferred *__restrict__ deferred,
-                            uint32_t *__restrict__ ndeferred, uint32_t max_deferred,
-                            int32_t *__restrict__ dup) {
+// duplicate point.  The accepted candidates' smallest site per job is reduced in LDS (a
+// block spans at most 256 jobs) and then joins the job's min conflict with one atomic.
+__global__ __launch_bounds__(256) void test_kernel(
+    const Job *__restrict__ jobs, const uint64_t *__restrict__ jobstart, int64_t njobs,
+    uint64_t c0, uint64_t ncand, const int4 *__restrict__ tv, const int64_t *__restrict__ coff,
+    const int32_t *__restrict__ pool, const float4 *__restrict__ P, uint8_t *__restrict__ flag,
+    int32_t *__restrict__ candq, int32_t *__restrict__ minc, Deferred *__restrict__ deferred,
+    uint32_t *__restrict__ ndeferred, uint32_t max_deferred, int32_t *__restrict__ dup) {
   const uint64_t idx = c0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // the jobs this block covers: [jlo, jhi], found once by the first lane
+  // the jobs this block covers: [s_lo, s_hi], found once by the first lane
   __shared__ int64_t s_lo, s_hi;
+  __shared__ int32_t s_min[256];
+  s_min[threadIdx.x] = kNone;
   if (threadIdx.x == 0) {
     const uint64_t first = c0 + (uint64_t)blockIdx.x * blockDim.x;
     const uint64_t last = min(first + blockDim.x, ncand) - 1;
@@ -281,71 +284,72 @@ __global__ void test_kernel(const Job *__restrict__ jobs, const uint64_t *__rest
     s_hi = lo2;
   }
   __syncthreads();
-  if (idx >= ncand) return;
-  int64_t lo = s_lo, hi = s_hi;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (jobstart[mid] <= idx) lo = mid; else hi = mid - 1;
-  }
-  const Job j = jobs[lo];
-  const int64_t e = (int64_t)(idx - jobstart[lo]);
-  const bool from_td = e < j.nd;
-  const int32_t q = from_td ? pool[coff[j.td] + e] : pool[coff[j.ts] + (e - j.nd)];
-  candq[idx] = q;
-  if (q == j.p) {
-    flag[idx] = 0;
-    return;
-  }
-  const double3 xq = site(P, q);
-  int c = conflict_filter(P, tv[j.tnew], xq);
-  if (c == 1 && !from_td) {
-    const int c2 = conflict_filter(P, tv[j.td], xq);   // already in td's list?
-    c = c2 == 0 ? 1 : (c2 == 1 ? 0 : 2);
-  }
-  if (c == 2) {
-    if (j.p >= 0) {
-      const float4 a = P[q], b = P[j.p];
-      if (a.x == b.x && a.y == b.y && a.z == b.z) atomicMin(dup, q);
+  if (idx < ncand) {
+    int64_t lo = s_lo, hi = s_hi;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (jobstart[mid] <= idx) lo = mid; else hi = mid - 1;
     }
-    const uint32_t s = atomicAdd(ndeferred, 1u);
-    if (s < max_deferred) {
-      Deferred d;
-      const int4 v = tv[j.tnew], vd = tv[j.td];
-      d.v[0] = v.x; d.v[1] = v.y; d.v[2] = v.z; d.v[3] = v.w;
-      d.vd[0] = vd.x; d.vd[1] = vd.y; d.vd[2] = vd.z; d.vd[3] = vd.w;
-      d.q = q;
-      d.from_td = from_td ? 1 : 0;
-      d.idx = (int64_t)idx;
-      deferred[s] = d;
+    const Job j = jobs[lo];
+    const int64_t e = (int64_t)(idx - jobstart[lo]);
+    const bool from_td = e < j.nd;
+    const int32_t q = from_td ? pool[coff[j.td] + e] : pool[coff[j.ts] + (e - j.nd)];
+    candq[idx] = q;
+    int c = 0;
+    if (q != j.p) {
+      const double3 xq = site(P, q);
+      c = conflict_filter(P, tv[j.tnew], xq);
+      if (c == 1 && !from_td) {
+        const int c2 = conflict_filter(P, tv[j.td], xq);   // already in td's list?
+        c = c2 == 0 ? 1 : (c2 == 1 ? 0 : 2);
+      }
+      if (c == 2) {
+        if (j.p >= 0) {
+          const float4 a = P[q], b = P[j.p];
+          if (a.x == b.x && a.y == b.y && a.z == b.z) atomicMin(dup, q);
+        }
+        const uint32_t s = atomicAdd(ndeferred, 1u);
+        if (s < max_deferred) {
+          Deferred d;
+          const int4 v = tv[j.tnew], vd = tv[j.td];
+          d.v[0] = v.x; d.v[1] = v.y; d.v[2] = v.z; d.v[3] = v.w;
+          d.vd[0] = vd.x; d.vd[1] = vd.y; d.vd[2] = vd.z; d.vd[3] = vd.w;
+          d.q = q;
+          d.from_td = from_td ? 1 : 0;
+          d.idx = (int64_t)idx;
+          d.tnew = j.tnew;
+          d.pad = 0;
+          deferred[s] = d;
+        }
+      }
+      if (c == 1) atomicMin(&s_min[lo - s_lo], q);
     }
+    flag[idx] = (uint8_t)c;
   }
-  flag[idx] = (uint8_t)c;
+  __syncthreads();
+  const int64_t nj = s_hi - s_lo + 1;
+  if ((int64_t)threadIdx.x < nj && s_min[threadIdx.x] != kNone)
+    atomicMin(&minc[jobs[s_lo + threadIdx.x].tnew], s_min[threadIdx.x]);
 }
 
+// Deferred signs decided on the host: the verdict goes to the flag, and an accepted
+// candidate joins its tetrahedron's min conflict.
 __global__ void settle_kernel(const Deferred *__restrict__ deferred,
                               const uint8_t *__restrict__ verdict, uint32_t n,
-                              uint8_t *__restrict__ flag) {
+                              uint8_t *__restrict__ flag, int32_t *__restrict__ minc) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flag[deferred[i].idx] = verdict[i];
+  if (i >= n) return;
+  const Deferred d = deferred[i];
+  flag[d.idx] = verdict[i];
+  if (verdict[i]) atomicMin(&minc[d.tnew], d.q);
 }
 
-// Accepted candidates go to their packed place in the pool; the new list's smallest site
-// becomes the tetrahedron's min conflict (one atomic per run of lanes of one job).
+// Accepted candidates go to their packed place in the pool.
 __global__ void write_kernel(const uint8_t *__restrict__ flag, const uint64_t *__restrict__ pos,
                              const int32_t *__restrict__ candq, uint64_t ncand,
-                             const Job *__restrict__ jobs, const uint64_t *__restrict__ jobstart,
-                             int64_t njobs, int64_t pool_base, int32_t *__restrict__ pool,
-                             int32_t *__restrict__ minc) {
+                             int64_t pool_base, int32_t *__restrict__ pool) {
   const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= ncand || !flag[idx]) return;
-  const int32_t q = candq[idx];
-  pool[pool_base + (int64_t)pos[idx]] = q;
-  int64_t lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (jobstart[mid] <= idx) lo = mid; else hi = mid - 1;
-  }
-  atomicMin(&minc[jobs[lo].tnew], q);
+  if (idx < ncand && flag[idx]) pool[pool_base + (int64_t)pos[idx]] = candq[idx];
 }
 
 // Each job's packed list range; then its ridge pairs for the next round: (tnew, ts) on the
@@ -628,7 +632,7 @@ static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStrea
       GB_CHECK(hipMemsetAsync(ndeferred.p, 0, sizeof(uint32_t), st));
       test_kernel<<<blocks((int64_t)len), 256, 0, st>>>(
           jobs.p, jobstart.p, njobs, c0, c0 + len, tv.p, coff.p, pool.p, dP.p, flag.p, candq.p,
-          deferred.p, ndeferred.p, max_deferred, dup.p);
+          minc.p, deferred.p, ndeferred.p, max_deferred, dup.p);
       uint32_t nd = 0;
       int32_t hdup = 0;
       GB_CHECK(hipMemcpyAsync(&nd, ndeferred.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -655,7 +659,7 @@ static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStrea
           hver[i] = c ? 1 : 0;
         }
         GB_CHECK(hipMemcpyAsync(verdict.p, hver.data(), nd, hipMemcpyHostToDevice, st));
-        settle_kernel<<<blocks(nd), 256, 0, st>>>(deferred.p, verdict.p, nd, flag.p);
+        settle_kernel<<<blocks(nd), 256, 0, st>>>(deferred.p, verdict.p, nd, flag.p, minc.p);
       }
       c0 += len;
     }
@@ -678,9 +682,8 @@ static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStrea
     }
     pool.reserve(pool_used + (int64_t)nacc + 1, st, true, pool_used);
     if (ncand > 0)
-      write_kernel<<<blocks((int64_t)ncand), 256, 0, st>>>(flag.p, pos.p, candq.p, ncand, jobs.p,
-                                                           jobstart.p, njobs, pool_used, pool.p,
-                                                           minc.p);
+      write_kernel<<<blocks((int64_t)ncand), 256, 0, st>>>(flag.p, pos.p, candq.p, ncand,
+                                                           pool_used, pool.p);
     GB_CHECK(hipMemsetAsync(nnext.p, 0, sizeof(uint32_t), st));
     finish_kernel<<<blocks(njobs), 256, 0, st>>>(jobs.p, jobstart.p, njobs, pos.p, ncand, nacc,
                                                  pool_used, tv.p, coff.p, clen.p, hkey.p, hval.p,
