@@ -5,10 +5,11 @@
 // 256-byte load, all its distances are computed in parallel, and the descent's "first entry
 // closer than the current site" (Alg. 1) is the lowest set bit of a ballot -- one memory
 // round trip per list instead of one per entry, and no divergence between entries of a
-// list.  The candidate list N (Alg. 2) is spread across the row: lane l holds slots
-// l, 16 + l, 32 + l, 48 + l (S slots per lane, k <= 16 S).  Inserting a candidate is a
-// row-wide compare, a population count for its position and a one-slot shift through the
-// row done with DPP row moves; only candidates that beat the current k-th key are inserted.
+// list.  The candidate list N (Alg. 2) is spread across the row: lane l holds positions
+// S l .. S l + S - 1 (S slots per lane, k <= 16 S).  Inserting a candidate is a row-wide
+// compare, a population count for its position and a one-position shift: inside each lane,
+// plus one DPP row move of the lane's last slot into the next lane; only candidates that
+// beat the current k-th key are inserted.
 //
 // Descent and seeding (Alg. 1): when a chunk of L_cur holds an entry closer than the current
 // site, only that transition site is offered to N and the walk jumps; a chunk without such
@@ -118,6 +119,16 @@ __device__ __forceinline__ bool in_row(int32_t v, int32_t x, std::integer_sequen
   return ((v == row_ror<T>(x)) | ...);
 }
 
+// Lanes of one wavefront exchanging values through LDS.  The hardware completes a
+// wavefront's LDS operations in program order, but the compiler must be told that other
+// lanes write the memory between two phases: otherwise it may forward a lane's own earlier
+// store to a later load of the same address.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int S, bool EXACTK>
 struct RowTopK {
   double d[S];
@@ -145,9 +156,9 @@ struct RowTopK {
     }
   }
 
-  // slot j (row-uniform) broadcast to the row
+  // position j (row-uniform) broadcast to the row: slot j % S of lane j / S
   __device__ __forceinline__ void slot(int j, double &od, int32_t &orr) const {
-    const int s = j >> 4, src = j & 15;
+    const int s = j % S, src = j / S;
     double vd = d[0];
     int32_t vr = r[0];
 #pragma unroll
@@ -179,28 +190,18 @@ struct RowTopK {
 #pragma unroll
     for (int s = 0; s < S; ++s)
       pos += __popc(row_bits(__ballot(key_less(d[s], r[s], cd, cr)), g));
-    // slot 16 s + l takes slot 16 s + l - 1 when it lies after the insertion point; lane 0
-    // of slot s takes lane 15 of slot s - 1.  Slots that lie wholly before every row's
-    // insertion point stay as they are.
-    double wd = 0.0;
-    int32_t wr = 0;
+    // position S l + s takes position S l + s - 1 when it lies after the insertion point:
+    // slot s - 1 of the same lane, or, for slot 0, the last slot of lane l - 1 (DPP
+    // row_shr:1; lane 0's slot 0 is position 0, never after the insertion point)
+    const double pd = dpp_f64<kDppRowShr1>(d[S - 1], d[S - 1]);
+    const int32_t pr = dpp_i32<kDppRowShr1>(r[S - 1], r[S - 1]);
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const double last_d = S > 1 ? dpp_f64<kDppRowBcast15>(d[s], d[s]) : 0.0;
-      const int32_t last_r = S > 1 ? dpp_i32<kDppRowBcast15>(r[s], r[s]) : 0;
-      if (S == 1 || __ballot(pos <= 16 * s + 15) != 0) {
-        double pd = dpp_f64<kDppRowShr1>(d[s], d[s]);
-        int32_t pr = dpp_i32<kDppRowShr1>(r[s], r[s]);
-        if (s > 0) {
-          pd = (l == 0) ? wd : pd;
-          pr = (l == 0) ? wr : pr;
-        }
-        const int j = 16 * s + l;
-        d[s] = j > pos ? pd : (j == pos ? cd : d[s]);
-        r[s] = j > pos ? pr : (j == pos ? cr : r[s]);
-      }
-      wd = last_d;
-      wr = last_r;
+    for (int s = S - 1; s >= 0; --s) {
+      const int j = S * l + s;
+      const double prevd = s > 0 ? d[s > 0 ? s - 1 : 0] : pd;
+      const int32_t prevr = s > 0 ? r[s > 0 ? s - 1 : 0] : pr;
+      d[s] = j > pos ? prevd : (j == pos ? cd : d[s]);
+      r[s] = j > pos ? prevr : (j == pos ? cr : r[s]);
     }
     return true;
   }
@@ -236,64 +237,84 @@ struct RowTopK {
     return better ? 1 : 0;
   }
 
-  // k > 16 (S slots per lane; slot s of lane l holds position 16 s + l): merge every lane's
-  // candidate with `better` set at once.  The candidates are sorted across the row and
-  // carried through the slots in order: at slot s the elementwise minimum of the slot and
-  // the mirrored carry (bitonic) becomes the new slot, the maximum (bitonic) the new carry,
-  // each sorted by a 4-stage bitonic merge; what is carried out of the last slot drops out.
-  // A slot whose largest key lies below every row's smallest carried key is left alone.
-  // Candidates already in N can only equal a key of a slot that is merged; they are dropped
-  // there (and the carry compacted) before the merge.
+  // k > 16 (S slots per lane, lane l holding positions S l .. S l + S - 1): merge every
+  // lane's candidate with `better` set at once, by ranks.  The candidates are sorted across
+  // the row and each finds by binary search over N (staged in LDS) how many keys of N lie
+  // below it, p; a candidate whose rank N already holds meets its own key there and is
+  // dropped.  The kept ones, numbered 0, 1, ... in order, have non-decreasing p, so the
+  // number of kept candidates below the key at position i is the largest (number + 1) of a
+  // kept candidate with p <= i: each kept candidate posts (number + 1) at position p with
+  // an LDS maximum, and a running maximum over the positions (within the lane, then across
+  // the row by DPP) gives every key its count.  Every key's new position is its old one
+  // plus that count; the keys that land below 16 S are scattered back into the staging
+  // area (every search has read it by then) and read back.  Kept candidates and keys of N
+  // never tie (equal keys mean equal ranks), so the new positions are a permutation.  The
+  // LDS areas are per row (16 rows of a 256-thread workgroup); the lanes of a row exchange
+  // values through them without a barrier, as LDS operations of one wavefront complete in
+  // program order.
   __device__ __forceinline__ int mergeS(bool better, double dd, int32_t rr, int l, int g,
                                         int k) {
     static_assert(S > 1, "mergeS serves more than one slot per lane");
+    constexpr int L = 16 * S;
+    constexpr int TOP = S == 2 ? 32 : 64;   // a power of two >= L / 2 (S = 2, 3, 4)
+    __shared__ double s_nd[16][L];
+    __shared__ int32_t s_nr[16][L];
+    __shared__ uint32_t s_m[16][L];
+    const int row = (int)(threadIdx.x >> 4);
     double cd = better ? dd : INFINITY;
     int32_t cr = better ? rr : kEmpty;
     row_sort16(cd, cr, l);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const double c0d = dpp_f64<kDppRowBcast0>(cd, cd);
-      const int32_t c0r = dpp_i32<kDppRowBcast0>(cr, cr);
-      const double n15d = dpp_f64<kDppRowBcast15>(d[s], d[s]);
-      const int32_t n15r = dpp_i32<kDppRowBcast15>(r[s], r[s]);
-      if (__ballot(!key_less(n15d, n15r, c0d, c0r)) == 0) continue;   // nothing lands here
-      // evaluated by every lane: the row moves must see all 16 ranks of the slot
-      const bool seen = in_row(cr, r[s], std::make_integer_sequence<int, 16>{});
-      const bool dup = seen & (cr != kEmpty);
-      if (__ballot(dup) != 0) {
-        cd = dup ? INFINITY : cd;
-        cr = dup ? kEmpty : cr;
-        // stable compaction of the row: kept candidates first, +inf after
-        const bool keep = cr != kEmpty;
-        const uint32_t bits = row_bits(__ballot(keep), g);
-        const int below = __popc(bits & ((1u << l) - 1u));
-        const int dst = keep ? below : __popc(bits) + (l - below);
-        const int addr = 4 * (16 * g + dst);
-        const int64_t v = __double_as_longlong(cd);
-        const int32_t lo = __builtin_amdgcn_ds_permute(addr, (int32_t)v);
-        const int32_t hi = __builtin_amdgcn_ds_permute(addr, (int32_t)(v >> 32));
-        cr = __builtin_amdgcn_ds_permute(addr, cr);
-        cd = __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+      s_nd[row][S * l + s] = d[s];
+      s_nr[row][S * l + s] = r[s];
+      s_m[row][S * l + s] = 0u;
+    }
+    wave_lds_sync();
+    // keys of N below the candidate (binary lifting over the sorted L keys)
+    int p = 0;
+#pragma unroll
+    for (int step = TOP; step > 0; step >>= 1)
+      if (p + step <= L && key_less(s_nd[row][p + step - 1], s_nr[row][p + step - 1], cd, cr))
+        p += step;
+    const bool real = cr != kEmpty;
+    const bool held = real && p < L && s_nr[row][p < L ? p : 0] == cr;
+    const bool kept = real && !held;
+    const int jk = __popc(row_bits(__ballot(kept), g) & ((1u << l) - 1u));
+    if (kept && p < L) atomicMax(&s_m[row][p], (uint32_t)(jk + 1));
+    wave_lds_sync();
+    // kept candidates below each key: running maximum within the lane, then the maximum
+    // over the lanes below (inclusive scan by DPP row_shr, shifted by one lane)
+    uint32_t below[S];
+    uint32_t run = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      run = max(run, s_m[row][S * l + s]);
+      below[s] = run;
+    }
+    uint32_t sc = run;
+    sc = max(sc, (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)sc, 0x111, 0xf, 0xf, false));
+    sc = max(sc, (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)sc, 0x112, 0xf, 0xf, false));
+    sc = max(sc, (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)sc, 0x114, 0xf, 0xf, false));
+    sc = max(sc, (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)sc, 0x118, 0xf, 0xf, false));
+    const uint32_t lower = (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)sc, 0x111, 0xf, 0xf, false);
+    if (kept && jk + p < L) {   // every lane's searches read the staged keys before this
+      s_nd[row][jk + p] = cd;
+      s_nr[row][jk + p] = cr;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int np = S * l + s + (int)max(lower, below[s]);
+      if (np < L) {
+        s_nd[row][np] = d[s];
+        s_nr[row][np] = r[s];
       }
-      const double md = xor_lane_f64<15>(cd);
-      const int32_t mr = xor_lane<15>(cr);
-      const bool lt = key_less(md, mr, d[s], r[s]);
-      double lod = lt ? md : d[s], hid = lt ? d[s] : md;
-      int32_t lor = lt ? mr : r[s], hir = lt ? r[s] : mr;
-      cas_stage<8, 8>(lod, lor, l);
-      cas_stage<4, 4>(lod, lor, l);
-      cas_stage<2, 2>(lod, lor, l);
-      cas_stage<1, 1>(lod, lor, l);
-      d[s] = lod;
-      r[s] = lor;
-      if (s + 1 < S) {
-        cas_stage<8, 8>(hid, hir, l);
-        cas_stage<4, 4>(hid, hir, l);
-        cas_stage<2, 2>(hid, hir, l);
-        cas_stage<1, 1>(hid, hir, l);
-        cd = hid;
-        cr = hir;
-      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      d[s] = s_nd[row][S * l + s];
+      r[s] = s_nr[row][S * l + s];
     }
     if (EXACTK) {
       thr_d = dpp_f64<kDppRowBcast15>(d[S - 1], d[S - 1]);
@@ -501,7 +522,7 @@ __device__ __forceinline__ void group_query(const QueryArgs &a, int64_t s, int l
   }
 #pragma unroll
   for (int t = 0; t < S; ++t) {
-    const int j = 16 * t + l;
+    const int j = S * l + t;   // lane l holds positions S l .. S l + S - 1
     if (j < k) {
       const bool empty = N.r[t] == kEmpty;
       a.out_idx[row + j] = empty ? -1 : N.r[t];

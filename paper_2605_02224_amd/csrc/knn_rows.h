@@ -151,7 +151,7 @@ struct RowWalker {
     const int64_t row = !UNIFORM && a.row_off ? a.row_off[qi] : qi * (int64_t)k;
 #pragma unroll
     for (int t = 0; t < S; ++t) {
-      const int j = 16 * t + l;
+      const int j = S * l + t;   // lane l holds positions S l .. S l + S - 1
       if (j < k) {
         const bool empty = N.r[t] == kEmpty;
         a.out_idx[row + j] = empty ? -1 : N.r[t];
@@ -173,21 +173,28 @@ struct RowWalker {
     const int g = (int)((threadIdx.x & 63) >> 4);
     const int32_t ko = !UNIFORM && a.kq ? a.kq[qi] : a.kout;
     const int64_t row = !UNIFORM && a.row_off ? a.row_off[qi] : qi * (int64_t)ko;
-    int32_t kept = 0;
+    // position S l + t (lane l holds S consecutive positions): the unmarked entries before
+    // it are those of the lanes below l, and those of this lane's earlier slots
+    bool live[S];
+    int32_t before = 0, kept = 0;
 #pragma unroll
     for (int t = 0; t < S; ++t) {
       const int32_t r = N.r[t];
-      const bool listed = 16 * t + l < k && r != kEmpty;
+      const bool listed = S * l + t < k && r != kEmpty;
       uint32_t e = 0;
       if (listed) e = a.dead[r];
-      const bool live = listed && (e == 0 || e > a.epoch);
-      const uint32_t lm = row_bits(__ballot(live), g);
-      const int32_t pos = kept + __popc(lm & ((1u << l) - 1u));
-      if (live && pos < ko) {
-        a.out_idx[row + pos] = r;
-        a.out_dist[row + pos] = (float)sqrt(N.d[t]);
-      }
+      live[t] = listed && (e == 0 || e > a.epoch);
+      const uint32_t lm = row_bits(__ballot(live[t]), g);
+      before += __popc(lm & ((1u << l) - 1u));
       kept += __popc(lm);
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      if (live[t] && before < ko) {
+        a.out_idx[row + before] = N.r[t];
+        a.out_dist[row + before] = (float)sqrt(N.d[t]);
+      }
+      before += live[t] ? 1 : 0;
     }
     for (int32_t j = kept + l; j < ko; j += 16) {
       a.out_idx[row + j] = -1;
@@ -439,7 +446,8 @@ struct RowWalker {
 // Plain launch: a wavefront owns `per_wave` consecutive sorted queries; row g takes
 // positions g, g + 4, g + 8, ... of them, so the rows stay on Morton neighbours.
 template <int S, bool EXACTK, bool DESCENT_FIRST, bool UNIFORM, bool LAZY = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : (S == 2 ? 7 : 1), 8)))
 void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
   const int lane = threadIdx.x & 63;
   const int l = lane & 15, g = lane >> 4;

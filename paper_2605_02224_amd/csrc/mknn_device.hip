@@ -1134,7 +1134,7 @@ mknn_status mknn_autotune(const mknn_cloud *c, const float *d_q, int64_t nq, int
     if (S == 1)
       for (int mm : {4, 6, 8}) cand.push_back({3, mm, pw});
     else
-      for (int mm : {8, 11, 14, 17}) cand.push_back({3, mm, pw});   // 17: never the network
+      for (int mm : {2, 4, 6, 8, 11}) cand.push_back({3, mm, pw});
   }
   cand.push_back({2, 6, 4});
   cand.push_back({1, 6, 4});
