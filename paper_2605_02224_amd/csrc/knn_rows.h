@@ -45,17 +45,23 @@ __device__ __forceinline__ void offer_all(RowTopK<S, EXACTK> &N, bool cand, doub
     N.insert_each(cand, dd, rr, l, g, k);
 }
 
-// kRowSettle (one slot per lane, descent steps first): the descent has ended and N is
-// still to be seeded from the ring (settle()).
+// kRowSettle (descent steps first): the descent has ended and N is still to be seeded from
+// the ring (settle()).
 constexpr int32_t kRowDescent = 0, kRowExpand = 1, kRowIdle = 2, kRowSettle = 3;
 
-// Per-row rings of transition sites (k <= 16), 16 entries for each of the 16 rows of a
-// 256-thread workgroup (every launch of these kernels uses 256 threads).  In LDS rather
-// than registers: 32 more VGPRs per lane would cost occupancy.
-__shared__ double g_ring_d[16 * 16];
-__shared__ int32_t g_ring_r[16 * 16];
-__device__ __forceinline__ double *ring_d(const QueryArgs &) { return g_ring_d + 16 * (threadIdx.x >> 4); }
-__device__ __forceinline__ int32_t *ring_r(const QueryArgs &) { return g_ring_r + 16 * (threadIdx.x >> 4); }
+// Per-row rings of transition sites, 16 S entries (the class's largest k) for each of the
+// 16 rows of a 256-thread workgroup (every launch of these kernels uses 256 threads).  In
+// LDS rather than registers: 32 more VGPRs per lane would cost occupancy.
+template <int S>
+__device__ __forceinline__ double *ring_d() {
+  __shared__ double ring[16 * 16 * S];
+  return ring + 16 * S * (threadIdx.x >> 4);
+}
+template <int S>
+__device__ __forceinline__ int32_t *ring_r() {
+  __shared__ int32_t ring[16 * 16 * S];
+  return ring + 16 * S * (threadIdx.x >> 4);
+}
 
 // The state of one row's current query.  Row-uniform values, held by every lane of the row.
 // WIDE_Q: hold the query in float64 (widened once rather than at every chunk), where the
@@ -77,9 +83,10 @@ struct RowWalker {
   // key of the confirmed neighbour whose list an expansion row scans (slot `it` of N)
   double od = 0;
   int32_t orr = 0;
-  // k <= 16: the transition sites of the descent (Alg. 1) go to a ring of 16 in LDS (entry
-  // t % 16 for the t-th); each is strictly closer than the one before, so the last 16 are
-  // the only ones that can rank among the k nearest and the ring holds them sorted.
+  // Descent steps first: the transition sites of the descent (Alg. 1) go to a ring of 16 S
+  // in LDS (entry t % 16 S for the t-th); each is strictly closer than the one before, so
+  // the last k are the only ones that can rank among the k nearest and the ring holds them
+  // sorted.
   int32_t ntrans = 0;
 
   // Start the query at sorted position s of request a.  A query whose prefix holds no live
@@ -117,13 +124,13 @@ struct RowWalker {
     const double dx = (double)qx - (double)a.hx, dy = (double)qy - (double)a.hy,
                  dz = (double)qz - (double)a.hz;
     dcur = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-    if constexpr (S == 1) {
-      if (l == 0) {
-        ring_d(a)[0] = dcur;
-        ring_r(a)[0] = cur;
-      }
-      ntrans = 1;
-    } else {
+    if (l == 0) {
+      ring_d<S>()[0] = dcur;
+      ring_r<S>()[0] = cur;
+    }
+    ntrans = 1;
+    if constexpr (S > 1) {
+      // the step<false> path seeds N with the transition sites directly
       if (l == 0) {
         N.d[0] = dcur;
         N.r[0] = cur;
@@ -266,8 +273,8 @@ struct RowWalker {
       cur = __shfl(r, j, 16);
       if constexpr (S == 1) {
         if (l == (ntrans & 15)) {
-          ring_d(a)[l] = dcur;
-          ring_r(a)[l] = cur;
+          ring_d<1>()[l] = dcur;
+          ring_r<1>()[l] = cur;
         }
         ++ntrans;
       }
@@ -279,8 +286,8 @@ struct RowWalker {
       // and the final list is scanned again as the expansion of N[0]
       const int have = ntrans < 16 ? ntrans : 16;
       const int src = (ntrans - 1 - l) & 15;
-      N.d[0] = l < have ? ring_d(a)[src] : INFINITY;
-      N.r[0] = l < have ? ring_r(a)[src] : kEmpty;
+      N.d[0] = l < have ? ring_d<S>()[src] : INFINITY;
+      N.r[0] = l < have ? ring_r<S>()[src] : kEmpty;
       N.refresh_threshold(k);
       od = dcur;   // slot 0: the nearest site, p_cur
       orr = cur;
@@ -315,17 +322,16 @@ struct RowWalker {
 
   // Descent steps first (DESCENT_FIRST): the two kinds of step below do what step<true>
   // does, each with only the work its rows need.  While some row of the wavefront is in its
-  // descent only those rows advance; once no row is, every busy row expands.  With one slot
-  // per lane the descent offers nothing to N (the transition sites go to the ring); with
-  // more, a jumping row offers its transition site and a row that does not jump offers the
-  // chunk (a long list that jumps later, or the final list, which is then Alg. 2's first
-  // iteration).
+  // descent only those rows advance, offering nothing to N: the transition sites go to the
+  // ring.  Once no row is, settle() seeds N from the ring and every busy row expands; the
+  // descent's final list is scanned again as the expansion of N[0], p_cur.
 
   // A step while some row is in its descent.
   __device__ __forceinline__ void step_descent(const QueryArgs &a, const float4 *ent,
                                                const uint64_t *lst, int l, int g, int32_t uk,
                                                int32_t um, int merge_min = 0) {
-    const int32_t k = EXACTK ? 16 * S : (UNIFORM ? uk : this->k);
+    (void)uk;
+    (void)merge_min;
     const int32_t m = UNIFORM ? um : this->m;
     const bool desc = phase == kRowDescent;
     const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
@@ -338,50 +344,43 @@ struct RowWalker {
     const double dv = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
     const uint32_t vmask = row_bits(__ballot(valid), g);
     const uint32_t jm = row_bits(__ballot(valid && dv < dcur), g);
-    if constexpr (S > 1) {
-      // tested against the k-th key on D only: an entry tied with it but of larger rank
-      // lands past the last slot
-      const int j = jm ? __ffs(jm) - 1 : 0;
-      const bool cand = (jm ? l == j : valid) && dv <= N.thr_d;
-      offer_all(N, cand, dv, r, l, g, k, merge_min);
-    }
     if (jm) {
       // the first strictly closer entry is the next transition site (Alg. 1)
       const int j = __ffs(jm) - 1;
       dcur = __shfl(dv, j, 16);
       cur = __shfl(r, j, 16);
-      if constexpr (S == 1) {
-        if (l == (ntrans & 15)) {
-          ring_d(a)[l] = dcur;
-          ring_r(a)[l] = cur;
-        }
-        ++ntrans;
+      if (l == (ntrans & 15)) {
+        ring_d<S>()[ntrans % (16 * S)] = dcur;
+        ring_r<S>()[ntrans % (16 * S)] = cur;
       }
+      ++ntrans;
       dsc = lst[cur];
       base = 0;
     } else if (desc) {
-      if (vmask == 0xffffu && base + 16 < len) {
+      if (vmask == 0xffffu && base + 16 < len)
         base += 16;   // the next chunk of a long list
-      } else if constexpr (S > 1) {
-        // the final list has been offered: the expansion continues with N[1]'s list
-        next_list(a, lst, l, k, 1);
-      } else {
+      else
         phase = kRowSettle;   // the descent ends at p_cur; N is seeded by settle()
-      }
     }
   }
 
-  // One slot per lane: a row whose descent has ended at p_cur starts N as the last
-  // transition sites, nearest first, and scans the final list again as the expansion of
-  // N[0].  Called once no row is in its descent (kept out of the descent steps, whose loop
-  // then carries fewer values).
+  // A row whose descent has ended at p_cur starts N as the last transition sites, nearest
+  // first, and scans the final list again as the expansion of N[0].  Called once no row is
+  // in its descent (kept out of the descent steps, whose loop then carries fewer values).
+  // Position S l + t of N takes the (S l + t)-th newest site of the ring.
   __device__ __forceinline__ void settle(const QueryArgs &a, int l, int32_t uk) {
-    const int32_t k = EXACTK ? 16 : (UNIFORM ? uk : this->k);
+    const int32_t k = EXACTK ? 16 * S : (UNIFORM ? uk : this->k);
+    wave_lds_sync();   // the ring entries were written by other lanes of the row
     if (phase != kRowSettle) return;
-    const int have = ntrans < 16 ? ntrans : 16;
-    const int src = (ntrans - 1 - l) & 15;
-    N.d[0] = l < have ? ring_d(a)[src] : INFINITY;
-    N.r[0] = l < have ? ring_r(a)[src] : kEmpty;
+    constexpr int R = 16 * S;
+    const int have = ntrans < R ? ntrans : R;
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int pos = S * l + t;
+      const int src = pos < have ? (ntrans - 1 - pos) % R : 0;
+      N.d[t] = pos < have ? ring_d<S>()[src] : INFINITY;
+      N.r[t] = pos < have ? ring_r<S>()[src] : kEmpty;
+    }
     N.refresh_threshold(k);
     od = dcur;
     orr = cur;
@@ -463,7 +462,7 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
     if (begin + g < end) w.begin(a, begin + g, l);
     while (__ballot(w.phase == kRowDescent) != 0)
       w.step_descent(a, a.ent, a.lst, l, g, a.k, m, a.merge_min);
-    if constexpr (S == 1) w.settle(a, l, a.k);
+    w.settle(a, l, a.k);
     while (__ballot(w.phase != kRowIdle) != 0)
       w.step_expand(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
   } else {

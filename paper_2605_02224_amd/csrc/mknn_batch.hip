@@ -256,9 +256,7 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
     if (__ballot(w.phase == kRowDescent) != 0) {
       w.step_descent(reqs[req], ent, lst, l, g, rk, rm, merge_min);
     } else {
-      if constexpr (S == 1) {
-        if (__ballot(w.phase == kRowSettle) != 0) w.settle(reqs[req], l, rk);
-      }
+      if (__ballot(w.phase == kRowSettle) != 0) w.settle(reqs[req], l, rk);
       if (__ballot(w.phase != kRowIdle) != 0)
         w.step_expand(reqs[req], ent, lst, merge_min, l, g, rk, rm);
     }
@@ -303,7 +301,7 @@ void knn_batch_flat_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
   if (begin + g < end) w.begin(a, begin + g, l);
   while (__ballot(w.phase == kRowDescent) != 0)
     w.step_descent(a, a.ent, a.lst, l, g, a.k, m, a.merge_min);
-  if constexpr (S == 1) w.settle(a, l, a.k);
+  w.settle(a, l, a.k);
   while (__ballot(w.phase != kRowIdle) != 0)
     w.step_expand(a, a.ent, a.lst, a.merge_min, l, g, a.k, m);
 }

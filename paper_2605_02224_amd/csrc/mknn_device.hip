@@ -544,9 +544,9 @@ static long env_long(const char *name, long dflt) {
 }
 
 // Defaults measured on the 1M torus: scheduled rows, one query per row, and the merge
-// network from 6 / 9 / 10 / 11 candidates per chunk for S = 1..4 slots per lane.
+// network from 6 / 8 / 8 / 8 candidates per chunk for S = 1..4 slots per lane.
 static TuneConfig default_config(int S) {
-  static const int32_t mm[4] = {6, 9, 10, 11};
+  static const int32_t mm[4] = {6, 8, 8, 8};
   return {3, mm[(S < 1 ? 1 : S > 4 ? 4 : S) - 1], 4};
 }
 
@@ -1134,7 +1134,7 @@ mknn_status mknn_autotune(const mknn_cloud *c, const float *d_q, int64_t nq, int
     if (S == 1)
       for (int mm : {4, 6, 8}) cand.push_back({3, mm, pw});
     else
-      for (int mm : {2, 4, 6, 8, 11}) cand.push_back({3, mm, pw});
+      for (int mm : {4, 6, 8, 11}) cand.push_back({3, mm, pw});
   }
   cand.push_back({2, 6, 4});
   cand.push_back({1, 6, 4});
