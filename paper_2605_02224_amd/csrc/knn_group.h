@@ -129,6 +129,33 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Per-row LDS of the row kernels, S > 1 (16 rows of a 256-thread workgroup).  A row's ring
+// of transition sites (written by the descent, read once by settle) and its merge area
+// (expansion only) are never in use at the same time, so they share the row's bytes.  The
+// row size is 16 words more than a multiple of 32, so the two rows of a 32-lane LDS pass
+// fall on different banks.
+template <int S>
+struct RowLds {
+  static constexpr int L = 16 * S, W = L + 16;
+  union {
+    struct {
+      double d[L];
+      int32_t r[L];
+    } ring;
+    struct {
+      double nd[L];     // position p at (p mod S) 16 + p / S
+      int32_t nr[W];
+      uint32_t m[W];
+    } merge;
+  };
+  int32_t pad[16];
+};
+template <int S>
+__device__ __forceinline__ RowLds<S> &row_lds() {
+  __shared__ RowLds<S> rows[16];
+  return rows[threadIdx.x >> 4];
+}
+
 template <int S, bool EXACTK>
 struct RowTopK {
   double d[S];
@@ -247,7 +274,8 @@ struct RowTopK {
   // an LDS maximum, and a running maximum over the positions (within the lane, then across
   // the row by DPP) gives every key its count.  Every key's new position is its old one
   // plus that count; the keys that land below 16 S are scattered back into the staging
-  // area (every search has read it by then) and read back.  Kept candidates and keys of N
+  // area (every search has read it by then) and read back.  Position p is held in LDS at
+  // (p mod S) 16 + p / S, and the 4-byte rows are padded, against bank conflicts.  Kept candidates and keys of N
   // never tie (equal keys mean equal ranks), so the new positions are a permutation.  The
   // LDS areas are per row (16 rows of a 256-thread workgroup); the lanes of a row exchange
   // values through them without a barrier, as LDS operations of one wavefront complete in
@@ -257,31 +285,35 @@ struct RowTopK {
     static_assert(S > 1, "mergeS serves more than one slot per lane");
     constexpr int L = 16 * S;
     constexpr int TOP = S == 2 ? 32 : 64;   // a power of two >= L / 2 (S = 2, 3, 4)
-    __shared__ double s_nd[16][L];
-    __shared__ int32_t s_nr[16][L];
-    __shared__ uint32_t s_m[16][L];
-    const int row = (int)(threadIdx.x >> 4);
+    // position p is stored at (p mod S) 16 + p / S: each slot's 16 positions are contiguous,
+    // so staging and reading back a lane's slots are free of bank conflicts
+    auto at = [](int p) { return (p % S) * 16 + p / S; };
+    RowLds<S> &lds = row_lds<S>();
+    double *s_nd = lds.merge.nd;
+    int32_t *s_nr = lds.merge.nr;
+    uint32_t *s_m = lds.merge.m;
     double cd = better ? dd : INFINITY;
     int32_t cr = better ? rr : kEmpty;
     row_sort16(cd, cr, l);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      s_nd[row][S * l + s] = d[s];
-      s_nr[row][S * l + s] = r[s];
-      s_m[row][S * l + s] = 0u;
+      s_nd[16 * s + l] = d[s];
+      s_nr[16 * s + l] = r[s];
+      s_m[16 * s + l] = 0u;
     }
     wave_lds_sync();
     // keys of N below the candidate (binary lifting over the sorted L keys)
     int p = 0;
 #pragma unroll
     for (int step = TOP; step > 0; step >>= 1)
-      if (p + step <= L && key_less(s_nd[row][p + step - 1], s_nr[row][p + step - 1], cd, cr))
+      if (p + step <= L &&
+          key_less(s_nd[at(p + step - 1)], s_nr[at(p + step - 1)], cd, cr))
         p += step;
     const bool real = cr != kEmpty;
-    const bool held = real && p < L && s_nr[row][p < L ? p : 0] == cr;
+    const bool held = real && p < L && s_nr[at(p < L ? p : 0)] == cr;
     const bool kept = real && !held;
     const int jk = __popc(row_bits(__ballot(kept), g) & ((1u << l) - 1u));
-    if (kept && p < L) atomicMax(&s_m[row][p], (uint32_t)(jk + 1));
+    if (kept && p < L) atomicMax(&s_m[at(p)], (uint32_t)(jk + 1));
     wave_lds_sync();
     // kept candidates below each key: running maximum within the lane, then the maximum
     // over the lanes below (inclusive scan by DPP row_shr, shifted by one lane)
@@ -289,7 +321,7 @@ struct RowTopK {
     uint32_t run = 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      run = max(run, s_m[row][S * l + s]);
+      run = max(run, s_m[16 * s + l]);
       below[s] = run;
     }
     uint32_t sc = run;
@@ -299,22 +331,22 @@ struct RowTopK {
     sc = max(sc, (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)sc, 0x118, 0xf, 0xf, false));
     const uint32_t lower = (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)sc, 0x111, 0xf, 0xf, false);
     if (kept && jk + p < L) {   // every lane's searches read the staged keys before this
-      s_nd[row][jk + p] = cd;
-      s_nr[row][jk + p] = cr;
+      s_nd[at(jk + p)] = cd;
+      s_nr[at(jk + p)] = cr;
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int np = S * l + s + (int)max(lower, below[s]);
       if (np < L) {
-        s_nd[row][np] = d[s];
-        s_nr[row][np] = r[s];
+        s_nd[at(np)] = d[s];
+        s_nr[at(np)] = r[s];
       }
     }
     wave_lds_sync();
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      d[s] = s_nd[row][S * l + s];
-      r[s] = s_nr[row][S * l + s];
+      d[s] = s_nd[16 * s + l];
+      r[s] = s_nr[16 * s + l];
     }
     if (EXACTK) {
       thr_d = dpp_f64<kDppRowBcast15>(d[S - 1], d[S - 1]);

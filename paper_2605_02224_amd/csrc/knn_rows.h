@@ -51,16 +51,19 @@ constexpr int32_t kRowDescent = 0, kRowExpand = 1, kRowIdle = 2, kRowSettle = 3;
 
 // Per-row rings of transition sites, 16 S entries (the class's largest k) for each of the
 // 16 rows of a 256-thread workgroup (every launch of these kernels uses 256 threads).  In
-// LDS rather than registers: 32 more VGPRs per lane would cost occupancy.
+// LDS rather than registers: 32 more VGPRs per lane would cost occupancy.  For S > 1 the
+// ring shares the row's LDS with the merge area (RowLds).
+__shared__ double g_ring1_d[16 * 16];
+__shared__ int32_t g_ring1_r[16 * 16];
 template <int S>
 __device__ __forceinline__ double *ring_d() {
-  __shared__ double ring[16 * 16 * S];
-  return ring + 16 * S * (threadIdx.x >> 4);
+  if constexpr (S == 1) return g_ring1_d + 16 * (threadIdx.x >> 4);
+  else return row_lds<S>().ring.d;
 }
 template <int S>
 __device__ __forceinline__ int32_t *ring_r() {
-  __shared__ int32_t ring[16 * 16 * S];
-  return ring + 16 * S * (threadIdx.x >> 4);
+  if constexpr (S == 1) return g_ring1_r + 16 * (threadIdx.x >> 4);
+  else return row_lds<S>().ring.r;
 }
 
 // The state of one row's current query.  Row-uniform values, held by every lane of the row.
@@ -446,7 +449,7 @@ struct RowWalker {
 // positions g, g + 4, g + 8, ... of them, so the rows stay on Morton neighbours.
 template <int S, bool EXACTK, bool DESCENT_FIRST, bool UNIFORM, bool LAZY = false>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : (S == 2 ? 7 : 1), 8)))
+__attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : (S == 2 ? 8 : (S == 3 ? 7 : 6)), 8)))
 void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
   const int lane = threadIdx.x & 63;
   const int l = lane & 15, g = lane >> 4;
