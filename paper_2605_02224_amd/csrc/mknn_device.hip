@@ -208,11 +208,13 @@ constexpr int kMortonBits = 16;
 constexpr int kMortonBins = 1 << kMortonBits;
 constexpr int64_t kSortMinQueries = 8192;
 
+// The histogram's atomic hands every query its rank within its bin, so the scatter below
+// places it with no atomic of its own.
 __global__ __launch_bounds__(256) void morton_hist_kernel(const float *q, int64_t nq, BoxArgs b,
-                                                          uint32_t *hist) {
+                                                          uint32_t *hist, uint32_t *rank) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nq) return;
-  atomicAdd(&hist[morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], b) >> (30 - kMortonBits)], 1u);
+  rank[i] = atomicAdd(&hist[morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], b) >> (30 - kMortonBits)], 1u);
 }
 
 // exclusive scan of kMortonBins counters by one workgroup of 1024 threads
@@ -243,12 +245,14 @@ __global__ __launch_bounds__(1024) void scan_bins_kernel(uint32_t *hist) {
   }
 }
 
+// start: each bin's first position (the exclusive scan of the histogram)
 __global__ __launch_bounds__(256) void morton_scatter_kernel(const float *q, int64_t nq, BoxArgs b,
-                                                             uint32_t *cursor, float4 *qs) {
+                                                             const uint32_t *start,
+                                                             const uint32_t *rank, float4 *qs) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nq) return;
   float x = q[3 * i], y = q[3 * i + 1], z = q[3 * i + 2];
-  uint32_t pos = atomicAdd(&cursor[morton30(x, y, z, b) >> (30 - kMortonBits)], 1u);
+  const uint32_t pos = start[morton30(x, y, z, b) >> (30 - kMortonBits)] + rank[i];
   qs[pos] = make_float4(x, y, z, __int_as_float((int32_t)i));
 }
 
@@ -687,7 +691,9 @@ static hipError_t dispatch_rows(const QueryArgs &a, int kmax, bool exact, int32_
 
 // Bytes of scratch the Morton bucketing of nq queries needs (0 below the sort threshold).
 static size_t sort_scratch_bytes(int64_t nq) {
-  return nq < kSortMinQueries ? 0 : sizeof(uint32_t) * kMortonBins + sizeof(float4) * (size_t)nq;
+  return nq < kSortMinQueries ? 0
+                              : sizeof(uint32_t) * kMortonBins +
+                                    (sizeof(float4) + sizeof(uint32_t)) * (size_t)nq;
 }
 
 // Morton bucketing of the queries, for batches large enough to pay for it.  The scratch
@@ -705,14 +711,16 @@ static mknn_status prepare_queries(const mknn_cloud *c, const float *d_q, int64_
     hist = (uint32_t *)*scratch;
   }
   float4 *qs = (float4 *)(hist + kMortonBins);
+  uint32_t *rank = (uint32_t *)(qs + nq);
   BoxArgs b = dev_box_of(c);
   const int threads = 256;
   const uint32_t blocks = (uint32_t)((nq + threads - 1) / threads);
   hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(kMortonBins / threads), dim3(threads), 0, s,
                      hist, (int64_t)kMortonBins, 0u);
-  hipLaunchKernelGGL(morton_hist_kernel, dim3(blocks), dim3(threads), 0, s, d_q, nq, b, hist);
+  hipLaunchKernelGGL(morton_hist_kernel, dim3(blocks), dim3(threads), 0, s, d_q, nq, b, hist, rank);
   hipLaunchKernelGGL(scan_bins_kernel, dim3(1), dim3(1024), 0, s, hist);
-  hipLaunchKernelGGL(morton_scatter_kernel, dim3(blocks), dim3(threads), 0, s, d_q, nq, b, hist, qs);
+  hipLaunchKernelGGL(morton_scatter_kernel, dim3(blocks), dim3(threads), 0, s, d_q, nq, b, hist,
+                     rank, qs);
   HIP_TRY(hipGetLastError(), "query sort launch");
   *qs_out = qs;
   return MKNN_OK;
@@ -835,7 +843,7 @@ static mknn_status check_per_query(const int32_t *d_k, const int32_t *d_m, const
 // ---------------------------------------------------------------------------------------
 constexpr int64_t kStaticMaxQueries = (int64_t)1 << 20;
 constexpr size_t kStaticScratchBytes =
-    sizeof(uint32_t) * kMortonBins + sizeof(float4) * (size_t)kStaticMaxQueries;
+    sizeof(uint32_t) * kMortonBins + (sizeof(float4) + sizeof(uint32_t)) * (size_t)kStaticMaxQueries;
 static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 constexpr int kMaxDevices = 64;
@@ -1042,7 +1050,8 @@ mknn_status mknn_knn_static(const mknn_cloud *c, const float *d_q, int64_t nq, i
   void *buf = nullptr;
   st = static_scratch(&buf);
   if (st != MKNN_OK) return st;
-  static_assert(kStaticScratchBytes >= sizeof(uint32_t) * kMortonBins + sizeof(float4) * (size_t)kStaticMaxQueries,
+  static_assert(kStaticScratchBytes >= sizeof(uint32_t) * kMortonBins +
+                                          (sizeof(float4) + sizeof(uint32_t)) * (size_t)kStaticMaxQueries,
                 "scratch holds the sort of the largest batch");
   return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, d_idx, d_dist, nullptr,
                    nullptr, nullptr, (hipStream_t)stream, "mknn_knn_static", nullptr, nullptr,
