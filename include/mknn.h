@@ -82,8 +82,10 @@ mknn_status mknn_build(const float *xyz, int64_t n, const int32_t *order, mknn_c
  *            the call synchronises it and returns when the lists are on the host.
  * Device memory: about 150 bytes per point for the created tetrahedra, their ridge table
  * and the sorted entries, plus 4 bytes per conflict record (a few hundred per point);
- * freed before the call returns.  Clouds of fewer than five points, and clouds whose first
- * four ranks are coplanar, are built by mknn_build (same lists, same errors).
+ * freed before the call returns.  Clouds whose first four ranks are coplanar start, as in
+ * mknn_build, from the first ranks off their line and plane (or spare points off them) and
+ * record the lists the same way.  Clouds of fewer than five points are built by mknn_build
+ * (same lists, same errors); so are those whose first two ranks coincide.
  * Errors: as mknn_build; EUNSUPPORTED for n above 2^21 - 2 (ridge keys pack three 21-bit
  * site ids); EHIP when a HIP call fails (device memory included); EDUPLICATE names the
  * first rank that repeats an older point, as mknn_build does. */
@@ -93,7 +95,8 @@ mknn_status mknn_build_device(const float *xyz, int64_t n, const int32_t *order,
 /* Counters of the calling thread's last mknn_build_device: counts[0] rounds, [1]
  * tetrahedra created (ghosts included), [2] conflict records written, [3] candidate tests,
  * [4] tests decided exactly on the host, [5] list entries; *ms (may be NULL) the call's
- * wall time in milliseconds.  Errors: EINVAL (counts NULL). */
+ * wall time in milliseconds.  All zero when the call was handed to mknn_build.
+ * Errors: EINVAL (counts NULL). */
 mknn_status mknn_build_device_stats(int64_t counts[6], double *ms);
 
 /* Number of points n of the cloud (including deleted ranks). */

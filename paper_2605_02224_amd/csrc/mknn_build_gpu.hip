@@ -407,6 +407,25 @@ __global__ void finish_kernel(const Job *__restrict__ jobs, const uint64_t *__re
   }
 }
 
+// Low-dimensional start: entries by position become entries by rank; an entry stays only
+// when its owner is an older real rank than its successor (a rank on the start's line or
+// plane has, among the older ranks, exactly its neighbours in the prefix's diagram, and the
+// start's later ranks and spare points own nothing here).
+__global__ void rank_pairs_kernel(uint64_t *pairs, int64_t m, const int32_t *rank_of_pos,
+                                  int64_t nreal) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m || pairs[e] == ~0ull) return;
+  const int64_t i = rank_of_pos[pairs[e] >> 32], j = rank_of_pos[(uint32_t)pairs[e]];
+  pairs[e] = (i < j && j < nreal) ? (((uint64_t)i << 32) | (uint64_t)j) : ~0ull;
+}
+
+// Entries (i, x) for every rank i < x: the start's ranks A and B (the first off the line,
+// the first off the plane) join every older list.
+__global__ void older_pairs_kernel(uint64_t *out, int64_t x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < x) out[i] = ((uint64_t)i << 32) | (uint64_t)x;
+}
+
 __global__ void fill_u64_kernel(uint64_t *p, uint64_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -533,11 +552,22 @@ struct Stats {
   double ms = 0;
 };
 
-// Lists by insertion position: succ.off / succ.ent over positions 0..n-1 (pos i's list holds
-// the later positions j whose creation of tetrahedra had i on the cavity boundary, plus
-// the start's pairs).  Returns 0, or the position of a duplicate site (> 0), or throws.
+// A start from ranks 0, 1, A, B when the first four ranks are coplanar (the host
+// construction's low-dimensional plan): the sites are then inserted in the order 0, 1, A,
+// B, the other real ranks ascending; A or B may be a spare point off the line or plane.
+struct LowDim {
+  std::vector<int32_t> rank_of_pos;   // rank (spares: nreal, nreal + 1) of each position
+  int64_t nreal = 0;
+  int32_t A = -1, B = -1;
+};
+
+// Successor lists of the sites at positions 0..n-1 of P (the insertion order).  Without a
+// low-dimensional plan the positions are the ranks: list i holds the later positions j
+// whose insertion created tetrahedra with i on the cavity boundary, plus the start's pairs.
+// With one, the entries are mapped to ranks as the host construction records them.
+// Throws the position of a duplicate site (int64_t), or std::runtime_error.
 static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStream_t st, Csr *succ,
-                               Stats *stats) {
+                               Stats *stats, const LowDim *ld = nullptr) {
   auto t0 = std::chrono::steady_clock::now();
   // sites as float4 (the inputs are float32; the host predicates see the same values)
   std::vector<float> P4(4 * (size_t)n);
@@ -735,10 +765,12 @@ static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStrea
     GB_CHECK(hipMemcpyAsync(jobs.p, j0.data(), sizeof(Job) * 5, hipMemcpyHostToDevice, st));
     GB_CHECK(hipMemcpyAsync(jobstart.p, s0.data(), sizeof(uint64_t) * 5, hipMemcpyHostToDevice, st));
     run_jobs(5, 5 * (uint64_t)l5, false);
-    // the start's list entries: every pair of the first four sites
+    // the start's list entries: every pair of the first four sites (low-dimensional start:
+    // only ranks 0 and 1, whose bisector plane is their common facet)
     std::vector<uint64_t> e0;
     for (int j = 1; j < 4; ++j)
-      for (int i = 0; i < j; ++i) e0.push_back(((uint64_t)i << 32) | (uint64_t)j);
+      for (int i = 0; i < j; ++i)
+        if (!ld || j == 1) e0.push_back(((uint64_t)i << 32) | (uint64_t)j);
     while (e0.size() < 18) e0.push_back(~0ull);   // pair slots of the six start tetrahedra
     GB_CHECK(hipMemcpyAsync(pairs.p, e0.data(), sizeof(uint64_t) * 18, hipMemcpyHostToDevice, st));
     // the ten ridge pairs of the start
@@ -812,7 +844,22 @@ static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStrea
   stats->tets = ntet - 1;   // the universe is no tetrahedron
 
   // entries (owner << 32 | successor): sort, drop repeats and the ghost slots, to CSR
-  const int64_t m = 3 * ntet;
+  int64_t m = 3 * ntet;
+  int64_t nout = n;   // lists produced
+  if (ld) {
+    DevBuf<int32_t> rop;
+    rop.reserve(n, st);
+    GB_CHECK(hipMemcpyAsync(rop.p, ld->rank_of_pos.data(), sizeof(int32_t) * n,
+                            hipMemcpyHostToDevice, st));
+    rank_pairs_kernel<<<blocks(m), 256, 0, st>>>(pairs.p, m, rop.p, ld->nreal);
+    const int64_t xa = ld->A < ld->nreal ? ld->A : 0, xb = ld->B < ld->nreal ? ld->B : 0;
+    pairs.reserve(m + xa + xb + 1, st, true, m);
+    if (xa > 0) older_pairs_kernel<<<blocks(xa), 256, 0, st>>>(pairs.p + m, xa);
+    if (xb > 0) older_pairs_kernel<<<blocks(xb), 256, 0, st>>>(pairs.p + m + xa, xb);
+    m += xa + xb;
+    nout = ld->nreal;
+    GB_CHECK(hipStreamSynchronize(st));   // rop ends with this block
+  }
   DevBuf<uint64_t> sorted, uniq;
   DevBuf<uint32_t> keep, kpos;
   sorted.reserve(m, st);
@@ -836,11 +883,12 @@ static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStrea
   DevBuf<int32_t> ent;
   DevBuf<int64_t> off;
   ent.reserve(nnz + 1, st);
-  off.reserve(n + 1, st);
-  csr_kernel<<<blocks(nnz + 1), 256, 0, st>>>(uniq.p, nnz, n, ent.p, off.p);
-  succ->off.resize(n + 1);
+  off.reserve(nout + 1, st);
+  csr_kernel<<<blocks(nnz + 1), 256, 0, st>>>(uniq.p, nnz, nout, ent.p, off.p);
+  succ->off.resize(nout + 1);
   succ->ent.resize(nnz);
-  GB_CHECK(hipMemcpyAsync(succ->off.data(), off.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
+  GB_CHECK(hipMemcpyAsync(succ->off.data(), off.p, sizeof(int64_t) * (nout + 1),
+                          hipMemcpyDeviceToHost, st));
   if (nnz > 0)
     GB_CHECK(hipMemcpyAsync(succ->ent.data(), ent.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
   GB_CHECK(hipStreamSynchronize(st));
@@ -881,6 +929,7 @@ extern "C" {
 mknn_status mknn_build_device(const float *xyz, int64_t n, const int32_t *order, void *stream,
                               mknn_cloud **out) {
   clear_error();
+  gbuild::g_last = gbuild::Stats{};   // stays zero when the host construction takes the call
   if (!out) return set_error(MKNN_EINVAL, "mknn_build_device: out is NULL");
   *out = nullptr;
   if (!xyz) return set_error(MKNN_EINVAL, "mknn_build_device: xyz is NULL");
@@ -916,12 +965,34 @@ mknn_status mknn_build_device(const float *xyz, int64_t n, const int32_t *order,
   } catch (const std::bad_alloc &) {
     return set_error(MKNN_ENOMEM, "mknn_build_device: out of host memory");
   }
-  if (n < 5 || orient3d(&P[0], &P[3], &P[6], &P[9]) == 0) return mknn_build(xyz, n, order, out);
+  if (n < 5) return mknn_build(xyz, n, order, out);
+  // the first four ranks coplanar: the host construction's plan of a start off the line and
+  // plane (A, B: ranks, or spare points appended after the real ones)
+  gbuild::LowDim low;
+  std::vector<double> Ppos;
+  const bool lowdim = orient3d(&P[0], &P[3], &P[6], &P[9]) == 0;
+  if (lowdim) {
+    std::vector<double> P2(P);
+    P2.resize(3 * (size_t)(n + 2));
+    int64_t bad = -1;
+    if (DelaunayBuilder::low_dim_plan(P2.data(), n, &low.A, &low.B, &bad) != kBuildOk)
+      return mknn_build(xyz, n, order, out);   // (ranks 0 and 1 coincide: its error)
+    low.nreal = n;
+    low.rank_of_pos = {0, 1, low.A, low.B};
+    for (int32_t r = 2; r < (int32_t)n; ++r)
+      if (r != low.A && r != low.B) low.rank_of_pos.push_back(r);
+    Ppos.resize(3 * low.rank_of_pos.size());
+    for (size_t q = 0; q < low.rank_of_pos.size(); ++q)
+      for (int k = 0; k < 3; ++k) Ppos[3 * q + k] = P2[3 * (size_t)low.rank_of_pos[q] + k];
+  }
+  const std::vector<double> &Pb = lowdim ? Ppos : P;
+  const int64_t nb = (int64_t)(Pb.size() / 3);
   // a site at the coordinates of one of the four start sites would never be met as a
   // repeat of a creating site (the start sites create nothing): check those here
-  for (int64_t r = 4; r < n; ++r)
+  for (int64_t r = 4; r < nb; ++r)
     for (int s = 0; s < 4; ++s)
-      if (P[3 * r] == P[3 * s] && P[3 * r + 1] == P[3 * s + 1] && P[3 * r + 2] == P[3 * s + 2]) {
+      if (Pb[3 * r] == Pb[3 * s] && Pb[3 * r + 1] == Pb[3 * s + 1] &&
+          Pb[3 * r + 2] == Pb[3 * s + 2]) {
         const int64_t first = gbuild::first_duplicate(P, n);
         return set_error(MKNN_EDUPLICATE, "mknn_build_device: point " +
                                               std::to_string(ord[first < 0 ? r : first]) +
@@ -933,7 +1004,7 @@ mknn_status mknn_build_device(const float *xyz, int64_t n, const int32_t *order,
     gbuild::Stats st;
     Csr succ;
     try {
-      gbuild::build_positions(P, n, (hipStream_t)stream, &succ, &st);
+      gbuild::build_positions(Pb, nb, (hipStream_t)stream, &succ, &st, lowdim ? &low : nullptr);
     } catch (int64_t) {
       // a repeated site was met; name the first rank (in insertion order) that repeats an
       // older one, as the host construction does

@@ -81,14 +81,46 @@ def test_device_lists_torus_1m(env):
     print(f"device build of 1M torus: {st}", flush=True)
 
 
-def test_device_build_coplanar_start(env):
-    """First four ranks coplanar: the device call takes the host construction."""
+def _low_dim_clouds():
+    rng = np.random.default_rng(13)
+    out = []
+    # first four ranks on a line (rank 3 between ranks 0 and 1), then a sphere
+    c = rng.standard_normal((3000, 3)).astype(np.float32)
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    c[3] = c[0] + np.float32(0.5) * (c[1] - c[0])
+    out.append(("line start", c))
+    # a fully planar cloud (every rank in z = 0): both start points are spares
+    g = rng.uniform(-1, 1, (4000, 2)).astype(np.float32)
+    out.append(("planar", np.concatenate([g, np.zeros((4000, 1), np.float32)], 1)))
+    # a plane for the first 500 ranks, then 3-D points: B is rank 500
+    pl = rng.uniform(-1, 1, (500, 2)).astype(np.float32)
+    sp = rng.uniform(-1, 1, (2500, 3)).astype(np.float32)
+    out.append(("plane then space", np.concatenate(
+        [np.concatenate([pl, np.zeros((500, 1), np.float32)], 1), sp], 0)))
+    # collinear for 100 ranks, then a plane, then space
+    t = np.sort(rng.uniform(-1, 1, 100)).astype(np.float32)[rng.permutation(100)]
+    line = np.stack([t, np.zeros(100, np.float32), np.zeros(100, np.float32)], 1)
+    pl2 = np.concatenate([rng.uniform(-1, 1, (400, 2)).astype(np.float32),
+                          np.zeros((400, 1), np.float32)], 1)
+    out.append(("line, plane, space", np.concatenate([line, pl2, sp[:1500]], 0)))
+    # an integer grid in one plane (cocircular ties everywhere)
+    gg = np.arange(30, dtype=np.float32)
+    grid = np.stack(np.meshgrid(gg, gg, indexing="ij"), -1).reshape(-1, 2)
+    grid = grid[rng.permutation(grid.shape[0])]
+    out.append(("planar grid", np.concatenate([grid, np.full((grid.shape[0], 1), 2.0, np.float32)], 1)))
+    return out
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_device_build_low_dimensional_start(env, case):
+    """First four ranks coplanar or collinear: the device construction starts from the first
+    ranks off the line and plane (or spare points), as the host construction does, and
+    records the same lists."""
     torch, A, W, _ = env
-    c = W.random_cloud(3000, 9, "sphere")
-    pts = c.by_rank.copy()
-    pts[3] = pts[0] + 0.5 * (pts[1] - pts[0]) + 0.25 * (pts[2] - pts[0])
-    pts[3] = pts[0] + np.float32(0.5) * (pts[1] - pts[0])   # on the line of ranks 0 and 1
-    _same_lists(A, pts)
+    name, pts = _low_dim_clouds()[case]
+    print(name, flush=True)
+    st, _ = _same_lists(A, pts)
+    assert st["rounds"] > 0, "the device path was not taken"
 
 
 @pytest.mark.parametrize("where", ["late", "start"])
