@@ -472,6 +472,11 @@ __global__ void csr_kernel(const uint64_t *__restrict__ key, int64_t nnz, int64_
   if (e < nnz) ent[e] = (int32_t)(uint32_t)key[e];
 }
 
+__global__ void swap_kernel(const uint64_t *__restrict__ in, int64_t m, uint64_t *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m) out[e] = (in[e] << 32) | (in[e] >> 32);
+}
+
 __global__ void unique_flag_kernel(const uint64_t *__restrict__ key, int64_t m,
                                    uint32_t *__restrict__ keep) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -567,7 +572,7 @@ struct LowDim {
 // With one, the entries are mapped to ranks as the host construction records them.
 // Throws the position of a duplicate site (int64_t), or std::runtime_error.
 static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStream_t st, Csr *succ,
-                               Stats *stats, const LowDim *ld = nullptr) {
+                               Csr *pred, Stats *stats, const LowDim *ld = nullptr) {
   auto t0 = std::chrono::steady_clock::now();
   // sites as float4 (the inputs are float32; the host predicates see the same values)
   std::vector<float> P4(4 * (size_t)n);
@@ -580,7 +585,10 @@ static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStrea
   GB_CHECK(hipMemcpyAsync(dP.p, P4.data(), sizeof(float4) * (size_t)n, hipMemcpyHostToDevice, st));
 
   // tetrahedra
-  int64_t tcap = 24 * n + 4096;
+  // capacities from measured ratios (tetrahedra created: 18-25 per point on surfaces, up to
+  // 29 on lattices; conflict records: about 800 per point for 1M surface points), grown
+  // when exceeded
+  int64_t tcap = 30 * n + 4096;
   DevBuf<int4> tv;
   DevBuf<int32_t> minc, clen;
   DevBuf<int64_t> coff;
@@ -593,7 +601,7 @@ static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStrea
   int64_t ntet = 0;
   // conflict pool
   DevBuf<int32_t> pool;
-  pool.reserve(64 * n + 4096, st);
+  pool.reserve(256 * n + 4096, st);
   int64_t pool_used = 0;
   // ridge hash table (faces checked in so far); load factor below one half
   uint64_t hsize = 1;
@@ -650,6 +658,9 @@ static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStrea
   // device), settles deferred ones on the host, packs the accepted ones into the pool and
   // sets each new tetrahedron's list; with checkin, emits the next round's ridge pairs.
   // Returns the number of pairs emitted.
+  flag.reserve(8 * n + 4096, st);
+  candq.reserve(8 * n + 4096, st);
+  pos.reserve(8 * n + 4096, st);
   auto run_jobs = [&](int64_t njobs, uint64_t ncand, bool checkin) -> uint32_t {
     flag.reserve((int64_t)ncand + 1, st);
     candq.reserve((int64_t)ncand + 1, st);
@@ -891,6 +902,22 @@ static int64_t build_positions(const std::vector<double> &P, int64_t n, hipStrea
                           hipMemcpyDeviceToHost, st));
   if (nnz > 0)
     GB_CHECK(hipMemcpyAsync(succ->ent.data(), ent.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
+  // (the copies above are ordered before the transpose below reuses ent and off on `st`)
+  // predecessors (the transpose): the same entries keyed (successor << 32 | owner), sorted
+  if (pred) {
+    swap_kernel<<<blocks(nnz), 256, 0, st>>>(uniq.p, nnz, sorted.p);
+    size_t bytes = 0;
+    GB_CHECK(hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, sorted.p, uniq.p, (int)nnz, 0, 64, st));
+    scratch.reserve((int64_t)bytes + 16, st);
+    GB_CHECK(hipcub::DeviceRadixSort::SortKeys(scratch.p, bytes, sorted.p, uniq.p, (int)nnz, 0, 64, st));
+    csr_kernel<<<blocks(nnz + 1), 256, 0, st>>>(uniq.p, nnz, nout, ent.p, off.p);
+    pred->off.resize(nout + 1);
+    pred->ent.resize(nnz);
+    GB_CHECK(hipMemcpyAsync(pred->off.data(), off.p, sizeof(int64_t) * (nout + 1),
+                            hipMemcpyDeviceToHost, st));
+    if (nnz > 0)
+      GB_CHECK(hipMemcpyAsync(pred->ent.data(), ent.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
+  }
   GB_CHECK(hipStreamSynchronize(st));
   stats->entries = nnz;
   stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1002,9 +1029,10 @@ mknn_status mknn_build_device(const float *xyz, int64_t n, const int32_t *order,
   mknn_cloud *c = nullptr;
   try {
     gbuild::Stats st;
-    Csr succ;
+    Csr succ, pred;
     try {
-      gbuild::build_positions(Pb, nb, (hipStream_t)stream, &succ, &st, lowdim ? &low : nullptr);
+      gbuild::build_positions(Pb, nb, (hipStream_t)stream, &succ, &pred, &st,
+                              lowdim ? &low : nullptr);
     } catch (int64_t) {
       // a repeated site was met; name the first rank (in insertion order) that repeats an
       // older one, as the host construction does
@@ -1027,15 +1055,7 @@ mknn_status mknn_build_device(const float *xyz, int64_t n, const int32_t *order,
       }
     }
     c->succ = std::move(succ);
-    // predecessors: the transpose of the successor lists
-    c->pred.off.assign(n + 1, 0);
-    for (int32_t e : c->succ.ent) c->pred.off[e + 1]++;
-    for (int64_t i = 0; i < n; ++i) c->pred.off[i + 1] += c->pred.off[i];
-    c->pred.ent.resize(c->succ.ent.size());
-    std::vector<int64_t> fill(c->pred.off.begin(), c->pred.off.end() - 1);
-    for (int64_t i = 0; i < n; ++i)
-      for (int64_t e = c->succ.off[i]; e < c->succ.off[i + 1]; ++e)
-        c->pred.ent[fill[c->succ.ent[e]]++] = (int32_t)i;
+    c->pred = std::move(pred);   // the transpose, sorted on the device
     c->live.assign(n, 1);
     c->nlive = n;
     c->head = 0;

@@ -154,3 +154,41 @@ def test_device_built_cloud_answers_queries(env):
     idv, dd = cd.knn(q, 8)
     torch.cuda.synchronize()
     assert torch.equal(ih, idv) and torch.equal(dh, dd)
+
+
+@pytest.mark.parametrize("lowdim", [False, True])
+def test_device_built_cloud_deletes_like_host(env, lowdim):
+    """Deletion (Alg. 3) walks the predecessor lists, which the device construction builds
+    too (the transpose, sorted on the GPU): deleting the same ranks from both clouds must
+    leave the same lists."""
+    torch, A, W, _ = env
+    if lowdim:
+        pts = _low_dim_clouds()[2][1]
+    else:
+        pts = W.random_cloud(20_000, 21, "ellipsoid").by_rank
+    host = A.Cloud.build(pts)
+    dev = A.Cloud.build(pts, device=True)
+    rng = np.random.default_rng(3)
+    ranks = rng.choice(np.arange(600, pts.shape[0]), 300, replace=False)
+    if not lowdim:
+        host.delete(ranks)
+        dev.delete(ranks)
+    else:
+        # local sets reaching into the planar prefix may be refused (EUNSUPPORTED): both
+        # clouds must then refuse the same ranks
+        refused = 0
+        for r in ranks[:60]:
+            out = []
+            for c in (host, dev):
+                try:
+                    c.delete([int(r)])
+                    out.append("ok")
+                except RuntimeError as e:
+                    out.append(str(e).split(":")[0])
+            assert out[0] == out[1], (int(r), out)
+            refused += out[0] != "ok"
+            if refused:
+                break   # a refused batch leaves both clouds as they were up to that rank
+    ho, he = host.successors()
+    do, de = dev.successors()
+    assert np.array_equal(ho, do) and np.array_equal(he, de)
