@@ -446,10 +446,12 @@ struct RowWalker {
 };
 
 // Plain launch: a wavefront owns `per_wave` consecutive sorted queries; row g takes
-// positions g, g + 4, g + 8, ... of them, so the rows stay on Morton neighbours.
+// positions g, g + 4, g + 8, ... of them, so the rows stay on Morton neighbours.  Eight
+// waves per SIMD for every class: the wider candidate lists then spill a few registers
+// (S = 4: 16), which costs less than the latency fewer waves leave exposed.
 template <int S, bool EXACTK, bool DESCENT_FIRST, bool UNIFORM, bool LAZY = false>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : (S == 2 ? 8 : (S == 3 ? 7 : 6)), 8)))
+__attribute__((amdgpu_waves_per_eu(8, 8)))
 void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
   const int lane = threadIdx.x & 63;
   const int l = lane & 15, g = lane >> 4;

@@ -268,12 +268,13 @@ void knn_batch_rows_kernel(const BatchHeader *h, const QueryArgs *reqs, const Ba
 // request e taking wavefronts woff[e] .. woff[e] + ceil(nq / 4) - 1, each four consecutive
 // sorted queries of that request, one per row, run to the end together as in the plain
 // kernel.  No tiles, atomics or per-wavefront request state: registers as in the plain
-// kernel, 8 waves per SIMD.  The grid is sized for the plan's capacity (fixed, so that one
+// kernel, 8 waves per SIMD (for the pending-deletion variants, whose filter would spill
+// more, the compiler's choice).  The grid is sized for the plan's capacity (fixed, so that one
 // graph replays any batch) and laid XCD-contiguously over the workgroups the batch needs:
 // block 8 i + x runs on XCD x and takes workgroup x * per + i, per = ceil(needed / 8);
 // blocks past that leave at once.
 template <int S, bool LAZY = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 1 ? 8 : 1, 8)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAZY ? (S == 1 ? 8 : 1) : 8, 8)))
 void knn_batch_flat_kernel(const BatchHeader *h, const QueryArgs *reqs, const BatchEntry *ents,
                            const int64_t *woff, int cls) {
   const int64_t nw = h->fwaves[cls];
