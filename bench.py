@@ -239,6 +239,39 @@ def memory_probes() -> dict:
             "buffer_bytes": nbytes}
 
 
+def layout_probe(cl, q, idx, dist, records_ms: float, reps: int, k: int):
+    """The same k=16 walk over a ranks-only copy of the lists (a 4-byte rank per entry, the
+    point gathered by rank) beside the record layout (coordinates inlined in 16-byte
+    records): kernel time of each, and whether the rows are bit-identical."""
+    import ctypes
+    import torch
+    from paper_2605_02224_amd import _lib
+    if k != 16:
+        return None
+    lib = _lib.lib()
+    gi = torch.empty_like(idx)
+    gd = torch.empty_like(dist)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    args = (cl.handle, ctypes.c_void_p(q.data_ptr()), q.shape[0], ctypes.c_void_p(gi.data_ptr()),
+            ctypes.c_void_p(gd.data_ptr()), st)
+    for _ in range(2):
+        _lib.check(lib.mknn_knn_gather_layout(*args))
+    torch.cuda.synchronize()
+    tot = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    lib.mknn_timing_enable(1)
+    lib.mknn_timing_read(ctypes.byref(tot), ctypes.byref(cnt))   # reset
+    for _ in range(max(3, reps // 4)):
+        _lib.check(lib.mknn_knn_gather_layout(*args))
+    torch.cuda.synchronize()
+    _lib.check(lib.mknn_timing_read(ctypes.byref(tot), ctypes.byref(cnt)))
+    lib.mknn_timing_enable(0)
+    gms = tot.value / max(cnt.value, 1)
+    return {"records_kernel_ms": round(records_ms, 4), "ranks_gather_kernel_ms": round(gms, 4),
+            "slowdown": round(gms / records_ms, 3),
+            "rows_equal": bool(torch.equal(gi, idx) and torch.equal(gd, dist))}
+
+
 def build_clouds(clouds, threads: int = 16):
     """Build and upload many clouds: the lists are built on the GPU one cloud after the
     other (the same lists as the host construction, which the GPU tests check)."""
@@ -880,6 +913,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the context measurements")
+    ap.add_argument("--layout-probe", action="store_true",
+                    help="time the ranks-only layout beside the record layout even with --no-extras")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and serving forms (child process)")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in configuration")
@@ -1045,6 +1080,9 @@ def _main(args, child) -> int:
             cl.knn(qq, kk, out=(i2, d2))
         torch.cuda.synchronize()
         extras[name + "_qps"] = round(nq * reps / (time.perf_counter() - t0), 1)
+    if not args.no_extras or args.layout_probe:
+        extras["layout_probe"] = layout_probe(cl, q, idx, dist, kern_ms, args.steps, k)
+        log(f"layout probe: {extras['layout_probe']}")
     if not args.no_extras:
         probe = memory_probes()
         probe["frac_of_stream_read"] = round(achieved / probe["stream_read_GBps"], 4)

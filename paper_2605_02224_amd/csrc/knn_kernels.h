@@ -47,6 +47,11 @@ struct QueryArgs {
   uint32_t epoch;
   int32_t kout;
   uint32_t *overflow;
+  // The ranks-only layout, for the measurement that compares it with the records above:
+  // rk[i] is the rank of record i, pts[r] the point of rank r (only the gather kernel reads
+  // these).
+  const int32_t *rk = nullptr;
+  const float4 *pts = nullptr;
 };
 
 // Extra neighbours a walk collects per query while deletions are pending.

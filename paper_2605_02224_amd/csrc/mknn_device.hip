@@ -217,6 +217,13 @@ __global__ __launch_bounds__(256) void morton_hist_kernel(const float *q, int64_
   rank[i] = atomicAdd(&hist[morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], b) >> (30 - kMortonBits)], 1u);
 }
 
+// The rank of every record of the arena (the ranks-only layout of the layout measurement).
+__global__ __launch_bounds__(256) void record_ranks_kernel(const float4 *ent, int64_t nrec,
+                                                           int32_t *rk) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nrec) rk[i] = __float_as_int(ent[i].w);
+}
+
 // exclusive scan of kMortonBins counters by one workgroup of 1024 threads
 __global__ __launch_bounds__(1024) void scan_bins_kernel(uint32_t *hist) {
   constexpr int per = kMortonBins / 1024;
@@ -1028,6 +1035,62 @@ mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t 
     return run_query(c, d_q, nq, kw, m, nullptr, nullptr, nullptr, kw, d_idx, d_dist, nullptr,
                      nullptr, nullptr, s, "mknn_knn", nullptr, nullptr, nullptr, lz);
   });
+}
+
+mknn_status mknn_knn_gather_layout(const mknn_cloud *c, const float *d_q, int64_t nq,
+                                   int32_t *d_idx, float *d_dist, void *stream) {
+  clear_error();
+  if (nq < 0 || nq > 0x7fffffffll)
+    return set_error(MKNN_EINVAL, "mknn_knn_gather_layout: nq out of range");
+  mknn_status st = check_uploaded(c, "mknn_knn_gather_layout");
+  if (st != MKNN_OK) return st;
+  if (nq == 0) return MKNN_OK;
+  if (!d_q || !d_idx || !d_dist)
+    return set_error(MKNN_EINVAL, "mknn_knn_gather_layout: NULL buffer");
+  if (c->dev_lazy.load() != 0)
+    return set_error(MKNN_EUNSUPPORTED, "mknn_knn_gather_layout: the cloud has pending deletions");
+  hipStream_t s = (hipStream_t)stream;
+  // the ranks-only arena: the rank of every record, padding included
+  const int64_t nrec = c->ent_cap + kEntPad;
+  int32_t *rk = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&rk, sizeof(int32_t) * (size_t)nrec, s),
+          "mknn_knn_gather_layout: rank array");
+  hipLaunchKernelGGL(record_ranks_kernel, dim3((uint32_t)((nrec + 255) / 256)), dim3(256), 0, s,
+                     (const float4 *)c->d_ent, nrec, rk);
+  QueryArgs a;
+  fill_cloud_args(c, &a);
+  a.q = d_q;
+  a.nq = nq;
+  a.k = 16;
+  a.m = (int32_t)c->dev_n;
+  a.kq = a.mq = nullptr;
+  a.row_off = nullptr;
+  a.out_idx = d_idx;
+  a.out_dist = d_dist;
+  a.cnt_entries = a.cnt_lists = a.cnt_inserts = nullptr;
+  a.rk = rk;
+  a.pts = (const float4 *)c->d_pts;
+  void *scratch = nullptr;
+  float4 *qs = nullptr;
+  st = prepare_queries(c, d_q, nq, s, &qs, &scratch);
+  if (st != MKNN_OK) {
+    (void)hipFreeAsync(rk, s);
+    return st;
+  }
+  a.qs = qs;
+  a.merge_min = config_for(16, true, c->dev_n).merge_min;
+  hipError_t e = timing_mark(s, true);
+  const int64_t waves = (nq + 3) / 4;
+  if (e == hipSuccess)
+    hipLaunchKernelGGL(knn_rows_gather_kernel<1>, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s,
+                       a, (int32_t)4);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = timing_mark(s, false);
+  if (scratch) (void)hipFreeAsync(scratch, s);
+  (void)hipFreeAsync(rk, s);
+  if (e != hipSuccess)
+    return set_error(MKNN_EHIP, std::string("mknn_knn_gather_layout: ") + hipGetErrorName(e));
+  return MKNN_OK;
 }
 
 mknn_status mknn_knn_static(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,

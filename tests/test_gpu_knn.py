@@ -289,3 +289,27 @@ def test_low_dimensional_clouds(env):
         Q[:3000, 2] = 0.0
         for k, m in ((1, None), (8, None), (16, 300), (33, None)):
             assert _run(env, cl, P, Q, k, m) <= 2
+
+
+def test_ranks_only_layout_gives_the_same_rows():
+    """mknn_knn_gather_layout (the ranks-only layout kept for the layout measurement) walks
+    the same lists: its rows equal mknn_knn's bit for bit."""
+    import ctypes
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_02224_amd import _lib
+    from paper_2605_02224_amd import workloads as W
+    from paper_2605_02224_amd.api import Cloud
+    w = W.torus_paper_scale(n=100_000, nq=30_000, k=16)
+    cl = Cloud.build(w.cloud.points, w.cloud.order).upload()
+    q = torch.from_numpy(w.queries).cuda()
+    i1, d1 = cl.knn(q, 16)
+    i2 = torch.empty_like(i1)
+    d2 = torch.empty_like(d1)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _lib.check(_lib.lib().mknn_knn_gather_layout(cl.handle, ctypes.c_void_p(q.data_ptr()),
+                                                 q.shape[0], ctypes.c_void_p(i2.data_ptr()),
+                                                 ctypes.c_void_p(d2.data_ptr()), st))
+    torch.cuda.synchronize()
+    assert torch.equal(i1, i2) and torch.equal(d1, d2)
