@@ -7,9 +7,9 @@
 // round trip per list instead of one per entry, and no divergence between entries of a
 // list.  The candidate list N (Alg. 2) is spread across the row: lane l holds positions
 // S l .. S l + S - 1 (S slots per lane, k <= 16 S).  Inserting a candidate is a row-wide
-// compare, a population count for its position and a one-position shift: inside each lane,
-// plus one DPP row move of the lane's last slot into the next lane; only candidates that
-// beat the current k-th key are inserted.
+// compare and a one-position shift, each lane deciding from its own comparisons: inside the
+// lane, plus one DPP row move of the lane's last slot into the next lane; only candidates
+// that beat the current k-th key are inserted.
 //
 // Descent and seeding (Alg. 1): when a chunk of L_cur holds an entry closer than the current
 // site, only that transition site is offered to N and the walk jumps; a chunk without such
@@ -213,22 +213,25 @@ struct RowTopK {
 #pragma unroll
     for (int s = 0; s < S; ++s) has |= (r[s] == cr);
     if (row_bits(__ballot(has), g)) return false;
-    int pos = 0;
+    // Every lane decides from its own comparisons: a position whose key is below the
+    // candidate keeps it; the first one that is not (its predecessor is below, or it is
+    // position 0) takes the candidate; every later one takes its predecessor's key.  The
+    // predecessor of slot 0 is the last slot of lane l - 1 (DPP row_shr:1); lane 0 reads 0
+    // there (no source lane), which stands for "below".
+    bool lt[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-      pos += __popc(row_bits(__ballot(key_less(d[s], r[s], cd, cr)), g));
-    // position S l + s takes position S l + s - 1 when it lies after the insertion point:
-    // slot s - 1 of the same lane, or, for slot 0, the last slot of lane l - 1 (DPP
-    // row_shr:1; lane 0's slot 0 is position 0, never after the insertion point)
+    for (int s = 0; s < S; ++s) lt[s] = key_less(d[s], r[s], cd, cr);
+    const int32_t prev_above =
+        __builtin_amdgcn_update_dpp(0, lt[S - 1] ? 0 : 1, kDppRowShr1, 0xf, 0xf, true);
     const double pd = dpp_f64<kDppRowShr1>(d[S - 1], d[S - 1]);
     const int32_t pr = dpp_i32<kDppRowShr1>(r[S - 1], r[S - 1]);
 #pragma unroll
     for (int s = S - 1; s >= 0; --s) {
-      const int j = S * l + s;
+      const bool prev_lt = s > 0 ? lt[s > 0 ? s - 1 : 0] : prev_above == 0;
       const double prevd = s > 0 ? d[s > 0 ? s - 1 : 0] : pd;
       const int32_t prevr = s > 0 ? r[s > 0 ? s - 1 : 0] : pr;
-      d[s] = j > pos ? prevd : (j == pos ? cd : d[s]);
-      r[s] = j > pos ? prevr : (j == pos ? cr : r[s]);
+      d[s] = lt[s] ? d[s] : (prev_lt ? cd : prevd);
+      r[s] = lt[s] ? r[s] : (prev_lt ? cr : prevr);
     }
     return true;
   }
