@@ -10,6 +10,12 @@ from . import _lib
 from ._lib import check
 
 
+
+def _library_alive() -> bool:
+    """False while the interpreter tears modules down: a handle collected then is left to
+    the process exit instead of being freed through a half-cleared module."""
+    return _lib is not None and callable(getattr(_lib, "lib", None))
+
 def _ptr(t) -> ctypes.c_void_p:
     if t is None:
         return None
@@ -49,7 +55,8 @@ class Cloud:
         return cls(h)
 
     def __del__(self):
-        self.close()
+        if _library_alive():
+            self.close()
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -296,7 +303,8 @@ class BatchPlan:
             self._h = None
 
     def __del__(self):
-        self.close()
+        if _library_alive():
+            self.close()
 
 
 def batch_knn(items, stream=None):
@@ -384,7 +392,8 @@ class Server:
             self._h = None
 
     def __del__(self):
-        self.close()
+        if _library_alive():
+            self.close()
 
 
 def build_device_stats() -> dict:
