@@ -185,16 +185,16 @@ struct RowTopK {
 
   // position j (row-uniform) broadcast to the row: slot j % S of lane j / S
   __device__ __forceinline__ void slot(int j, double &od, int32_t &orr) const {
-    const int s = j % S, src = j / S;
+    const uint32_t s = (uint32_t)j % S, src = (uint32_t)j / S;
     double vd = d[0];
     int32_t vr = r[0];
 #pragma unroll
     for (int t = 1; t < S; ++t) {
-      vd = (t == s) ? d[t] : vd;
-      vr = (t == s) ? r[t] : vr;
+      vd = ((uint32_t)t == s) ? d[t] : vd;
+      vr = ((uint32_t)t == s) ? r[t] : vr;
     }
-    od = __shfl(vd, src, 16);
-    orr = __shfl(vr, src, 16);
+    od = __shfl(vd, (int)src, 16);
+    orr = __shfl(vr, (int)src, 16);
   }
 
   // Insert the row-uniform candidate (cd, cr) unless already present.  Only called for a
@@ -290,7 +290,8 @@ struct RowTopK {
     constexpr int TOP = S == 2 ? 32 : 64;   // a power of two >= L / 2 (S = 2, 3, 4)
     // position p is stored at (p mod S) 16 + p / S: each slot's 16 positions are contiguous,
     // so staging and reading back a lane's slots are free of bank conflicts
-    auto at = [](int p) { return (p % S) * 16 + p / S; };
+    // (unsigned: S = 2 and 4 then take a mask and a shift, S = 3 a multiply-high)
+    auto at = [](uint32_t p) { return (p % S) * 16u + p / S; };
     RowLds<S> &lds = row_lds<S>();
     double *s_nd = lds.merge.nd;
     int32_t *s_nr = lds.merge.nr;
@@ -306,7 +307,7 @@ struct RowTopK {
     }
     wave_lds_sync();
     // keys of N below the candidate (binary lifting over the sorted L keys)
-    int p = 0;
+    uint32_t p = 0;
 #pragma unroll
     for (int step = TOP; step > 0; step >>= 1)
       if (p + step <= L &&
@@ -315,8 +316,8 @@ struct RowTopK {
     const bool real = cr != kEmpty;
     const bool held = real && p < L && s_nr[at(p < L ? p : 0)] == cr;
     const bool kept = real && !held;
-    const int jk = __popc(row_bits(__ballot(kept), g) & ((1u << l) - 1u));
-    if (kept && p < L) atomicMax(&s_m[at(p)], (uint32_t)(jk + 1));
+    const uint32_t jk = __popc(row_bits(__ballot(kept), g) & ((1u << l) - 1u));
+    if (kept && p < L) atomicMax(&s_m[at(p)], jk + 1u);
     wave_lds_sync();
     // kept candidates below each key: running maximum within the lane, then the maximum
     // over the lanes below (inclusive scan by DPP row_shr, shifted by one lane)
@@ -339,7 +340,7 @@ struct RowTopK {
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int np = S * l + s + (int)max(lower, below[s]);
+      const uint32_t np = (uint32_t)(S * l + s) + max(lower, below[s]);
       if (np < L) {
         s_nd[at(np)] = d[s];
         s_nr[at(np)] = r[s];

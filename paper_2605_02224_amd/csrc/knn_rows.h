@@ -374,8 +374,8 @@ struct RowWalker {
       dcur = __shfl(dv, j, 16);
       cur = __shfl(r, j, 16);
       if (l == (ntrans & 15)) {
-        ring_d<S>()[ntrans % (16 * S)] = dcur;
-        ring_r<S>()[ntrans % (16 * S)] = cur;
+        ring_d<S>()[(uint32_t)ntrans % (16u * S)] = dcur;
+        ring_r<S>()[(uint32_t)ntrans % (16u * S)] = cur;
       }
       ++ntrans;
       dsc = lst[cur];
@@ -401,7 +401,7 @@ struct RowWalker {
 #pragma unroll
     for (int t = 0; t < S; ++t) {
       const int pos = S * l + t;
-      const int src = pos < have ? (ntrans - 1 - pos) % R : 0;
+      const int src = pos < have ? (int)((uint32_t)(ntrans - 1 - pos) % (uint32_t)R) : 0;
       N.d[t] = pos < have ? ring_d<S>()[src] : INFINITY;
       N.r[t] = pos < have ? ring_r<S>()[src] : kEmpty;
     }
