@@ -239,37 +239,47 @@ def memory_probes() -> dict:
             "buffer_bytes": nbytes}
 
 
+LAYOUTS = {"ranks": 1, "arrays": 2}   # MKNN_LAYOUT_RANKS, MKNN_LAYOUT_ARRAYS
+
+
 def layout_probe(cl, q, idx, dist, records_ms: float, reps: int, k: int):
-    """The same k=16 walk over a ranks-only copy of the lists (a 4-byte rank per entry, the
-    point gathered by rank) beside the record layout (coordinates inlined in 16-byte
-    records): kernel time of each, and whether the rows are bit-identical."""
+    """The same k=16 walk over two other layouts of the lists beside the record layout
+    (coordinates inlined in 16-byte records): ranks only (a 4-byte rank per entry, the point
+    gathered by rank) and four arrays (rank, x, y, z, 4 bytes each): kernel time of each, and
+    whether the rows are bit-identical to the records' rows."""
     import ctypes
     import torch
     from paper_2605_02224_amd import _lib
     if k != 16:
         return None
     lib = _lib.lib()
-    gi = torch.empty_like(idx)
-    gd = torch.empty_like(dist)
-    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    args = (cl.handle, ctypes.c_void_p(q.data_ptr()), q.shape[0], ctypes.c_void_p(gi.data_ptr()),
-            ctypes.c_void_p(gd.data_ptr()), st)
-    for _ in range(2):
-        _lib.check(lib.mknn_knn_gather_layout(*args))
-    torch.cuda.synchronize()
-    tot = ctypes.c_double()
-    cnt = ctypes.c_int64()
-    lib.mknn_timing_enable(1)
-    lib.mknn_timing_read(ctypes.byref(tot), ctypes.byref(cnt))   # reset
-    for _ in range(max(3, reps // 4)):
-        _lib.check(lib.mknn_knn_gather_layout(*args))
-    torch.cuda.synchronize()
-    _lib.check(lib.mknn_timing_read(ctypes.byref(tot), ctypes.byref(cnt)))
-    lib.mknn_timing_enable(0)
-    gms = tot.value / max(cnt.value, 1)
-    return {"records_kernel_ms": round(records_ms, 4), "ranks_gather_kernel_ms": round(gms, 4),
-            "slowdown": round(gms / records_ms, 3),
-            "rows_equal": bool(torch.equal(gi, idx) and torch.equal(gd, dist))}
+    out = {"records_kernel_ms": round(records_ms, 4)}
+    equal = True
+    for name, layout in LAYOUTS.items():
+        gi = torch.empty_like(idx)
+        gd = torch.empty_like(dist)
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        args = (cl.handle, layout, ctypes.c_void_p(q.data_ptr()), q.shape[0],
+                ctypes.c_void_p(gi.data_ptr()), ctypes.c_void_p(gd.data_ptr()), st)
+        for _ in range(2):
+            _lib.check(lib.mknn_knn_layout(*args))
+        torch.cuda.synchronize()
+        tot = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        lib.mknn_timing_enable(1)
+        lib.mknn_timing_read(ctypes.byref(tot), ctypes.byref(cnt))   # reset
+        for _ in range(max(3, reps // 4)):
+            _lib.check(lib.mknn_knn_layout(*args))
+        torch.cuda.synchronize()
+        _lib.check(lib.mknn_timing_read(ctypes.byref(tot), ctypes.byref(cnt)))
+        lib.mknn_timing_enable(0)
+        ms = tot.value / max(cnt.value, 1)
+        out[name + "_kernel_ms"] = round(ms, 4)
+        out[name + "_slowdown"] = round(ms / records_ms, 3)
+        equal = equal and bool(torch.equal(gi, idx) and torch.equal(gd, dist))
+        del gi, gd
+    out["rows_equal"] = equal
+    return out
 
 
 def build_clouds(clouds, threads: int = 16):
@@ -914,7 +924,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the context measurements")
     ap.add_argument("--layout-probe", action="store_true",
-                    help="time the ranks-only layout beside the record layout even with --no-extras")
+                    help="time the other list layouts beside the records even with --no-extras")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and serving forms (child process)")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in configuration")

@@ -163,15 +163,20 @@ mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t 
 mknn_status mknn_knn_static(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t k,
                             int32_t m, int32_t *d_idx, float *d_dist, void *stream);
 
-/* mknn_knn_gather_layout: mknn_knn with k = 16 and m = n over a ranks-only copy of the
- * lists, for callers that measure the device layout (Sec. 3's successor table is kept
- * as records that inline each entry's coordinates; this call reads instead a 4-byte rank
- * per entry and then gathers the point by rank).  Same rows as mknn_knn, bit for bit; the
- * query kernel is timed by mknn_timing_* like mknn_knn's.  The rank array (4 bytes per
- * record) is built and freed on `stream` in the call.
- * Errors: as mknn_knn; EUNSUPPORTED while deletions are pending (mknn_delete_lazy). */
-mknn_status mknn_knn_gather_layout(const mknn_cloud *c, const float *d_q, int64_t nq,
-                                   int32_t *d_idx, float *d_dist, void *stream);
+/* mknn_knn_layout: mknn_knn with k = 16 and m = n over another layout of the same lists,
+ * for callers that measure the device layout (Sec. 3's successor table is kept as 16-byte
+ * records {x, y, z, rank} that inline each entry's coordinates):
+ *   MKNN_LAYOUT_RANKS   a 4-byte rank per entry, the point then gathered by rank;
+ *   MKNN_LAYOUT_ARRAYS  four arrays of 4-byte values per entry: rank, x, y, z.
+ * Same rows as mknn_knn, bit for bit; the query kernel is timed by mknn_timing_* like
+ * mknn_knn's.  The arrays (4 or 16 bytes per record) are built from the records and freed
+ * on `stream` in the call.
+ * Errors: as mknn_knn; EINVAL for another layout; EUNSUPPORTED while deletions are pending
+ * (mknn_delete_lazy). */
+#define MKNN_LAYOUT_RANKS 1
+#define MKNN_LAYOUT_ARRAYS 2
+mknn_status mknn_knn_layout(const mknn_cloud *c, int32_t layout, const float *d_q, int64_t nq,
+                            int32_t *d_idx, float *d_dist, void *stream);
 
 /* mknn_knn_var: per-query k and prefix m with ragged output rows.
  *   d_k        device int32 [nq], each in [1, MKNN_KMAX]

@@ -30,7 +30,7 @@ SIGNATURES = {
     "mknn_device_bytes": (_I64, [_P]),
     "mknn_knn": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P]),
     "mknn_knn_static": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P]),
-    "mknn_knn_gather_layout": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),
+    "mknn_knn_layout": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, _P, _P, _P]),
     "mknn_knn_plane": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P, _P]),
     "mknn_knn_var": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P]),
     "mknn_knn_counts": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _P, _P]),

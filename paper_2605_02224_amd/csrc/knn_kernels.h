@@ -47,12 +47,17 @@ struct QueryArgs {
   uint32_t epoch;
   int32_t kout;
   uint32_t *overflow;
-  // The ranks-only layout, for the measurement that compares it with the records above:
-  // rk[i] is the rank of record i, pts[r] the point of rank r (only the gather kernel reads
-  // these).
+  // Other layouts of the same lists, for the measurement that compares them with the
+  // records above (only the layout kernel reads these): rk[i] is the rank of record i;
+  // ranks only: pts[r] is the point of rank r; four arrays: sx, sy, sz[i] are the
+  // coordinates of record i.
   const int32_t *rk = nullptr;
   const float4 *pts = nullptr;
+  const float *sx = nullptr, *sy = nullptr, *sz = nullptr;
 };
+
+// List layouts of the layout measurement (the query launches use kLayoutRecords).
+constexpr int kLayoutRecords = 0, kLayoutRanks = 1, kLayoutArrays = 2;
 
 // Extra neighbours a walk collects per query while deletions are pending.
 constexpr int32_t kLazyMargin = 16;

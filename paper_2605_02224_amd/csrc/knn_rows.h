@@ -67,22 +67,27 @@ __device__ __forceinline__ int32_t *ring_r() {
 }
 
 // Entry idx of a list: the record {x, y, z, rank} (the layout of every query launch), or,
-// GATHER (the measurement of the layout choice only), its rank from the ranks-only array
-// and then the point from the rank-indexed point array, a dependent 16-byte gather.
+// for the measurement of the layout choice only: kLayoutRanks, its rank from the ranks-only
+// array and then the point from the rank-indexed point array, a dependent 16-byte gather;
+// kLayoutArrays, its rank and its three coordinates from four arrays of 4-byte values.
 // in_list: the lane's entry lies inside the list (the padding past a list holds no rank).
-template <bool GATHER>
+template <int LAYOUT>
 __device__ __forceinline__ float4 load_entry(const QueryArgs &a, const float4 *ent, uint32_t idx,
                                              bool in_list) {
-  if constexpr (!GATHER) {
+  if constexpr (LAYOUT == kLayoutRecords) {
     (void)a;
     (void)in_list;
     return ent[idx];
-  } else {
+  } else if constexpr (LAYOUT == kLayoutRanks) {
     (void)ent;
     const int32_t r = a.rk[idx];
     float4 p = a.pts[in_list ? r : 0];
     p.w = __int_as_float(in_list ? r : kEmpty);
     return p;
+  } else {
+    (void)ent;
+    (void)in_list;
+    return make_float4(a.sx[idx], a.sy[idx], a.sz[idx], __int_as_float(a.rk[idx]));
   }
 }
 
@@ -93,7 +98,7 @@ __device__ __forceinline__ float4 load_entry(const QueryArgs &a, const float4 *e
 // launch may filter pending deletions (QueryArgs::dead); kept out of the other launches,
 // whose registers (and so occupancy) the filter would cost.
 template <int S, bool EXACTK, bool WIDE_Q = (S == 1), bool UNIFORM = EXACTK, bool LAZY = false,
-          bool GATHER = false>
+          int LAYOUT = kLayoutRecords>
 struct RowWalker {
   RowTopK<S, EXACTK> N;
   using QCoord = typename std::conditional<WIDE_Q, double, float>::type;
@@ -267,7 +272,7 @@ struct RowWalker {
     // the end of a list (or of the arena's used part), which the arena's padding covers;
     // records past the list are ignored.  An idle row's descriptor is 0 (begin and finish
     // reset it), so it never points into another request's arena in the batched form.
-    const float4 c = load_entry<GATHER>(a, ent, st + e, e < len);
+    const float4 c = load_entry<LAYOUT>(a, ent, st + e, e < len);
     const int32_t r = __float_as_int(c.w);
     const bool valid = active && e < len && r < m;
     const double dx = (double)qx - (double)c.x, dy = (double)qy - (double)c.y,
@@ -360,7 +365,7 @@ struct RowWalker {
     const bool desc = phase == kRowDescent;
     const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
     const uint32_t e = base + (uint32_t)l;
-    const float4 c = load_entry<GATHER>(a, ent, st + e, e < len);   // in bounds for every lane: see step()
+    const float4 c = load_entry<LAYOUT>(a, ent, st + e, e < len);   // in bounds for every lane: see step()
     const int32_t r = __float_as_int(c.w);
     const bool valid = desc && e < len && r < m;
     const double dx = (double)qx - (double)c.x, dy = (double)qy - (double)c.y,
@@ -430,7 +435,7 @@ struct RowWalker {
     const bool act = phase != kRowIdle;
     const uint32_t st = (uint32_t)dsc, len = (uint32_t)(dsc >> 32);
     const uint32_t e = base + (uint32_t)l;
-    const float4 c = load_entry<GATHER>(a, ent, st + e, e < len);
+    const float4 c = load_entry<LAYOUT>(a, ent, st + e, e < len);
     const int32_t r = __float_as_int(c.w);
     const bool valid = act && e < len && r < m;
     const double dx = (double)qx - (double)c.x, dy = (double)qy - (double)c.y,
@@ -504,20 +509,20 @@ void knn_rows_kernel(QueryArgs a, int32_t per_wave) {
   }
 }
 
-// The row kernel over the ranks-only layout (k == 16, one k and m per launch, descent steps
-// first): the measurement that shows what inlining the coordinates in the list records
-// saves.  Same walk and results as knn_rows_kernel<1, true, true, true>.
-template <int S = 1>
+// The row kernel over another layout of the lists (k == 16, one k and m per launch, descent
+// steps first): the measurement of what the records' layout saves.  Same walk and results as
+// knn_rows_kernel<1, true, true, true>.
+template <int LAYOUT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
-void knn_rows_gather_kernel(QueryArgs a, int32_t per_wave) {
-  static_assert(S == 1, "the layout measurement runs the k == 16 class");
+void knn_rows_layout_kernel(QueryArgs a, int32_t per_wave) {
+  static_assert(LAYOUT == kLayoutRanks || LAYOUT == kLayoutArrays, "a layout to measure");
   const int lane = threadIdx.x & 63;
   const int l = lane & 15, g = lane >> 4;
   const int64_t wave =
       ((int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t begin = wave * per_wave;
   const int64_t end = begin + per_wave < a.nq ? begin + per_wave : a.nq;
-  RowWalker<1, true, true, true, false, true> w;
+  RowWalker<1, true, true, true, false, LAYOUT> w;
   w.N.init();
   const int32_t m = (int32_t)(a.m < a.n ? (int64_t)a.m : a.n);
   if (begin + g < end) w.begin(a, begin + g, l);

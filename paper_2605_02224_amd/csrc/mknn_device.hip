@@ -217,11 +217,20 @@ __global__ __launch_bounds__(256) void morton_hist_kernel(const float *q, int64_
   rank[i] = atomicAdd(&hist[morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], b) >> (30 - kMortonBits)], 1u);
 }
 
-// The rank of every record of the arena (the ranks-only layout of the layout measurement).
-__global__ __launch_bounds__(256) void record_ranks_kernel(const float4 *ent, int64_t nrec,
-                                                           int32_t *rk) {
+// The records of the arena split for the layout measurement: the rank of every record, and,
+// when x is given, its coordinates into three arrays.
+__global__ __launch_bounds__(256) void split_records_kernel(const float4 *ent, int64_t nrec,
+                                                            int32_t *rk, float *x, float *y,
+                                                            float *z) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nrec) rk[i] = __float_as_int(ent[i].w);
+  if (i >= nrec) return;
+  const float4 e = ent[i];
+  rk[i] = __float_as_int(e.w);
+  if (x) {
+    x[i] = e.x;
+    y[i] = e.y;
+    z[i] = e.z;
+  }
 }
 
 // exclusive scan of kMortonBins counters by one workgroup of 1024 threads
@@ -557,7 +566,7 @@ static long env_long(const char *name, long dflt) {
 // Defaults measured on the 1M torus: scheduled rows, one query per row, and the merge
 // network from 6 / 8 / 8 / 8 candidates per chunk for S = 1..4 slots per lane.
 static TuneConfig default_config(int S) {
-  static const int32_t mm[4] = {6, 8, 8, 8};
+  static const int32_t mm[4] = {8, 8, 8, 8};
   return {3, mm[(S < 1 ? 1 : S > 4 ? 4 : S) - 1], 4};
 }
 
@@ -1037,26 +1046,35 @@ mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t 
   });
 }
 
-mknn_status mknn_knn_gather_layout(const mknn_cloud *c, const float *d_q, int64_t nq,
-                                   int32_t *d_idx, float *d_dist, void *stream) {
+mknn_status mknn_knn_layout(const mknn_cloud *c, int32_t layout, const float *d_q, int64_t nq,
+                            int32_t *d_idx, float *d_dist, void *stream) {
   clear_error();
+  if (layout != MKNN_LAYOUT_RANKS && layout != MKNN_LAYOUT_ARRAYS)
+    return set_error(MKNN_EINVAL, "mknn_knn_layout: layout must be MKNN_LAYOUT_RANKS or "
+                                  "MKNN_LAYOUT_ARRAYS");
   if (nq < 0 || nq > 0x7fffffffll)
-    return set_error(MKNN_EINVAL, "mknn_knn_gather_layout: nq out of range");
-  mknn_status st = check_uploaded(c, "mknn_knn_gather_layout");
+    return set_error(MKNN_EINVAL, "mknn_knn_layout: nq out of range");
+  mknn_status st = check_uploaded(c, "mknn_knn_layout");
   if (st != MKNN_OK) return st;
   if (nq == 0) return MKNN_OK;
   if (!d_q || !d_idx || !d_dist)
-    return set_error(MKNN_EINVAL, "mknn_knn_gather_layout: NULL buffer");
+    return set_error(MKNN_EINVAL, "mknn_knn_layout: NULL buffer");
   if (c->dev_lazy.load() != 0)
-    return set_error(MKNN_EUNSUPPORTED, "mknn_knn_gather_layout: the cloud has pending deletions");
+    return set_error(MKNN_EUNSUPPORTED, "mknn_knn_layout: the cloud has pending deletions");
   hipStream_t s = (hipStream_t)stream;
-  // the ranks-only arena: the rank of every record, padding included
+  // the other layout of every record, padding included: 4 bytes of rank, and for the four
+  // arrays 12 more bytes of coordinates
+  const bool arrays = layout == MKNN_LAYOUT_ARRAYS;
   const int64_t nrec = c->ent_cap + kEntPad;
-  int32_t *rk = nullptr;
-  HIP_TRY(hipMallocAsync((void **)&rk, sizeof(int32_t) * (size_t)nrec, s),
-          "mknn_knn_gather_layout: rank array");
-  hipLaunchKernelGGL(record_ranks_kernel, dim3((uint32_t)((nrec + 255) / 256)), dim3(256), 0, s,
-                     (const float4 *)c->d_ent, nrec, rk);
+  const size_t per = arrays ? 16 : 4;
+  char *buf = nullptr;
+  HIP_TRY(hipMallocAsync((void **)&buf, per * (size_t)nrec, s), "mknn_knn_layout: arrays");
+  int32_t *rk = (int32_t *)buf;
+  float *sx = arrays ? (float *)(buf + 4 * (size_t)nrec) : nullptr;
+  float *sy = arrays ? (float *)(buf + 8 * (size_t)nrec) : nullptr;
+  float *sz = arrays ? (float *)(buf + 12 * (size_t)nrec) : nullptr;
+  hipLaunchKernelGGL(split_records_kernel, dim3((uint32_t)((nrec + 255) / 256)), dim3(256), 0,
+                     s, (const float4 *)c->d_ent, nrec, rk, sx, sy, sz);
   QueryArgs a;
   fill_cloud_args(c, &a);
   a.q = d_q;
@@ -1070,26 +1088,35 @@ mknn_status mknn_knn_gather_layout(const mknn_cloud *c, const float *d_q, int64_
   a.cnt_entries = a.cnt_lists = a.cnt_inserts = nullptr;
   a.rk = rk;
   a.pts = (const float4 *)c->d_pts;
+  a.sx = sx;
+  a.sy = sy;
+  a.sz = sz;
   void *scratch = nullptr;
   float4 *qs = nullptr;
   st = prepare_queries(c, d_q, nq, s, &qs, &scratch);
   if (st != MKNN_OK) {
-    (void)hipFreeAsync(rk, s);
+    (void)hipFreeAsync(buf, s);
     return st;
   }
   a.qs = qs;
   a.merge_min = config_for(16, true, c->dev_n).merge_min;
   hipError_t e = timing_mark(s, true);
   const int64_t waves = (nq + 3) / 4;
-  if (e == hipSuccess)
-    hipLaunchKernelGGL(knn_rows_gather_kernel<1>, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s,
-                       a, (int32_t)4);
+  const dim3 grid((uint32_t)((waves + 3) / 4));
+  if (e == hipSuccess) {
+    if (arrays)
+      hipLaunchKernelGGL(knn_rows_layout_kernel<kLayoutArrays>, grid, dim3(256), 0, s, a,
+                         (int32_t)4);
+    else
+      hipLaunchKernelGGL(knn_rows_layout_kernel<kLayoutRanks>, grid, dim3(256), 0, s, a,
+                         (int32_t)4);
+  }
   if (e == hipSuccess) e = hipGetLastError();
   if (e == hipSuccess) e = timing_mark(s, false);
   if (scratch) (void)hipFreeAsync(scratch, s);
-  (void)hipFreeAsync(rk, s);
+  (void)hipFreeAsync(buf, s);
   if (e != hipSuccess)
-    return set_error(MKNN_EHIP, std::string("mknn_knn_gather_layout: ") + hipGetErrorName(e));
+    return set_error(MKNN_EHIP, std::string("mknn_knn_layout: ") + hipGetErrorName(e));
   return MKNN_OK;
 }
 
@@ -1242,6 +1269,16 @@ mknn_status mknn_autotune(const mknn_cloud *c, const float *d_q, int64_t nq, int
   size_t bi = 0;
   for (size_t t = 1; t < cand.size(); ++t)
     if (ms[t] < ms[bi]) bi = t;
+  // The built-in configuration stays unless a candidate is faster by more than 1%, so that
+  // timing noise (a profiler attached, another process on the device) does not flip the
+  // choice between near-equal candidates.
+  const TuneConfig def = default_config(S);
+  for (size_t t = 0; t < cand.size(); ++t)
+    if (cand[t].family == def.family && cand[t].merge_min == def.merge_min &&
+        cand[t].per_wave == def.per_wave && ms[t] <= 1.01f * ms[bi]) {
+      bi = t;
+      break;
+    }
   int dev = 0;
   (void)hipGetDevice(&dev);
   {

@@ -291,9 +291,10 @@ def test_low_dimensional_clouds(env):
             assert _run(env, cl, P, Q, k, m) <= 2
 
 
-def test_ranks_only_layout_gives_the_same_rows():
-    """mknn_knn_gather_layout (the ranks-only layout kept for the layout measurement) walks
-    the same lists: its rows equal mknn_knn's bit for bit."""
+@pytest.mark.parametrize("layout", [1, 2])   # MKNN_LAYOUT_RANKS, MKNN_LAYOUT_ARRAYS
+def test_other_layouts_give_the_same_rows(layout):
+    """mknn_knn_layout (the ranks-only and four-array layouts kept for the layout
+    measurement) walks the same lists: its rows equal mknn_knn's bit for bit."""
     import ctypes
     import torch
     if not torch.cuda.is_available():
@@ -301,6 +302,7 @@ def test_ranks_only_layout_gives_the_same_rows():
     from paper_2605_02224_amd import _lib
     from paper_2605_02224_amd import workloads as W
     from paper_2605_02224_amd.api import Cloud
+    print(f"layout {layout}", flush=True)
     w = W.torus_paper_scale(n=100_000, nq=30_000, k=16)
     cl = Cloud.build(w.cloud.points, w.cloud.order).upload()
     q = torch.from_numpy(w.queries).cuda()
@@ -308,8 +310,8 @@ def test_ranks_only_layout_gives_the_same_rows():
     i2 = torch.empty_like(i1)
     d2 = torch.empty_like(d1)
     st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    _lib.check(_lib.lib().mknn_knn_gather_layout(cl.handle, ctypes.c_void_p(q.data_ptr()),
-                                                 q.shape[0], ctypes.c_void_p(i2.data_ptr()),
-                                                 ctypes.c_void_p(d2.data_ptr()), st))
+    _lib.check(_lib.lib().mknn_knn_layout(cl.handle, layout, ctypes.c_void_p(q.data_ptr()),
+                                          q.shape[0], ctypes.c_void_p(i2.data_ptr()),
+                                          ctypes.c_void_p(d2.data_ptr()), st))
     torch.cuda.synchronize()
     assert torch.equal(i1, i2) and torch.equal(d1, d2)
