@@ -315,3 +315,48 @@ def test_other_layouts_give_the_same_rows(layout):
                                           ctypes.c_void_p(d2.data_ptr()), st))
     torch.cuda.synchronize()
     assert torch.equal(i1, i2) and torch.equal(d1, d2)
+
+
+def test_layout_measurement_edges():
+    """mknn_knn_layout on a ragged batch (1,001 queries: not a whole number of wavefronts)
+    equals mknn_knn; an empty batch returns at once; a cloud with pending lazy deletions is
+    refused (the other layouts are built from the records alone) until they are applied."""
+    import ctypes
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_02224_amd import _lib
+    from paper_2605_02224_amd import workloads as W
+    from paper_2605_02224_amd.api import Cloud
+    w = W.sphere_small(n=10_000, nq=1_001, k=16)
+    cl = Cloud.build(w.cloud.points, w.cloud.order).upload()
+    q = torch.from_numpy(w.queries).cuda()
+    lib = _lib.lib()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def run(layout, nq):
+        i2 = torch.full((max(nq, 1), 16), -7, dtype=torch.int32, device="cuda")
+        d2 = torch.zeros((max(nq, 1), 16), dtype=torch.float32, device="cuda")
+        s = lib.mknn_knn_layout(cl.handle, layout, ctypes.c_void_p(q.data_ptr()), nq,
+                                ctypes.c_void_p(i2.data_ptr()), ctypes.c_void_p(d2.data_ptr()), st)
+        torch.cuda.synchronize()
+        return s, i2, d2
+
+    i1, d1 = cl.knn(q, 16)
+    torch.cuda.synchronize()
+    for layout in (1, 2):
+        print(f"layout {layout}: ragged batch", flush=True)
+        s, i2, d2 = run(layout, q.shape[0])
+        assert s == _lib.OK
+        assert torch.equal(i1, i2) and torch.equal(d1, d2)
+        s, i2, _ = run(layout, 0)
+        assert s == _lib.OK and bool((i2 == -7).all())
+    cl.delete_lazy([17, 4242])
+    for layout in (1, 2):
+        s, _, _ = run(layout, q.shape[0])
+        assert s == _lib.EUNSUPPORTED
+    cl.flush()
+    i1, d1 = cl.knn(q, 16)
+    torch.cuda.synchronize()
+    s, i2, d2 = run(2, q.shape[0])
+    assert s == _lib.OK and torch.equal(i1, i2) and torch.equal(d1, d2)
