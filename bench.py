@@ -946,7 +946,7 @@ def main() -> int:
         return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU: the query path has no "
-                                   "multi-GPU form in this build, so --gpus must be 1"}))
+                                   "multi-GPU form, so --gpus must be 1"}))
         return 2
 
     # the forms run in a child process started before this process touches the GPU; it
