@@ -33,7 +33,15 @@ def test_autotune_keeps_results(env, k, tmp_path):
     best, tried = A.autotune(cl, q, k)
     assert len(tried) >= 4 and best in tried
     assert all(t["ms"] > 0 for t in tried)
-    assert best["ms"] == min(t["ms"] for t in tried)
+    # the fastest candidate, or the built-in configuration (scheduled rows, merge threshold
+    # 8, 4 queries per wavefront) when it is within 1% of the fastest
+    fastest = min(t["ms"] for t in tried)
+    builtin = [t for t in tried if (t["family"], t["merge_min"], t["per_wave"]) == ("rows", 8, 4)]
+    assert len(builtin) == 1
+    if np.float32(builtin[0]["ms"]) <= np.float32(1.01) * np.float32(fastest):   # as the tuner
+        assert best == builtin[0]
+    else:
+        assert best["ms"] == fastest
     after = cl.knn(q, k)
     torch.cuda.synchronize()
     assert torch.equal(before[0], after[0]) and torch.equal(before[1], after[1])
