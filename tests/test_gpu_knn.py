@@ -200,6 +200,28 @@ def test_torus_1m_paper_scale_sampled(env):
             assert ex <= 2
 
 
+def test_torus_1m_wide_k_sampled(env):
+    """The k > 16 classes (two, three and four candidate slots per lane) on the headline
+    workload at full size (1M torus points, 1M volume queries), in the launch configuration
+    `bench.py --k K` times, checked on a seeded sample of rows.  One oracle pass for the 65
+    nearest serves the three k."""
+    torch, oracle, A = env
+    from paper_2605_02224_amd import workloads as W
+    w = W.torus_paper_scale()
+    P = w.cloud.by_rank
+    cl = A.Cloud.build(P).upload()
+    qd = torch.from_numpy(w.queries).cuda()
+    sel = np.random.default_rng(1).choice(w.queries.shape[0], 2000, replace=False)
+    ri, _, rD = oracle.knn_bruteforce(P, w.queries[sel], 65)
+    for k in (32, 48, 64):
+        print(f"k={k}", flush=True)
+        idx, dist = cl.knn(qd, k)
+        torch.cuda.synchronize()
+        ex = compare_rows(idx.cpu().numpy()[sel], dist.cpu().numpy()[sel], ri[:, :k],
+                          rD[:, :k], rD[:, k], P=P, Q=w.queries[sel])
+        assert ex <= 2
+
+
 def test_heightfield_2m_prefix_paper_scale_sampled(env):
     """Dynamic prefix queries at full size: 2M height-field points, 2M volume queries, each with
     its own prefix m (log-uniform in [n/1000, n]) and k in {1, 8, 32}, checked on a seeded
