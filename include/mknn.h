@@ -152,8 +152,9 @@ mknn_status mknn_knn(const mknn_cloud *c, const float *d_q, int64_t nq, int32_t 
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
  * arguments, rows and errors as mknn_knn, bit-identical results (the same kernels), but
  * the query sort's scratch is a fixed array of the library on each GPU
- * (64 Ki histogram bins + 20 bytes per query for at most 2^20 = 1,048,576 queries, about
- * 20.3 MiB per GPU, held until the process ends) instead of stream-ordered allocations:
+ * (256 Ki histogram bins and 256 block totals + 20 bytes per query for at most 2^20 =
+ * 1,048,576 queries, about 21.0 MiB per GPU, held until the process ends) instead of
+ * stream-ordered allocations:
  * the call makes no hipMalloc/hipFree and no allocating library call.  The array's device
  * address is looked up on the first call on each device.  Every call on one GPU shares that
  * GPU's array: calls whose work overlaps on one GPU (other streams, other threads) race on

@@ -204,8 +204,12 @@ __global__ __launch_bounds__(256) void knn_lane_kernel(QueryArgs a) {
 // their position in the cloud's bounding box (counting sort: histogram, scan, scatter).
 // Only locality matters here -- each query's answer does not depend on where it runs.
 // ---------------------------------------------------------------------------------------
-constexpr int kMortonBits = 16;
+constexpr int kMortonBits = 18;
 constexpr int kMortonBins = 1 << kMortonBits;
+// the histogram is scanned in blocks of kScanBlock bins, then over the blocks' totals
+constexpr int kScanBlock = 1024;
+constexpr int kScanBlocks = kMortonBins / kScanBlock;
+static_assert(kScanBlocks <= 1024, "one workgroup scans the block totals");
 constexpr int64_t kSortMinQueries = 8192;
 
 // The histogram's atomic hands every query its rank within its bin, so the scatter below
@@ -233,42 +237,44 @@ __global__ __launch_bounds__(256) void split_records_kernel(const float4 *ent, i
   }
 }
 
-// exclusive scan of kMortonBins counters by one workgroup of 1024 threads
-__global__ __launch_bounds__(1024) void scan_bins_kernel(uint32_t *hist) {
-  constexpr int per = kMortonBins / 1024;
+// Exclusive scan of n counters in place by one workgroup of 1024 threads (n <= 1024); the
+// total goes to *total when given.
+__device__ __forceinline__ void scan_1024(uint32_t *v, int64_t n, uint32_t *total) {
   __shared__ uint32_t part[1024];
   const int t = threadIdx.x;
-  uint32_t local[per];
-  uint32_t sum = 0;
-#pragma unroll
-  for (int i = 0; i < per; ++i) {
-    local[i] = hist[t * per + i];
-    sum += local[i];
-  }
-  part[t] = sum;
+  const uint32_t x = t < n ? v[t] : 0u;
+  part[t] = x;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t v = t >= off ? part[t - off] : 0u;
+    const uint32_t u = t >= off ? part[t - off] : 0u;
     __syncthreads();
-    part[t] += v;
+    part[t] += u;
     __syncthreads();
   }
-  uint32_t run = part[t] - sum;
-#pragma unroll
-  for (int i = 0; i < per; ++i) {
-    hist[t * per + i] = run;
-    run += local[i];
-  }
+  if (t < n) v[t] = part[t] - x;
+  if (total && t == 1023) *total = part[t];
 }
 
-// start: each bin's first position (the exclusive scan of the histogram)
+// exclusive scan of every block of kScanBlock bins in place; each block's total to sums
+__global__ __launch_bounds__(1024) void scan_bins_kernel(uint32_t *hist, uint32_t *sums) {
+  scan_1024(hist + (int64_t)blockIdx.x * kScanBlock, kScanBlock, sums + blockIdx.x);
+}
+
+// exclusive scan of the kScanBlocks block totals (one workgroup)
+__global__ __launch_bounds__(1024) void scan_sums_kernel(uint32_t *sums) {
+  scan_1024(sums, kScanBlocks, nullptr);
+}
+
+// a bin's first position: its offset in its scan block (start) plus the block's (sums)
 __global__ __launch_bounds__(256) void morton_scatter_kernel(const float *q, int64_t nq, BoxArgs b,
                                                              const uint32_t *start,
+                                                             const uint32_t *sums,
                                                              const uint32_t *rank, float4 *qs) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nq) return;
   float x = q[3 * i], y = q[3 * i + 1], z = q[3 * i + 2];
-  const uint32_t pos = start[morton30(x, y, z, b) >> (30 - kMortonBits)] + rank[i];
+  const uint32_t bin = morton30(x, y, z, b) >> (30 - kMortonBits);
+  const uint32_t pos = start[bin] + sums[bin / kScanBlock] + rank[i];
   qs[pos] = make_float4(x, y, z, __int_as_float((int32_t)i));
 }
 
@@ -708,7 +714,7 @@ static hipError_t dispatch_rows(const QueryArgs &a, int kmax, bool exact, int32_
 // Bytes of scratch the Morton bucketing of nq queries needs (0 below the sort threshold).
 static size_t sort_scratch_bytes(int64_t nq) {
   return nq < kSortMinQueries ? 0
-                              : sizeof(uint32_t) * kMortonBins +
+                              : sizeof(uint32_t) * (kMortonBins + kScanBlocks) +
                                     (sizeof(float4) + sizeof(uint32_t)) * (size_t)nq;
 }
 
@@ -726,7 +732,8 @@ static mknn_status prepare_queries(const mknn_cloud *c, const float *d_q, int64_
     HIP_TRY(hipMallocAsync(scratch, sort_scratch_bytes(nq), s), "query sort scratch");
     hist = (uint32_t *)*scratch;
   }
-  float4 *qs = (float4 *)(hist + kMortonBins);
+  uint32_t *sums = hist + kMortonBins;
+  float4 *qs = (float4 *)(sums + kScanBlocks);
   uint32_t *rank = (uint32_t *)(qs + nq);
   BoxArgs b = dev_box_of(c);
   const int threads = 256;
@@ -734,9 +741,10 @@ static mknn_status prepare_queries(const mknn_cloud *c, const float *d_q, int64_
   hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(kMortonBins / threads), dim3(threads), 0, s,
                      hist, (int64_t)kMortonBins, 0u);
   hipLaunchKernelGGL(morton_hist_kernel, dim3(blocks), dim3(threads), 0, s, d_q, nq, b, hist, rank);
-  hipLaunchKernelGGL(scan_bins_kernel, dim3(1), dim3(1024), 0, s, hist);
+  hipLaunchKernelGGL(scan_bins_kernel, dim3(kScanBlocks), dim3(1024), 0, s, hist, sums);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, sums);
   hipLaunchKernelGGL(morton_scatter_kernel, dim3(blocks), dim3(threads), 0, s, d_q, nq, b, hist,
-                     rank, qs);
+                     sums, rank, qs);
   HIP_TRY(hipGetLastError(), "query sort launch");
   *qs_out = qs;
   return MKNN_OK;
@@ -858,8 +866,8 @@ static mknn_status check_per_query(const int32_t *d_k, const int32_t *d_m, const
 // per device with that device current.
 // ---------------------------------------------------------------------------------------
 constexpr int64_t kStaticMaxQueries = (int64_t)1 << 20;
-constexpr size_t kStaticScratchBytes =
-    sizeof(uint32_t) * kMortonBins + (sizeof(float4) + sizeof(uint32_t)) * (size_t)kStaticMaxQueries;
+constexpr size_t kStaticScratchBytes = sizeof(uint32_t) * (kMortonBins + kScanBlocks) +
+                                       (sizeof(float4) + sizeof(uint32_t)) * (size_t)kStaticMaxQueries;
 static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 constexpr int kMaxDevices = 64;
@@ -1140,7 +1148,7 @@ mknn_status mknn_knn_static(const mknn_cloud *c, const float *d_q, int64_t nq, i
   void *buf = nullptr;
   st = static_scratch(&buf);
   if (st != MKNN_OK) return st;
-  static_assert(kStaticScratchBytes >= sizeof(uint32_t) * kMortonBins +
+  static_assert(kStaticScratchBytes >= sizeof(uint32_t) * (kMortonBins + kScanBlocks) +
                                           (sizeof(float4) + sizeof(uint32_t)) * (size_t)kStaticMaxQueries,
                 "scratch holds the sort of the largest batch");
   return run_query(c, d_q, nq, k, m, nullptr, nullptr, nullptr, k, d_idx, d_dist, nullptr,
