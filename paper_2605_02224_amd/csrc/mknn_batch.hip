@@ -52,8 +52,8 @@ namespace mknn {
 
 constexpr int kQueues = 8;
 constexpr int kClasses = 4;              // S = 1..4 slots per lane (k <= 16, 32, 48, 64)
-constexpr int kSegBits = 12;             // Morton bits per request in the batch sort
-constexpr int kSegBins = 1 << kSegBits;
+// Morton bits per request of the batch sort, chosen per plan (seg_bits_for)
+constexpr int kSegBitsMin = 12, kSegBitsMax = 16;
 
 // A queue lists its requests; request e of a queue owns the queue's tiles
 // [first, first of the next entry), each `tile[class]` sorted queries long.
@@ -84,6 +84,7 @@ __device__ __forceinline__ int32_t request_of(const int64_t *qoff, int32_t nreq,
   return lo;
 }
 
+template <int BITS>
 __global__ __launch_bounds__(256) void seg_hist_kernel(const BatchHeader *h, const QueryArgs *reqs,
                                                        const int64_t *qoff, const BoxArgs *boxes,
                                                        uint32_t *bins) {
@@ -93,19 +94,20 @@ __global__ __launch_bounds__(256) void seg_hist_kernel(const BatchHeader *h, con
        i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r = request_of(qoff, h->nreq, i);
     const float *q = reqs[r].q + 3 * (i - qoff[r]);
-    const uint32_t bin = morton30(q[0], q[1], q[2], boxes[r]) >> (30 - kSegBits);
-    atomicAdd(&bins[(int64_t)r * kSegBins + bin], 1u);
+    const uint32_t bin = morton30(q[0], q[1], q[2], boxes[r]) >> (30 - BITS);
+    atomicAdd(&bins[((int64_t)r << BITS) + bin], 1u);
   }
 }
 
 // one workgroup per request: exclusive scan of its bins, offset by the request's start
+template <int BITS>
 __global__ __launch_bounds__(1024) void seg_scan_kernel(const BatchHeader *h, const int64_t *qoff,
                                                         uint32_t *bins) {
   const int32_t r = blockIdx.x;
   if (!h->sorted || r >= h->nreq) return;
-  constexpr int per = kSegBins / 1024;
+  constexpr int per = (1 << BITS) / 1024;
   __shared__ uint32_t part[1024];
-  uint32_t *b = bins + (int64_t)r * kSegBins;
+  uint32_t *b = bins + ((int64_t)r << BITS);
   const int t = threadIdx.x;
   uint32_t local[per];
   uint32_t sum = 0;
@@ -130,6 +132,7 @@ __global__ __launch_bounds__(1024) void seg_scan_kernel(const BatchHeader *h, co
   }
 }
 
+template <int BITS>
 __global__ __launch_bounds__(256) void seg_scatter_kernel(const BatchHeader *h,
                                                           const QueryArgs *reqs,
                                                           const int64_t *qoff,
@@ -142,8 +145,8 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(const BatchHeader *h,
     const int32_t r = request_of(qoff, h->nreq, i);
     const int64_t local = i - qoff[r];
     const float *q = reqs[r].q + 3 * local;
-    const uint32_t bin = morton30(q[0], q[1], q[2], boxes[r]) >> (30 - kSegBits);
-    const uint32_t pos = atomicAdd(&bins[(int64_t)r * kSegBins + bin], 1u);
+    const uint32_t bin = morton30(q[0], q[1], q[2], boxes[r]) >> (30 - BITS);
+    const uint32_t pos = atomicAdd(&bins[((int64_t)r << BITS) + bin], 1u);
     qs[pos] = make_float4(q[0], q[1], q[2], __int_as_float((int32_t)local));
   }
 }
@@ -337,6 +340,7 @@ struct mknn_batch_plan {
   int device = -1;
   int64_t max_req = 0, max_q = 0;
   int32_t tile_q = 16;
+  int32_t seg_bits = kSegBitsMin;   // Morton bits per request of the batch sort
   bool sort = true, use_graph = true;
   // device: staging mirror | counters | bins | sorted queries
   char *d_base = nullptr;
@@ -427,16 +431,29 @@ static hipError_t plan_enqueue(mknn_batch_plan *p, hipStream_t s, bool lazy) {
   hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(64), dim3(256), 0, s, p->d_counters,
                      (int64_t)(kClasses * kQueues) + p->max_req, 0u);
   if (p->sort) {
-    const int64_t nb = p->max_req * kSegBins;
+    const int64_t nb = p->max_req << p->seg_bits;
     const uint32_t gb = (uint32_t)std::min<int64_t>(4096, (nb + 255) / 256);
     hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(gb), dim3(256), 0, s, p->d_bins, nb, 0u);
     const uint32_t gq = p->grid_stream;
-    hipLaunchKernelGGL(seg_hist_kernel, dim3(gq), dim3(256), 0, s, hdr, reqs, qoff, boxes,
-                       p->d_bins);
-    hipLaunchKernelGGL(seg_scan_kernel, dim3((uint32_t)p->max_req), dim3(1024), 0, s, hdr, qoff,
-                       p->d_bins);
-    hipLaunchKernelGGL(seg_scatter_kernel, dim3(gq), dim3(256), 0, s, hdr, reqs, qoff, boxes,
-                       p->d_bins, p->d_qs);
+    switch (p->seg_bits) {
+#define MKNN_SEG_CASE(B)                                                                        \
+  case B:                                                                                       \
+    hipLaunchKernelGGL(seg_hist_kernel<B>, dim3(gq), dim3(256), 0, s, hdr, reqs, qoff, boxes,   \
+                       p->d_bins);                                                              \
+    hipLaunchKernelGGL(seg_scan_kernel<B>, dim3((uint32_t)p->max_req), dim3(1024), 0, s, hdr,   \
+                       qoff, p->d_bins);                                                        \
+    hipLaunchKernelGGL(seg_scatter_kernel<B>, dim3(gq), dim3(256), 0, s, hdr, reqs, qoff,       \
+                       boxes, p->d_bins, p->d_qs);                                              \
+    break;
+      MKNN_SEG_CASE(12)
+      MKNN_SEG_CASE(13)
+      MKNN_SEG_CASE(14)
+      MKNN_SEG_CASE(15)
+      MKNN_SEG_CASE(16)
+#undef MKNN_SEG_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -645,6 +662,20 @@ const uint32_t *batch_plan_overflow(const mknn_batch_plan *p) {
 
 extern "C" {
 
+// Morton bits per request of the batch sort: about 4 queries per bin at the plan's average
+// request size, between kSegBitsMin and kSegBitsMax.  Queries within a bin run in arbitrary
+// order, so finer bins give a wavefront's four rows more alike work; the bins are cleared and
+// scanned at the plan's capacity on every run, which caps them for plans of small requests.
+// A plan of one request serves requests of any size up to its capacity, which then says
+// nothing of their typical size: it keeps the minimum.
+static int32_t seg_bits_for(int64_t max_queries, int64_t max_requests) {
+  if (max_requests < 2) return kSegBitsMin;
+  const int64_t avg = std::max<int64_t>(1, max_queries / max_requests);
+  int32_t b = kSegBitsMin;
+  while (b < kSegBitsMax && ((int64_t)4 << b) < avg) ++b;
+  return b;
+}
+
 mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, int32_t tile_queries,
                                    int32_t flags, mknn_batch_plan **out) {
   clear_error();
@@ -661,6 +692,7 @@ mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, in
   p->max_q = max_queries;
   p->tile_q = tile_queries;
   p->sort = !(flags & MKNN_BATCH_NO_SORT);
+  p->seg_bits = seg_bits_for(max_queries, max_requests);
   p->persistent = batch_persistent();
   p->use_graph = !(flags & MKNN_BATCH_NO_GRAPH);
   hipError_t e = hipGetDevice(&p->device);
@@ -682,7 +714,7 @@ mknn_status mknn_batch_plan_create(int64_t max_requests, int64_t max_queries, in
   // tile counters, then one overflow counter per request (pending deletions)
   o = align256(o + sizeof(uint32_t) * (kClasses * kQueues + (size_t)p->max_req));
   const size_t bins_at = o;
-  if (p->sort) o = align256(o + sizeof(uint32_t) * (size_t)p->max_req * kSegBins);
+  if (p->sort) o = align256(o + (sizeof(uint32_t) * (size_t)p->max_req << p->seg_bits));
   const size_t qs_at = o;
   if (p->sort) o = align256(o + sizeof(float4) * (size_t)p->max_q);
   if (e == hipSuccess) e = hipMalloc((void **)&p->d_base, o);
